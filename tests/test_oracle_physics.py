@@ -1,0 +1,173 @@
+"""Pins of the oracle's pointwise physics: flux definition, HLLD properties,
+GLM upwinding (no GPU)."""
+import numpy as np
+import pytest
+
+from oracle import physics as ph
+
+G = 5.0 / 3.0
+
+
+def random_states(rng, n, glm=True):
+    rho = rng.uniform(0.5, 2.0, n)
+    v = rng.uniform(-1.0, 1.0, (3, n))
+    p = rng.uniform(0.2, 2.0, n)
+    B = rng.uniform(-1.5, 1.5, (3, n))
+    psi = rng.uniform(-0.5, 0.5, n) if glm else None
+    return ph.prim_to_cons(rho, v, p, B, G, psi)
+
+
+def test_flux_matches_tensor_form():
+    # eq. mhd-flux written as a matrix: columns of [rho v; rho v v^T + pT I - B B^T;
+    # (E+pT) v - (v.B) B; B v^T - v B^T]
+    rng = np.random.default_rng(1)
+    U = random_states(rng, 20, glm=False)
+    for k in range(20):
+        u = U[:, k]
+        rho, v, E, Bv = u[0], u[1:4] / u[0], u[4], u[5:8]
+        p = (G - 1) * (E - 0.5 * rho * v @ v - 0.5 * Bv @ Bv)
+        pt = p + 0.5 * Bv @ Bv
+        T = np.zeros((8, 3))
+        T[0] = rho * v
+        T[1:4] = rho * np.outer(v, v) + pt * np.eye(3) - np.outer(Bv, Bv)
+        T[4] = (E + pt) * v - (v @ Bv) * Bv
+        T[5:8] = np.outer(Bv, v) - np.outer(v, Bv)
+        for a in range(3):
+            assert np.allclose(ph.flux(u[:, None], a, G)[:, 0], T[:, a], atol=1e-14, rtol=1e-13)
+            assert ph.flux(u[:, None], a, G)[5 + a, 0] == 0.0  # no normal-B flux
+
+
+@pytest.mark.parametrize("glm", [False, True])
+def test_numerical_flux_consistency(glm):
+    rng = np.random.default_rng(2)
+    U = random_states(rng, 200, glm=glm)
+    for a in range(3):
+        F, bnF = ph.numerical_flux(U, U, a, G, glm=glm, ch=2.5)
+        Fa = ph.flux(U, a, G, glm=glm, ch=2.5)
+        assert np.allclose(F, Fa, atol=1e-13, rtol=1e-12)
+        assert np.allclose(bnF, U[5 + a], rtol=1e-15)
+
+
+def test_hlld_upwind_branches():
+    rng = np.random.default_rng(3)
+    UL = random_states(rng, 100, glm=False)
+    UR = random_states(rng, 100, glm=False)
+    # super-fast flow to the right: F = F_L (with the common face normal field)
+    for sgn in (+1, -1):
+        A, Bs = UL.copy(), UR.copy()
+        for U in (A, Bs):
+            rho = U[0]
+            v = U[1:4] / rho
+            p = ph.pressure(U, G)
+            v[0] += sgn * 30.0
+            U[:] = ph.prim_to_cons(rho, v, p, U[5:8], G)
+        F, bnF = ph.numerical_flux(A, Bs, 0, G)
+        up = A if sgn > 0 else Bs
+        rho = up[0]
+        v = up[1:4] / rho
+        p = ph.pressure(up, G)
+        Bv = up[5:8].copy()
+        Bv[0] = bnF
+        Uup = ph.prim_to_cons(rho, v, p, Bv, G)
+        assert np.allclose(F, ph.flux(Uup, 0, G), rtol=1e-13, atol=1e-12)
+
+
+def test_hlld_stationary_contact():
+    # v = 0, equal p and B, density jump: no mass or energy flux, momentum = pT - Bn^2
+    n = 50
+    rng = np.random.default_rng(4)
+    Bv = rng.uniform(-1, 1, (3, n))
+    p = rng.uniform(0.5, 2, n)
+    z = np.zeros((3, n))
+    UL = ph.prim_to_cons(rng.uniform(0.5, 1, n), z, p, Bv, G)
+    UR = ph.prim_to_cons(rng.uniform(1, 3, n), z, p, Bv, G)
+    F, _ = ph.numerical_flux(UL, UR, 0, G)
+    assert np.abs(F[0]).max() < 1e-14
+    assert np.abs(F[4]).max() < 1e-13
+    assert np.allclose(F[1], p + 0.5 * (Bv ** 2).sum(0) - Bv[0] ** 2, rtol=1e-13)
+    assert np.abs(F[5:8]).max() < 1e-13
+
+
+def test_hlld_mirror_symmetry():
+    # reflecting x -> -x swaps L/R and flips normal velocity and normal field;
+    # the flux of even components flips sign, odd ones keep it
+    rng = np.random.default_rng(5)
+    UL = random_states(rng, 100, glm=False)
+    UR = random_states(rng, 100, glm=False)
+    M = np.ones(8)
+    M[1] = -1.0
+    M[5] = -1.0
+    F, _ = ph.numerical_flux(UL, UR, 0, G)
+    Fm, _ = ph.numerical_flux(UR * M[:, None], UL * M[:, None], 0, G)
+    assert np.allclose(Fm, -(F * M[:, None]), rtol=1e-12, atol=1e-12)
+
+
+def test_hlld_axis_permutation():
+    rng = np.random.default_rng(6)
+    UL = random_states(rng, 100, glm=True)
+    UR = random_states(rng, 100, glm=True)
+    perm = lambda U, s: np.concatenate([U[:1], np.roll(U[1:4], s, 0), U[4:5], np.roll(U[5:8], s, 0), U[8:]])
+    F0, _ = ph.numerical_flux(UL, UR, 0, G, glm=True, ch=3.0)
+    for a in (1, 2):
+        Fa, _ = ph.numerical_flux(perm(UL, a), perm(UR, a), a, G, glm=True, ch=3.0)
+        assert np.allclose(Fa, perm(F0, a), rtol=1e-13, atol=1e-13)
+
+
+def _hllc_toro(UL, UR):
+    """HLLC of Toro with the star energy (E/rho + (S*-u)(S* + p/(rho (S-u)))),
+    for B = 0; wave speeds +-max fast speed as in the HLLD estimate."""
+    def prim(U):
+        rho = U[0]
+        u = U[1] / rho
+        p = ph.pressure(U, G)
+        return rho, u, p, np.sqrt(G * p / rho)
+    rL, uL, pL, cL = prim(UL)
+    rR, uR, pR, cR = prim(UR)
+    c = np.maximum(cL, cR)
+    SL, SR = np.minimum(uL, uR) - c, np.maximum(uL, uR) + c
+    Ss = (pR - pL + rL * uL * (SL - uL) - rR * uR * (SR - uR)) / (rL * (SL - uL) - rR * (SR - uR))
+    def star(U, r, u, p, S):
+        f = r * (S - u) / (S - Ss)
+        return np.stack([f, f * Ss, f * U[2] / r, f * U[3] / r,
+                         f * (U[4] / r + (Ss - u) * (Ss + p / (r * (S - u)))), 0 * f, 0 * f, 0 * f])
+    FL, FR = ph.flux(UL, 0, G), ph.flux(UR, 0, G)
+    FsL = FL + SL * (star(UL, rL, uL, pL, SL) - UL)
+    FsR = FR + SR * (star(UR, rR, uR, pR, SR) - UR)
+    return np.where(SL > 0, FL, np.where(Ss > 0, FsL, np.where(SR > 0, FsR, FR)))
+
+
+def test_hlld_reduces_to_hllc_without_field():
+    rng = np.random.default_rng(7)
+    n = 300
+    mk = lambda: ph.prim_to_cons(rng.uniform(0.2, 3, n), rng.uniform(-2, 2, (3, n)),
+                                 rng.uniform(0.1, 3, n), np.zeros((3, n)), G)
+    UL, UR = mk(), mk()
+    F, _ = ph.numerical_flux(UL, UR, 0, G)
+    assert np.allclose(F, _hllc_toro(UL, UR), rtol=1e-12, atol=1e-12)
+
+
+def test_glm_upwind_exact_for_linear_waves():
+    # For the linear GLM subsystem, (Bn*, psi*) is the exact Riemann state:
+    # its characteristic variables psi +- ch Bn are taken from the upwind sides.
+    rng = np.random.default_rng(8)
+    ch = 1.7
+    UL = random_states(rng, 50)
+    UR = random_states(rng, 50)
+    F, _ = ph.numerical_flux(UL, UR, 0, G, glm=True, ch=ch)
+    psi_s, bn_s = F[5], F[8] / ch ** 2
+    # w+ = psi + ch Bn travels right (from L), w- = psi - ch Bn travels left (from R)
+    assert np.allclose(psi_s + ch * bn_s, UL[8] + ch * UL[5], rtol=1e-13)
+    assert np.allclose(psi_s - ch * bn_s, UR[8] - ch * UR[5], rtol=1e-13)
+
+
+def test_face_normal_field_alfven_weighting():
+    # eq. bxface-average-alfven: equal densities -> arithmetic mean; lies between the two
+    rng = np.random.default_rng(9)
+    bl, br = rng.normal(size=100), rng.normal(size=100)
+    rl, rr = rng.uniform(0.1, 5, 100), rng.uniform(0.1, 5, 100)
+    assert np.allclose(ph.face_normal_field(bl, rl, br, rl), 0.5 * (bl + br))
+    b = ph.face_normal_field(bl, rl, br, rr)
+    assert np.all((b - np.minimum(bl, br) > -1e-15) & (np.maximum(bl, br) - b > -1e-15))
+    # the lighter side (larger Alfven speed) gets the larger weight
+    b = ph.face_normal_field(np.array([1.0]), np.array([0.25]), np.array([0.0]), np.array([4.0]))
+    assert np.isclose(b[0], 0.8)

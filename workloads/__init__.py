@@ -1,0 +1,245 @@
+"""Seeded synthetic inputs for the DG MHD scheme.
+
+This module only draws random numbers and evaluates analytic *primitive*
+fields (rho, v, p, B, psi) at physical points.  It holds none of the scheme's
+arithmetic: no quadrature, no basis, no projection, no equation of state.
+Both the CPU oracle and the HIP library project these pointwise values onto
+their own modal bases with their own code.
+
+Every evaluator accepts numpy arrays or torch tensors (``xp`` is picked from
+the input), so the same seeded field can be evaluated on the host for the
+oracle and on the device for large runs.
+
+Recipes (one per workload):
+  smooth      rho = 1 + 0.1 S_rho, p = 1 + 0.1 S_p, v = 0.1 S_v,
+              B = curl(0.1 S_A) with S a normalised random Fourier sum over
+              integer wave vectors 1 <= |k| <= 4 (half space), amplitudes
+              U(-1,1), phases U(0, 2 pi); draw order rho, p, vx, vy, vz, A.
+  blast       rho = 1, p = 0.1, v = 0, B = (1, 0.5, 0.2)/sqrt(4 pi); 8 spheres
+              (centres U[0,1)^3, radii U[0.05, 0.1], periodic distance) with
+              p = 10 inside.
+  peaks       rho = 1 + 9 sum_i exp(-|x - c_i|^2 / (2 * 0.03^2)) over 16 peaks
+              (periodic distance), p = 1, v = (0.5, 0.25, 0.125),
+              B = (1, 0.5, 0.2)/sqrt(4 pi): an exact entropy wave.
+  alfven2d    circularly polarised Alfven wave of the paper's 2-D convergence
+              test (box sqrt(5), eps = 0.1, p = 0.1), exact at any time.
+  alfven3d    the 3-D variant along the cube diagonal (p = 100, eps = 0.02).
+"""
+import math
+
+import numpy as np
+
+try:  # torch is optional here
+    import torch
+except Exception:  # pragma: no cover
+    torch = None
+
+
+def _xp(x):
+    if torch is not None and isinstance(x, torch.Tensor):
+        return torch
+    return np
+
+
+def _const(xp, like, val):
+    if xp is np:
+        return np.full(like.shape, float(val))
+    return torch.full(like.shape, float(val), dtype=like.dtype, device=like.device)
+
+
+def wave_vectors(D, kmax=4):
+    """Integer k with 1 <= |k| <= kmax, first nonzero component > 0, lexicographic."""
+    out = []
+    rng = range(-kmax, kmax + 1)
+    if D == 2:
+        cand = [(a, b) for a in rng for b in rng]
+    else:
+        cand = [(a, b, c) for a in rng for b in rng for c in rng]
+    for k in cand:
+        n2 = sum(x * x for x in k)
+        if n2 == 0 or n2 > kmax * kmax:
+            continue
+        first = next(x for x in k if x != 0)
+        if first > 0:
+            out.append(k)
+    return np.array(out, dtype=np.float64)
+
+
+class FourierField:
+    """S(x) = sum_k a_k cos(2 pi k.x + phi_k) / sum_k |a_k| and its gradient."""
+
+    def __init__(self, rng, D):
+        self.k = wave_vectors(D)
+        nk = self.k.shape[0]
+        self.a = rng.uniform(-1.0, 1.0, nk)
+        self.phi = rng.uniform(0.0, 2.0 * math.pi, nk)
+        self.norm = np.abs(self.a).sum()
+
+    def _arg(self, x):
+        xp = _xp(x)
+        k = self.k if xp is np else torch.as_tensor(self.k, dtype=x.dtype, device=x.device)
+        phi = self.phi if xp is np else torch.as_tensor(self.phi, dtype=x.dtype, device=x.device)
+        return 2.0 * math.pi * (x @ k.T) + phi, xp
+
+    def value(self, x):
+        arg, xp = self._arg(x)
+        a = self.a if xp is np else torch.as_tensor(self.a, dtype=x.dtype, device=x.device)
+        return (xp.cos(arg) @ a) / self.norm
+
+    def grad(self, x):
+        arg, xp = self._arg(x)
+        a = self.a if xp is np else torch.as_tensor(self.a, dtype=x.dtype, device=x.device)
+        k = self.k if xp is np else torch.as_tensor(self.k, dtype=x.dtype, device=x.device)
+        s = -xp.sin(arg) * a  # [P, nk]
+        return (2.0 * math.pi / self.norm) * (s @ k)  # [P, D]
+
+
+class Smooth:
+    """Smooth periodic MHD state on [0,1]^D (divergence-free B)."""
+
+    def __init__(self, seed, D):
+        rng = np.random.default_rng(seed)
+        self.D = D
+        self.rho = FourierField(rng, D)
+        self.p = FourierField(rng, D)
+        self.v = [FourierField(rng, D) for _ in range(3)]
+        self.A = [FourierField(rng, D) for _ in range(1 if D == 2 else 3)]
+
+    def __call__(self, x):
+        """x[P, D] -> dict of primitive fields (each [P])."""
+        xp = _xp(x)
+        rho = 1.0 + 0.1 * self.rho.value(x)
+        p = 1.0 + 0.1 * self.p.value(x)
+        v = [0.1 * f.value(x) for f in self.v]
+        if self.D == 2:
+            gz = 0.1 * self.A[0].grad(x)
+            Bv = [gz[:, 1], -gz[:, 0], _const(xp, rho, 0.0)]
+        else:
+            g = [0.1 * f.grad(x) for f in self.A]  # g[c][:, j] = d A_c / d x_j
+            Bv = [g[2][:, 1] - g[1][:, 2], g[0][:, 2] - g[2][:, 0], g[1][:, 0] - g[0][:, 1]]
+        return dict(rho=rho, v=v, p=p, B=Bv, psi=_const(xp, rho, 0.0))
+
+
+def _periodic_d2(x, c):
+    xp = _xp(x)
+    d = x - c
+    d = d - xp.round(d)
+    return (d * d).sum(axis=-1) if xp is np else (d * d).sum(dim=-1)
+
+
+class Blast:
+    """Uniform magnetised medium with 8 over-pressured spheres in [0,1]^3."""
+
+    B0 = (1.0 / math.sqrt(4 * math.pi), 0.5 / math.sqrt(4 * math.pi), 0.2 / math.sqrt(4 * math.pi))
+
+    def __init__(self, seed, nsph=8, p_in=10.0, p_out=0.1):
+        rng = np.random.default_rng(seed)
+        self.c = rng.uniform(0.0, 1.0, (nsph, 3))
+        self.r = rng.uniform(0.05, 0.1, nsph)
+        self.p_in, self.p_out = p_in, p_out
+
+    def __call__(self, x):
+        xp = _xp(x)
+        inside = None
+        for c, r in zip(self.c, self.r):
+            cc = c if xp is np else torch.as_tensor(c, dtype=x.dtype, device=x.device)
+            m = _periodic_d2(x, cc) < r * r
+            inside = m if inside is None else (inside | m)
+        p = xp.where(inside, _const(xp, x[:, 0], self.p_in), _const(xp, x[:, 0], self.p_out))
+        z = _const(xp, x[:, 0], 0.0)
+        return dict(rho=_const(xp, x[:, 0], 1.0), v=[z, z, z], p=p,
+                    B=[_const(xp, x[:, 0], b) for b in self.B0], psi=z)
+
+
+class Peaks:
+    """16 Gaussian density peaks advected by a uniform flow (exact entropy wave)."""
+
+    B0 = Blast.B0
+    V0 = (0.5, 0.25, 0.125)
+
+    def __init__(self, seed, npk=16, width=0.03, contrast=10.0):
+        rng = np.random.default_rng(seed)
+        self.c = rng.uniform(0.0, 1.0, (npk, 3))
+        self.width, self.amp = width, contrast - 1.0
+
+    def __call__(self, x, t=0.0):
+        xp = _xp(x)
+        shift = np.array(self.V0) * t
+        rho = _const(xp, x[:, 0], 1.0)
+        for c in self.c:
+            cc = (c + shift) % 1.0
+            cc = cc if xp is np else torch.as_tensor(cc, dtype=x.dtype, device=x.device)
+            rho = rho + self.amp * xp.exp(-_periodic_d2(x, cc) / (2.0 * self.width ** 2))
+        return dict(rho=rho, v=[_const(xp, rho, u) for u in self.V0], p=_const(xp, rho, 1.0),
+                    B=[_const(xp, rho, b) for b in self.B0], psi=_const(xp, rho, 0.0))
+
+    def refine_flags(self, centers, radius):
+        """Cells (by centre) within `radius` (periodic) of any peak at t = 0."""
+        flag = np.zeros(centers.shape[0], dtype=bool)
+        for c in self.c:
+            flag |= _periodic_d2(centers, c) < radius * radius
+        return flag
+
+
+class Alfven2D:
+    """Travelling circularly polarised Alfven wave in [0, sqrt 5]^2 (exact)."""
+
+    def __init__(self, eps=0.1, p=0.1, m=2):
+        self.alpha = math.atan(1.0 / m)
+        self.L = 1.0 / math.sin(self.alpha)
+        self.eps, self.p0 = eps, p
+
+    def __call__(self, x, t=0.0):
+        xp = _xp(x)
+        ca, sa = math.cos(self.alpha), math.sin(self.alpha)
+        # the wave moves with -v_A = -1 along the parallel direction
+        xs, ys = x[:, 0] + t * ca, x[:, 1] + t * sa
+        phase = 2.0 * math.pi * (xs * ca + ys * sa)
+        e = self.eps
+        bpar, bperp, bz = 1.0, e * xp.sin(phase), e * xp.cos(phase)
+        vpar, vperp, vz = 0.0, e * xp.sin(phase), e * xp.cos(phase)
+        one = _const(xp, phase, 1.0)
+        Bx = bpar * ca * one - bperp * sa
+        By = bpar * sa * one + bperp * ca
+        vx = vpar * ca * one - vperp * sa
+        vy = vpar * sa * one + vperp * ca
+        return dict(rho=one, v=[vx, vy, vz], p=self.p0 * one, B=[Bx, By, bz], psi=0.0 * one)
+
+
+class Alfven3D:
+    """Circularly polarised Alfven wave along the diagonal of [0,1]^3 (exact)."""
+
+    def __init__(self, eps=0.02, p=100.0):
+        self.eps, self.p0 = eps, p
+        e1 = np.array([1.0, 1.0, 1.0]) / math.sqrt(3.0)
+        e2 = np.array([1.0, -1.0, 0.0]) / math.sqrt(2.0)
+        e3 = np.cross(e1, e2)
+        self.E = np.stack([e1, e2, e3])  # rows: primed axes in unprimed coordinates
+        self.lam = 1.0 / math.sqrt(3.0)
+
+    def __call__(self, x, t=0.0):
+        xp = _xp(x)
+        e = self.eps
+        E = self.E if xp is np else torch.as_tensor(self.E, dtype=x.dtype, device=x.device)
+        xpar = x @ E[0]
+        phase = 2.0 * math.pi / self.lam * (xpar - 2.0 * t)
+        one = _const(xp, phase, 1.0)
+        vprime = [one, e * xp.cos(phase), e * xp.sin(phase)]
+        bprime = [one, -e * xp.cos(phase), -e * xp.sin(phase)]
+        v = [sum(vprime[i] * float(self.E[i, c]) for i in range(3)) for c in range(3)]
+        B = [sum(bprime[i] * float(self.E[i, c]) for i in range(3)) for c in range(3)]
+        return dict(rho=one, v=v, p=self.p0 * one, B=B, psi=0.0 * one)
+
+
+def config_field(cfg, replicate=0):
+    """Seeded field of a benchmark configuration (seed = 1000 cfg + replicate)."""
+    seed = 1000 * cfg + replicate
+    if cfg == 0:
+        return Smooth(seed, 2)
+    if cfg == 1:
+        return Smooth(seed, 3)
+    if cfg in (2, 4):
+        return Blast(seed)
+    if cfg == 3:
+        return Peaks(seed)
+    raise ValueError(cfg)
