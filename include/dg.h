@@ -1,0 +1,171 @@
+/*
+ * dg.h -- C ABI of the gfx950 DG ideal-MHD library (libdgmhd.so).
+ *
+ * The library advances the modal discontinuous-Galerkin discretisation of
+ * ideal MHD of Guillet et al., "High-order magnetohydrodynamics for
+ * astrophysics with an adaptive mesh refinement discontinuous Galerkin
+ * scheme" (MNRAS 2019):
+ *   - state: per-cell modal weights w_l^K (Sec. 3.1, eq. u-exp) on the
+ *     Legendre basis (Sec. 3.2) or, for the magnetic field under the Powell
+ *     scheme, the locally divergence-free basis (Sec. 3.3, App. A);
+ *   - right-hand side: the weak form eq. wdot with (d+1)-point Gauss-Legendre
+ *     quadrature (Sec. 3.5), HLLD face fluxes with the Alfven-weighted face
+ *     normal field (Sec. 4.1.2, eq. bxface-average-alfven), Powell face terms
+ *     (Sec. 4.1.3, eq. powell-src-face, eq. powellq-average) or GLM cleaning
+ *     (Sec. 4.1.5);
+ *   - time step: eq. cfl, the Powell cap eq. powell_dt, c_h and c_p of
+ *     Sec. 4.1.5; SSP-RK3 stages (Sec. 3.6);
+ *   - limiters after every stage: TVB characteristic slope limiter
+ *     (Sec. 4.2.1-4.2.2, eq. tvb-limiter), LDF slope fix (Sec. 4.2.4) and the
+ *     positivity limiter (Sec. 4.3, eq. wtilde, eq. tau_rho, eq. tau_press).
+ *
+ * Conventions shared with every caller:
+ *   Variables v = (rho, m1, m2, m3, E, B1, B2, B3, psi); Heaviside-Lorentz
+ *   units; ideal gas with adiabatic index gamma.
+ *   Legendre modes: l_k normalised by l_k(1) = 1 (mode 0 = cell mean,
+ *   mass M = prod 2/(2k+1)); modes of total degree <= d ordered by total
+ *   degree, then k1 descending, then k2 descending.  Mode index v*n(d) + l.
+ *   Powell: the 5 hydro variables (and B3 in 2-D) on the Legendre basis,
+ *   then N_div LDF weights generated as in App. A: curls of the Legendre
+ *   products of degree <= d+1 placed in the x, then y, then z component,
+ *   stably sorted by degree, Gram-Schmidt orthogonalised, not normalised.
+ *   State array: [nmodes][ld], cells fastest, ld a multiple of 64 (see
+ *   dg_layout); FP64 if precision == DG_FP64, FP32 otherwise.
+ *   Uniform grids: cell index i + n0 (j + n1 k); octree meshes: the caller's
+ *   leaf order.
+ *
+ * Ownership: the caller owns every state / output array (device memory) and
+ * the stream.  The handle owns its tables, workspaces and face lists and
+ * frees them in dg_destroy.
+ *
+ * Errors: every call returns DG_OK or a negative code.  DG_EINVAL and
+ * DG_EUNSUPPORTED are detected before any device work and leave all arrays
+ * untouched.  dg_last_error(h) returns a message for the last failure.  No
+ * C++ exception crosses this interface.
+ *
+ * Concurrency: all device work is ordered on the stream given to dg_init.
+ * Calls that return host values (dg_dt, dg_limit with stats, dg_step with a
+ * time pointer, dg_proj_points) synchronise that stream.  A handle must not
+ * be used from two threads at once.
+ */
+#ifndef DGMHD_DG_H
+#define DGMHD_DG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dg_handle_s* dg_handle;
+
+enum {
+  DG_OK = 0,
+  DG_EINVAL = -1,        /* bad argument (null pointer, size, unknown enum) */
+  DG_EUNSUPPORTED = -2,  /* valid but not built (e.g. degree > 3) */
+  DG_EHIP = -3,          /* a HIP runtime call failed */
+  DG_ENOMEM = -4,        /* device allocation failed */
+  DG_ENONFINITE = -5,    /* a non-finite value appeared in the state */
+  DG_ECH = -6            /* GLM with fixed c_h: c_h < 2 * max signal speed seen */
+};
+enum { DG_GLM = 0, DG_POWELL = 1 };
+enum { DG_FP64 = 0, DG_FP32 = 1 };
+enum { DG_LIM_TVB = 1, DG_LIM_CHAR = 2, DG_LIM_POS = 4, DG_LIM_LEARNED = 8 };
+enum { DG_MESH_UNIFORM = 0, DG_MESH_OCTREE = 1 };
+
+/* Scheme parameters (Sec. 3.6, 4.1, 4.2, 4.3; defaults of the paper in
+ * brackets).  rk_stages must be 3 (SSP-RK3).  cfl_glm is C' of Sec. 4.1.5
+ * (0 selects min(2 cfl, 0.9)); glm_cr is c_r = c_p^2 / c_h [0.18];
+ * glm_ch_fixed > 0 fixes c_h (required on octree meshes).  tvb_Mtilde [5],
+ * tvb_beta [2], tvb_eps [1e-8]; eps_rho = eps_p [1e-12]; powell_eta [0.2].
+ * mlp_lo / mlp_hi bound the band of learned-indicator outputs that falls
+ * back to the plain TVB detector. */
+typedef struct {
+  int32_t dim, degree, divb, precision, rk_stages, limiter;
+  double gamma, cfl, cfl_glm, glm_cr, glm_ch_fixed;
+  double tvb_Mtilde, tvb_beta, tvb_eps, eps_rho, eps_p, powell_eta;
+  double mlp_lo, mlp_hi;
+} dg_params;
+
+/* Mesh on the periodic box [0, box]^dim.  kind == DG_MESH_UNIFORM: n[0..dim)
+ * cells per axis, cubic cells (box[a]/n[a] equal).  kind == DG_MESH_OCTREE:
+ * n[] is the level-0 grid, and leaf c has refinement level level[c] >= 0 and
+ * integer coordinates ijk[3c..3c+2] on the grid of that level (host arrays,
+ * copied by dg_init).  Leaves must tile the box and be 2:1 balanced across
+ * faces. */
+typedef struct {
+  int32_t kind;
+  int32_t n[3];
+  double box[3];
+  int64_t nleaves;
+  const int8_t* level; /* [host] */
+  const int32_t* ijk;  /* [host] */
+} dg_mesh;
+
+/* Limiter statistics of one dg_limit call / one dg_step (summed over stages). */
+typedef struct {
+  int64_t n_tvb_triggered, n_mlp_flagged, n_fallback, n_pos_scaled, n_floor;
+  double injected_mass, injected_energy, max_signal, ch;
+} dg_limit_stats;
+
+/* Create a handle: builds the tables (Gauss-Legendre rules, Legendre and LDF
+ * bases, face tables), the face lists and the workspaces on the current HIP
+ * device.  hip_stream: a hipStream_t (NULL = default stream). */
+int dg_init(const dg_params* p /*[host]*/, const dg_mesh* m /*[host]*/, void* hip_stream,
+            dg_handle* out /*[host]*/);
+
+/* Sizes of the state array: nmodes rows of ld elements, ncells of them used. */
+int dg_layout(dg_handle h, int64_t* nmodes, int64_t* ncells, int64_t* ld);
+
+/* Reference coordinates of the (d+3)^dim projection points used by
+ * dg_project (Sec. 5.2.1 rule), point-major: xi[p*dim + a]; synchronous. */
+int dg_proj_points(dg_handle h, double* xi /*[host] or NULL*/, int64_t* npts /*[host]*/);
+
+/* L2 projection of pointwise primitive values onto the modal state
+ * (w_l = M_l^-1 sum_q w_q u(x_q) . phi_l(xi_q)).  prim: device FP64 array
+ * [9][ncell][npts] holding (rho, v1, v2, v3, p, B1, B2, B3, psi) at the
+ * points of dg_proj_points for cells cell0 .. cell0+ncell-1; writes those
+ * columns of w.  Async. */
+int dg_project(dg_handle h, const double* prim, int64_t cell0, int64_t ncell, void* w);
+
+/* Time step of the state w (eq. cfl; Powell cap eq. powell_dt; GLM c_h and
+ * kappa = c_h^2 / c_p^2 of Sec. 4.1.5).  Synchronous; outputs on the host. */
+int dg_dt(dg_handle h, const void* w, double* dt, double* ch, double* kappa);
+
+/* dwdt = M^-1 R(w): the semi-discrete right-hand side of eq. wdot including
+ * the Powell face terms or the GLM flux and damping source (c_h, kappa
+ * given).  w and dwdt: [nmodes][ld] device arrays (distinct).  Async. */
+int dg_rhs(dg_handle h, const void* w, void* dwdt, double ch, double kappa);
+
+/* Apply the limiters selected in dg_params.limiter to w in place (slope
+ * limiter first, then positivity).  stats == NULL: async; otherwise the
+ * stream is synchronised and stats filled. */
+int dg_limit(dg_handle h, void* w, dg_limit_stats* stats /*[host] or NULL*/);
+
+/* Advance w by nsteps SSP-RK3 steps (Sec. 3.6); dt, c_h and kappa are
+ * computed on the device from the state at the start of each step and the
+ * selected limiters run after every stage (Sec. 4.3: before any state is
+ * evaluated at quadrature points again).  Limiting the initial state is the
+ * caller's dg_limit call.  t (host, may be NULL) is advanced by the sum of
+ * the steps' dt; a non-NULL t synchronises. */
+int dg_step(dg_handle h, void* w, int32_t nsteps, double* t /*[host] in/out*/);
+
+/* Install the learned troubled-cell indicator: w_bf16 device array of BF16
+ * weights (layout in dg_mlp_layout), b host FP32 biases. */
+int dg_set_mlp(dg_handle h, const void* w_bf16, const float* b /*[host]*/, int32_t in_dim);
+
+/* Measurement hook: launch one kernel of the step `reps` times back to back
+ * on the handle's stream between two HIP events and return the mean time per
+ * launch in ms.  which: 0 face flux kernel, 1 cell (volume + surface + stage
+ * update) kernel, 2 time-step reduction, 3 limiter sequence.  Reads w; writes
+ * only the handle's workspaces.  Synchronous. */
+int dg_time_kernel(dg_handle h, const void* w, int32_t which, int32_t reps, double* ms /*[host]*/);
+
+const char* dg_last_error(dg_handle h);
+void dg_destroy(dg_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGMHD_DG_H */

@@ -105,7 +105,8 @@ def hlld(WL, WR, bx, gamma):
             bz * u - w * bx,
         ])
         gp = g * p
-        cf2 = 0.5 * ((gp + bsq) / rho + np.sqrt(((gp + bsq) / rho) ** 2 - 4.0 * gp * bx * bx / (rho * rho)))
+        disc = np.maximum(((gp + bsq) / rho) ** 2 - 4.0 * gp * bx * bx / (rho * rho), 0.0)
+        cf2 = 0.5 * ((gp + bsq) / rho + np.sqrt(disc))
         return U, F, E, pt, np.sqrt(cf2)
 
     UL, FL, EL, ptL, cfL = cons_and_flux(WL)

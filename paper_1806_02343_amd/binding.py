@@ -1,0 +1,209 @@
+"""ctypes binding of the C ABI in include/dg.h (argument marshalling only)."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdgmhd.so")
+
+DG_OK, DG_EINVAL, DG_EUNSUPPORTED, DG_EHIP, DG_ENOMEM, DG_ENONFINITE, DG_ECH = 0, -1, -2, -3, -4, -5, -6
+DG_GLM, DG_POWELL = 0, 1
+DG_FP64, DG_FP32 = 0, 1
+DG_LIM_TVB, DG_LIM_CHAR, DG_LIM_POS, DG_LIM_LEARNED = 1, 2, 4, 8
+DG_MESH_UNIFORM, DG_MESH_OCTREE = 0, 1
+
+EXPORTS = ["dg_init", "dg_layout", "dg_proj_points", "dg_project", "dg_dt", "dg_rhs", "dg_limit", "dg_step",
+           "dg_set_mlp", "dg_time_kernel", "dg_last_error", "dg_destroy"]
+
+
+class dg_params(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("degree", ctypes.c_int32), ("divb", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("rk_stages", ctypes.c_int32), ("limiter", ctypes.c_int32),
+                ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("cfl_glm", ctypes.c_double),
+                ("glm_cr", ctypes.c_double), ("glm_ch_fixed", ctypes.c_double),
+                ("tvb_Mtilde", ctypes.c_double), ("tvb_beta", ctypes.c_double), ("tvb_eps", ctypes.c_double),
+                ("eps_rho", ctypes.c_double), ("eps_p", ctypes.c_double), ("powell_eta", ctypes.c_double),
+                ("mlp_lo", ctypes.c_double), ("mlp_hi", ctypes.c_double)]
+
+
+class dg_mesh(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("box", ctypes.c_double * 3),
+                ("nleaves", ctypes.c_int64), ("level", ctypes.POINTER(ctypes.c_int8)),
+                ("ijk", ctypes.POINTER(ctypes.c_int32))]
+
+
+class dg_limit_stats(ctypes.Structure):
+    _fields_ = [("n_tvb_triggered", ctypes.c_int64), ("n_mlp_flagged", ctypes.c_int64),
+                ("n_fallback", ctypes.c_int64), ("n_pos_scaled", ctypes.c_int64), ("n_floor", ctypes.c_int64),
+                ("injected_mass", ctypes.c_double), ("injected_energy", ctypes.c_double),
+                ("max_signal", ctypes.c_double), ("ch", ctypes.c_double)]
+
+
+class DGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"dg error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libdgmhd.so and declare its signatures.  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libdgmhd.so not built ({path}); run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    P, I64, I32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    lib.dg_init.argtypes = [ctypes.POINTER(dg_params), ctypes.POINTER(dg_mesh), P, ctypes.POINTER(P)]
+    lib.dg_layout.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64)]
+    lib.dg_proj_points.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(I64)]
+    lib.dg_project.argtypes = [P, P, I64, I64, P]
+    lib.dg_dt.argtypes = [P, P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)]
+    lib.dg_rhs.argtypes = [P, P, P, D, D]
+    lib.dg_limit.argtypes = [P, P, ctypes.POINTER(dg_limit_stats)]
+    lib.dg_step.argtypes = [P, P, I32, ctypes.POINTER(D)]
+    lib.dg_set_mlp.argtypes = [P, P, ctypes.POINTER(ctypes.c_float), I32]
+    lib.dg_time_kernel.argtypes = [P, P, I32, I32, ctypes.POINTER(D)]
+    lib.dg_last_error.argtypes = [P]
+    lib.dg_last_error.restype = ctypes.c_char_p
+    lib.dg_destroy.argtypes = [P]
+    lib.dg_destroy.restype = None
+    for name in EXPORTS:
+        if name not in ("dg_last_error", "dg_destroy"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class DG:
+    """One handle of the library on the current HIP device.
+
+    Arguments mirror dg_params / dg_mesh; state tensors are [nmodes][ld]
+    torch tensors on the device (float64 or float32)."""
+
+    def __init__(self, dim, degree, n, box=1.0, divb=DG_GLM, precision=DG_FP64, limiter=0, gamma=5.0 / 3.0,
+                 cfl=0.3, cfl_glm=0.0, glm_cr=0.18, glm_ch_fixed=0.0, tvb_Mtilde=5.0, tvb_beta=2.0, tvb_eps=1e-8,
+                 eps_rho=1e-12, eps_p=1e-12, powell_eta=0.2, mlp_lo=0.0, mlp_hi=0.0, stream=None):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self.dim, self.degree, self.divb, self.precision = dim, degree, divb, precision
+        p = dg_params(dim, degree, divb, precision, 3, limiter, gamma, cfl, cfl_glm, glm_cr, glm_ch_fixed,
+                      tvb_Mtilde, tvb_beta, tvb_eps, eps_rho, eps_p, powell_eta, mlp_lo, mlp_hi)
+        nn = list(n) if hasattr(n, "__len__") else [n] * dim
+        bb = list(box) if hasattr(box, "__len__") else [box] * dim
+        nn += [1] * (3 - len(nn))
+        bb += [1.0] * (3 - len(bb))
+        m = dg_mesh(DG_MESH_UNIFORM, (ctypes.c_int32 * 3)(*nn), (ctypes.c_double * 3)(*bb), 0, None, None)
+        self.n, self.box = nn[:dim], bb[:dim]
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = self.lib.dg_init(ctypes.byref(p), ctypes.byref(m), ctypes.c_void_p(stream), ctypes.byref(h))
+        if rc != DG_OK:
+            raise DGError(rc, self.lib.dg_last_error(None).decode())
+        self.h = h
+        nm, nc, ld = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self._check(self.lib.dg_layout(h, ctypes.byref(nm), ctypes.byref(nc), ctypes.byref(ld)))
+        self.nmodes, self.ncells, self.ld = nm.value, nc.value, ld.value
+        self.dtype = torch.float64 if precision == DG_FP64 else torch.float32
+
+    def _check(self, rc):
+        if rc != DG_OK:
+            raise DGError(rc, self.lib.dg_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------
+    def empty_state(self):
+        return self.torch.zeros((self.nmodes, self.ld), dtype=self.dtype, device="cuda")
+
+    def proj_points(self):
+        import numpy as np
+        npts = ctypes.c_int64()
+        self._check(self.lib.dg_proj_points(self.h, None, ctypes.byref(npts)))
+        xi = np.zeros(npts.value * self.dim)
+        self._check(self.lib.dg_proj_points(self.h, xi.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            ctypes.byref(npts)))
+        return xi.reshape(npts.value, self.dim)
+
+    def project(self, prim, cell0, ncell, w):
+        """prim: device float64 tensor [9][ncell][npts] of primitive values."""
+        assert prim.dtype == self.torch.float64 and prim.is_contiguous()
+        self._check(self.lib.dg_project(self.h, _ptr(prim), cell0, ncell, _ptr(w)))
+
+    def dt(self, w):
+        dt, ch, k = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._check(self.lib.dg_dt(self.h, _ptr(w), ctypes.byref(dt), ctypes.byref(ch), ctypes.byref(k)))
+        return dt.value, ch.value, k.value
+
+    def rhs(self, w, dwdt, ch, kappa):
+        self._check(self.lib.dg_rhs(self.h, _ptr(w), _ptr(dwdt), ch, kappa))
+
+    def limit(self, w, stats=False):
+        if stats:
+            s = dg_limit_stats()
+            self._check(self.lib.dg_limit(self.h, _ptr(w), ctypes.byref(s)))
+            return {k: getattr(s, k) for k, _ in dg_limit_stats._fields_}
+        self._check(self.lib.dg_limit(self.h, _ptr(w), None))
+        return None
+
+    def step(self, w, nsteps=1, t=0.0):
+        tt = ctypes.c_double(t)
+        self._check(self.lib.dg_step(self.h, _ptr(w), nsteps, ctypes.byref(tt)))
+        return tt.value
+
+    def time_kernel(self, w, which, reps=10):
+        """Mean ms per launch of one kernel of the step (0 face, 1 cell, 2 dt, 3 limiter)."""
+        ms = ctypes.c_double()
+        self._check(self.lib.dg_time_kernel(self.h, _ptr(w), which, reps, ctypes.byref(ms)))
+        return ms.value
+
+    def step_async(self, w, nsteps=1):
+        self._check(self.lib.dg_step(self.h, _ptr(w), nsteps, None))
+
+    def cell_centers(self, c0, nc):
+        """Centres of uniform-grid cells c0 .. c0+nc-1 (index i + n0 (j + n1 k))."""
+        torch = self.torch
+        idx = torch.arange(c0, c0 + nc, device="cuda", dtype=torch.int64)
+        h = self.box[0] / self.n[0]
+        cols, stride = [], 1
+        for a in range(self.dim):
+            cols.append(((idx // stride) % self.n[a]).to(torch.float64) * h + 0.5 * h)
+            stride *= self.n[a]
+        return torch.stack(cols, dim=1), h
+
+    def project_field(self, field, w, chunk=1 << 16):
+        """Evaluate a pointwise primitive field (callable x[P, D] -> dict, see
+        workloads) at the library's projection points and project it into w."""
+        torch = self.torch
+        xi = torch.as_tensor(self.proj_points(), dtype=torch.float64, device="cuda")
+        npts = xi.shape[0]
+        for c0 in range(0, self.ncells, chunk):
+            nc = min(chunk, self.ncells - c0)
+            ctr, h = self.cell_centers(c0, nc)
+            x = (ctr[:, None, :] + 0.5 * h * xi[None, :, :]).reshape(-1, self.dim)
+            pr = field(x)
+            comps = [pr["rho"], pr["v"][0], pr["v"][1], pr["v"][2], pr["p"], pr["B"][0], pr["B"][1], pr["B"][2],
+                     pr["psi"]]
+            comps = [c if isinstance(c, torch.Tensor) else torch.full_like(x[:, 0], float(c)) for c in comps]
+            prim = torch.stack([c.to(torch.float64) for c in comps]).reshape(9, nc, npts).contiguous()
+            self.project(prim, c0, nc, w)
+            del prim, x
+        return w

@@ -1,0 +1,290 @@
+// C ABI of the DG MHD library: handle management, argument checking and the
+// per-step launch sequence (time-step reduction, three SSP-RK3 stages, each
+// face kernel -> cell kernel -> limiters), all ordered on one HIP stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/dg.h"
+#include "dg_kernels.h"
+#include "dg_tables.h"
+
+using namespace dgmhd;
+
+struct dg_handle_s {
+  dg_params p{};
+  Grid g{};
+  SchemeParams sp{};
+  Tables tabs;
+  Launcher* L = nullptr;
+  hipStream_t stream = nullptr;
+  void* ff = nullptr;     // face fluxes
+  void* jp = nullptr;     // Powell normal-field jumps
+  void* S1 = nullptr;     // stage state
+  void* jsum = nullptr;   // Powell per-face jump integrals
+  void* lscr = nullptr;   // limiter scratch
+  Scal* sc = nullptr;     // device scalars
+  double hmin = 0.0;
+  size_t elem = 8;
+  std::string err;
+};
+
+namespace {
+
+std::string g_err;  // message for failures before a handle exists
+
+int fail(dg_handle h, int code, const std::string& msg) {
+  if (h) h->err = msg; else g_err = msg;
+  return code;
+}
+
+int check_hip(dg_handle h, hipError_t e, const char* what) {
+  if (e == hipSuccess) return DG_OK;
+  return fail(h, DG_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int check_launch(dg_handle h, const char* what) { return check_hip(h, hipGetLastError(), what); }
+
+int valid_state(dg_handle h, const void* w) {
+  if (!h) return DG_EINVAL;
+  if (!w) return fail(h, DG_EINVAL, "null state pointer");
+  return DG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dg_init(const dg_params* p, const dg_mesh* m, void* hip_stream, dg_handle* out) {
+  if (!p || !m || !out) return fail(nullptr, DG_EINVAL, "null argument");
+  *out = nullptr;
+  if (p->dim != 2 && p->dim != 3) return fail(nullptr, DG_EINVAL, "dim must be 2 or 3");
+  if (p->degree < 1 || p->degree > 3) return fail(nullptr, DG_EUNSUPPORTED, "degree must be 1..3");
+  if (p->divb != DG_GLM && p->divb != DG_POWELL) return fail(nullptr, DG_EINVAL, "unknown divb");
+  if (p->divb == DG_POWELL && p->dim != 3) return fail(nullptr, DG_EUNSUPPORTED, "Powell/LDF is built for 3-D");
+  if (p->precision != DG_FP64 && p->precision != DG_FP32) return fail(nullptr, DG_EINVAL, "unknown precision");
+  if (p->rk_stages != 3) return fail(nullptr, DG_EUNSUPPORTED, "only SSP-RK3 (rk_stages = 3)");
+  if (!(p->gamma > 1.0) || !(p->cfl > 0.0) || !(p->cfl < 1.0)) return fail(nullptr, DG_EINVAL, "gamma/cfl");
+  if (m->kind != DG_MESH_UNIFORM) return fail(nullptr, DG_EUNSUPPORTED, "octree meshes not built yet");
+  for (int a = 0; a < p->dim; ++a)
+    if (m->n[a] < 1 || !(m->box[a] > 0.0)) return fail(nullptr, DG_EINVAL, "mesh size");
+  for (int a = 1; a < p->dim; ++a)
+    if (std::fabs(m->box[a] / m->n[a] - m->box[0] / m->n[0]) > 1e-12 * m->box[0] / m->n[0])
+      return fail(nullptr, DG_EINVAL, "cells must be cubic");
+
+  dg_handle h = new (std::nothrow) dg_handle_s();
+  if (!h) return fail(nullptr, DG_ENOMEM, "host allocation");
+  h->p = *p;
+  h->stream = (hipStream_t)hip_stream;
+  h->elem = p->precision == DG_FP64 ? 8 : 4;
+  Grid& g = h->g;
+  g.n0 = m->n[0];
+  g.n1 = m->n[1];
+  g.n2 = p->dim == 3 ? m->n[2] : 1;
+  g.C = (int64_t)g.n0 * g.n1 * g.n2;
+  g.ld = (g.C + 63) / 64 * 64;
+  g.h = m->box[0] / m->n[0];
+  h->hmin = g.h;
+  SchemeParams& sp = h->sp;
+  sp.gamma = p->gamma;
+  sp.cfl = p->cfl;
+  sp.cfl_glm = p->cfl_glm > 0.0 ? p->cfl_glm : std::fmin(2.0 * p->cfl, 0.9);
+  sp.glm_cr = p->glm_cr > 0.0 ? p->glm_cr : 0.18;
+  sp.glm_ch_fixed = p->glm_ch_fixed;
+  sp.powell_eta = p->powell_eta > 0.0 ? p->powell_eta : 0.2;
+  sp.tvb_Mtilde = p->tvb_Mtilde;
+  sp.tvb_beta = p->tvb_beta > 0.0 ? p->tvb_beta : 2.0;
+  sp.tvb_eps = p->tvb_eps > 0.0 ? p->tvb_eps : 1e-8;
+  sp.eps_rho = p->eps_rho > 0.0 ? p->eps_rho : 1e-12;
+  sp.eps_p = p->eps_p > 0.0 ? p->eps_p : 1e-12;
+  sp.limiter = p->limiter;
+
+  std::string err;
+  if (!build_tables(p->dim, p->degree, p->divb, h->tabs, err)) { int r = fail(nullptr, DG_EINVAL, err); delete h; return r; }
+  h->L = make_launcher(p->precision, p->dim, p->degree, p->divb);
+  if (!h->L) { delete h; return fail(nullptr, DG_EUNSUPPORTED, "configuration not built"); }
+  auto cleanup = [&](int code, const std::string& msg) { g_err = msg; dg_destroy(h); return code; };
+  hipError_t e = h->L->upload_tables(h->tabs);
+  if (e != hipSuccess) return cleanup(DG_EHIP, std::string("table upload: ") + hipGetErrorString(e));
+  const size_t nm = (size_t)h->L->nmodes();
+  if ((e = hipMalloc(&h->ff, h->L->face_buffer_elems(g) * h->elem)) != hipSuccess) return cleanup(DG_ENOMEM, "face buffer");
+  if (size_t nj = h->L->jump_buffer_elems(g)) {
+    if ((e = hipMalloc(&h->jp, nj * h->elem)) != hipSuccess) return cleanup(DG_ENOMEM, "jump buffer");
+    if ((e = hipMalloc(&h->jsum, (size_t)2 * p->dim * g.C * sizeof(double))) != hipSuccess) return cleanup(DG_ENOMEM, "jump sums");
+  }
+  if ((e = hipMalloc(&h->S1, nm * g.ld * h->elem)) != hipSuccess) return cleanup(DG_ENOMEM, "stage buffer");
+  if ((e = hipMemset(h->S1, 0, nm * g.ld * h->elem)) != hipSuccess) return cleanup(DG_EHIP, "stage buffer clear");
+  if (size_t ls = h->L->limit_scratch_bytes(g)) {
+    if ((e = hipMalloc(&h->lscr, ls)) != hipSuccess) return cleanup(DG_ENOMEM, "limiter scratch");
+  }
+  if ((e = hipMalloc(&h->sc, sizeof(Scal))) != hipSuccess) return cleanup(DG_ENOMEM, "scalars");
+  if ((e = hipMemset(h->sc, 0, sizeof(Scal))) != hipSuccess) return cleanup(DG_EHIP, "scalars clear");
+  *out = h;
+  return DG_OK;
+}
+
+int dg_layout(dg_handle h, int64_t* nmodes, int64_t* ncells, int64_t* ld) {
+  if (!h) return DG_EINVAL;
+  if (nmodes) *nmodes = h->L->nmodes();
+  if (ncells) *ncells = h->g.C;
+  if (ld) *ld = h->g.ld;
+  return DG_OK;
+}
+
+int dg_proj_points(dg_handle h, double* xi, int64_t* npts) {
+  if (!h || !npts) return DG_EINVAL;
+  *npts = h->tabs.NPROJ;
+  if (xi) std::memcpy(xi, h->tabs.xproj.data(), h->tabs.xproj.size() * sizeof(double));
+  return DG_OK;
+}
+
+int dg_project(dg_handle h, const double* prim, int64_t cell0, int64_t ncell, void* w) {
+  if (int r = valid_state(h, w)) return r;
+  if (!prim) return fail(h, DG_EINVAL, "null prim");
+  if (cell0 < 0 || ncell < 0 || cell0 + ncell > h->g.C) return fail(h, DG_EINVAL, "cell range");
+  if (ncell == 0) return DG_OK;
+  h->L->project(prim, cell0, ncell, w, h->g, h->sp, h->stream);
+  return check_launch(h, "project");
+}
+
+static int dt_sequence(dg_handle h, const void* w) {
+  launch_reset_step(h->sc, h->stream);
+  h->L->maxsig(w, h->g, h->sc, h->sp, h->stream);
+  if (h->p.divb == DG_POWELL) h->L->powell_cap(w, h->jsum, h->g, h->sc, h->sp, h->stream);
+  launch_finalize_dt(h->sc, h->sp, h->p.dim, h->p.degree, h->p.divb, h->hmin, h->stream);
+  return check_launch(h, "time step");
+}
+
+int dg_dt(dg_handle h, const void* w, double* dt, double* ch, double* kappa) {
+  if (int r = valid_state(h, w)) return r;
+  if (int r = dt_sequence(h, w)) return r;
+  Scal s;
+  if (int r = check_hip(h, hipMemcpyAsync(&s, h->sc, sizeof(Scal), hipMemcpyDeviceToHost, h->stream), "copy")) return r;
+  if (int r = check_hip(h, hipStreamSynchronize(h->stream), "sync")) return r;
+  if (dt) *dt = s.dt;
+  if (ch) *ch = s.ch;
+  if (kappa) *kappa = s.kappa;
+  if (s.nonfinite) return fail(h, DG_ENONFINITE, "non-finite signal speed");
+  return DG_OK;
+}
+
+int dg_rhs(dg_handle h, const void* w, void* dwdt, double ch, double kappa) {
+  if (int r = valid_state(h, w)) return r;
+  if (!dwdt || dwdt == w) return fail(h, DG_EINVAL, "dwdt must be a distinct array");
+  if (h->p.divb == DG_GLM && !(ch > 0.0)) return fail(h, DG_EINVAL, "GLM needs c_h > 0");
+  launch_set_scalars(h->sc, ch, kappa, 0.0, h->stream);
+  h->L->face(w, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
+  h->L->cell(w, w, dwdt, h->ff, h->jp, h->g, h->sc, h->sp, 0.0, 1.0, 0, h->stream);
+  return check_launch(h, "rhs");
+}
+
+int dg_limit(dg_handle h, void* w, dg_limit_stats* stats) {
+  if (int r = valid_state(h, w)) return r;
+  if (h->p.limiter) h->L->limit(w, h->lscr, h->g, h->sc, h->sp, h->stream);
+  if (int r = check_launch(h, "limit")) return r;
+  if (stats) {
+    Scal s;
+    if (int r = check_hip(h, hipMemcpyAsync(&s, h->sc, sizeof(Scal), hipMemcpyDeviceToHost, h->stream), "copy")) return r;
+    if (int r = check_hip(h, hipStreamSynchronize(h->stream), "sync")) return r;
+    stats->n_tvb_triggered = (int64_t)s.n_tvb;
+    stats->n_mlp_flagged = (int64_t)s.n_mlp;
+    stats->n_fallback = (int64_t)s.n_fallback;
+    stats->n_pos_scaled = (int64_t)s.n_pos;
+    stats->n_floor = (int64_t)s.n_floor;
+    stats->injected_mass = s.inj_mass;
+    stats->injected_energy = s.inj_energy;
+    stats->max_signal = s.last_maxsig;
+    stats->ch = s.ch;
+    if (s.nonfinite) return fail(h, DG_ENONFINITE, "non-finite value in the state");
+  }
+  return DG_OK;
+}
+
+int dg_step(dg_handle h, void* w, int32_t nsteps, double* t) {
+  if (int r = valid_state(h, w)) return r;
+  if (nsteps < 0) return fail(h, DG_EINVAL, "nsteps < 0");
+  const bool lim = h->p.limiter != 0;
+  launch_set_time(h->sc, 0.0, h->stream);  // device clock of this call
+  for (int32_t n = 0; n < nsteps; ++n) {
+    if (int r = dt_sequence(h, w)) return r;
+    // stage 1: S1 = w + dt L(w)
+    h->L->face(w, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
+    h->L->cell(w, w, h->S1, h->ff, h->jp, h->g, h->sc, h->sp, 0.0, 1.0, 1, h->stream);
+    if (lim) h->L->limit(h->S1, h->lscr, h->g, h->sc, h->sp, h->stream);
+    // stage 2: S1 = 3/4 w + 1/4 (S1 + dt L(S1))
+    h->L->face(h->S1, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
+    h->L->cell(h->S1, w, h->S1, h->ff, h->jp, h->g, h->sc, h->sp, 0.75, 0.25, 1, h->stream);
+    if (lim) h->L->limit(h->S1, h->lscr, h->g, h->sc, h->sp, h->stream);
+    // stage 3: w = 1/3 w + 2/3 (S1 + dt L(S1))
+    h->L->face(h->S1, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
+    h->L->cell(h->S1, w, w, h->ff, h->jp, h->g, h->sc, h->sp, 1.0 / 3.0, 2.0 / 3.0, 1, h->stream);
+    if (lim) h->L->limit(w, h->lscr, h->g, h->sc, h->sp, h->stream);
+    if (int r = check_launch(h, "step")) return r;
+  }
+  if (t) {
+    Scal s;
+    if (int r = check_hip(h, hipMemcpyAsync(&s, h->sc, sizeof(Scal), hipMemcpyDeviceToHost, h->stream), "copy")) return r;
+    if (int r = check_hip(h, hipStreamSynchronize(h->stream), "sync")) return r;
+    *t += s.t;
+    if (s.nonfinite) return fail(h, DG_ENONFINITE, "non-finite value in the state");
+  }
+  return DG_OK;
+}
+
+int dg_set_mlp(dg_handle h, const void* w_bf16, const float* b, int32_t in_dim) {
+  if (!h) return DG_EINVAL;
+  (void)w_bf16; (void)b; (void)in_dim;
+  return fail(h, DG_EUNSUPPORTED, "learned indicator not built yet");
+}
+
+int dg_time_kernel(dg_handle h, const void* w, int32_t which, int32_t reps, double* ms) {
+  if (int r = valid_state(h, w)) return r;
+  if (!ms || reps < 1 || which < 0 || which > 3) return fail(h, DG_EINVAL, "time_kernel arguments");
+  // workspaces: the face buffer is filled once so the cell kernel reads valid fluxes
+  if (int r = dt_sequence(h, w)) return r;
+  h->L->face(w, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
+  if (which == 3) {
+    const size_t bytes = (size_t)h->L->nmodes() * h->g.ld * h->elem;
+    if (int r = check_hip(h, hipMemcpyAsync(h->S1, w, bytes, hipMemcpyDeviceToDevice, h->stream), "copy")) return r;
+  }
+  hipEvent_t e0, e1;
+  if (int r = check_hip(h, hipEventCreate(&e0), "event")) return r;
+  if (int r = check_hip(h, hipEventCreate(&e1), "event")) { (void)hipEventDestroy(e0); return r; }
+  (void)hipEventRecord(e0, h->stream);
+  for (int i = 0; i < reps; ++i) {
+    switch (which) {
+      case 0: h->L->face(w, h->ff, h->jp, h->g, h->sc, h->sp, h->stream); break;
+      case 1: h->L->cell(w, w, h->S1, h->ff, h->jp, h->g, h->sc, h->sp, 0.0, 1.0, 1, h->stream); break;
+      case 2: (void)dt_sequence(h, w); break;
+      default: h->L->limit(h->S1, h->lscr, h->g, h->sc, h->sp, h->stream); break;
+    }
+  }
+  (void)hipEventRecord(e1, h->stream);
+  int rc = check_hip(h, hipEventSynchronize(e1), "event sync");
+  float t = 0.f;
+  if (rc == DG_OK) rc = check_hip(h, hipEventElapsedTime(&t, e0, e1), "elapsed");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc == DG_OK) rc = check_launch(h, "time_kernel");
+  *ms = (double)t / reps;
+  return rc;
+}
+
+const char* dg_last_error(dg_handle h) { return h ? h->err.c_str() : g_err.c_str(); }
+
+void dg_destroy(dg_handle h) {
+  if (!h) return;
+  if (h->L) { h->L->free_tables(); delete h->L; }
+  if (h->ff) (void)hipFree(h->ff);
+  if (h->jp) (void)hipFree(h->jp);
+  if (h->jsum) (void)hipFree(h->jsum);
+  if (h->S1) (void)hipFree(h->S1);
+  if (h->lscr) (void)hipFree(h->lscr);
+  if (h->sc) (void)hipFree(h->sc);
+  delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// Internal interface between the C ABI and the templated gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "dg_tables.h"
+
+namespace dgmhd {
+
+// Device-resident scalars of a step: written by reductions and the
+// finalisation kernel, read by every stage kernel (no host round trip).
+struct Scal {
+  double dt, ch, kappa, t;
+  double last_maxsig;                    // max_K sum_a(|v_a|+c)/D of the last reduction
+  unsigned long long maxrate_bits;       // max_K s_K / h_K (bit pattern of a non-negative double)
+  unsigned long long maxsig_bits;        // max_K s_K
+  unsigned long long powell_rate_bits;   // max_K |divB|_K |v.B| / E (Powell cap)
+  unsigned long long n_ch_violation;     // fixed c_h below twice the max signal
+  unsigned long long nonfinite;          // non-finite values met by a reduction
+  // limiter statistics (accumulated, reset by the host)
+  unsigned long long n_tvb, n_pos, n_floor, n_mlp, n_fallback;
+  double inj_mass, inj_energy;
+};
+
+struct Grid {
+  int n0, n1, n2;   // cells per axis (n2 = 1 in 2-D)
+  int64_t C;        // number of cells
+  int64_t ld;       // leading dimension of state arrays
+  double h;         // cell size (uniform grids)
+};
+
+struct SchemeParams {
+  double gamma, cfl, cfl_glm, glm_cr, glm_ch_fixed, powell_eta;
+  double tvb_Mtilde, tvb_beta, tvb_eps, eps_rho, eps_p;
+  int limiter;
+};
+
+// Per-configuration launcher; one instance per handle.
+struct Launcher {
+  virtual ~Launcher() {}
+  virtual hipError_t upload_tables(const Tables& t) = 0;
+  virtual void free_tables() = 0;
+  virtual size_t face_buffer_elems(const Grid& g) const = 0;
+  virtual size_t jump_buffer_elems(const Grid& g) const = 0;
+  // face fluxes of state w into ff (and Powell jumps into jp)
+  virtual void face(const void* w, void* ff, void* jp, const Grid& g, const Scal* sc, const SchemeParams& sp,
+                    hipStream_t s) = 0;
+  // mode 0: out = M^-1 R;  mode 1: out = a0 w0 + b0 (w + dt M^-1 R)
+  virtual void cell(const void* w, const void* w0, void* out, const void* ff, const void* jp, const Grid& g,
+                    const Scal* sc, const SchemeParams& sp, double a0, double b0, int mode, hipStream_t s) = 0;
+  // per-cell signal speeds -> atomic maxima in sc
+  virtual void maxsig(const void* w, const Grid& g, Scal* sc, const SchemeParams& sp, hipStream_t s) = 0;
+  // Powell dt cap: per-face normal-field jumps then per-cell rate
+  virtual void powell_cap(const void* w, void* jsum, const Grid& g, Scal* sc, const SchemeParams& sp,
+                          hipStream_t s) = 0;
+  virtual void project(const double* prim, int64_t cell0, int64_t ncell, void* w, const Grid& g,
+                       const SchemeParams& sp, hipStream_t s) = 0;
+  // limiters in place
+  virtual void limit(void* w, void* scratch, const Grid& g, Scal* sc, const SchemeParams& sp, hipStream_t s) = 0;
+  virtual size_t limit_scratch_bytes(const Grid& g) const = 0;
+  virtual int nmodes() const = 0;
+};
+
+Launcher* make_launcher(int precision, int D, int d, int divb);
+
+// scalar kernels
+void launch_reset_step(Scal* sc, hipStream_t s);
+void launch_finalize_dt(Scal* sc, const SchemeParams& sp, int D, int d, int divb, double hmin, hipStream_t s);
+void launch_set_scalars(Scal* sc, double ch, double kappa, double dt, hipStream_t s);
+void launch_set_time(Scal* sc, double t, hipStream_t s);
+
+}  // namespace dgmhd

@@ -1,0 +1,644 @@
+// gfx950 kernels of the DG right-hand side, stage update, time-step
+// reductions and initial projection.
+//
+// State arrays are SoA: w[mode][cell] with cells fastest, so a wavefront of
+// consecutive cells reads each mode row with one coalesced access.
+//
+// Face kernel (one thread per (axis, face point, face); consecutive threads
+// take consecutive faces of the same point, so both traces are coalesced
+// reads): traces from both cells, face normal field, HLLD, GLM fluxes; the
+// face fluxes go to a face buffer ff[axis][var][point][face] and, for Powell,
+// the normal-field jumps to jp[axis][side][point][face].
+//
+// Cell kernel (one block per tile of TC consecutive cells): the tile's modes
+// are staged in LDS; quadrature points are processed in chunks of NT/TC
+// points: every thread evaluates one (cell, point) state and its D analytic
+// fluxes into LDS, then every thread accumulates its (mode, cell) outputs of
+// the volume integral.  The surface integral gathers the 2D face fluxes of
+// the cell from the face buffer (owner gather, no atomics, deterministic);
+// Powell face terms, GLM damping, the inverse mass and the SSP-RK stage
+// combination are fused before the single store.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <vector>
+
+#include "dg_kernels.h"
+#include "dg_physics.h"
+
+namespace dgmhd {
+
+template <int D, int DEG, int DIVB>
+struct Cfg {
+  static constexpr int P = DEG + 1;
+  static constexpr int N = D == 2 ? (DEG + 1) * (DEG + 2) / 2 : (DEG + 1) * (DEG + 2) * (DEG + 3) / 6;
+  static constexpr int NM1 = D == 2 ? DEG * (DEG + 1) / 2 : DEG * (DEG + 1) * (DEG + 2) / 6;
+  static constexpr int Q = D == 2 ? P * P : P * P * P;
+  static constexpr int FP = D == 2 ? P : P * P;
+  static constexpr int NV = DIVB == GLM ? 9 : 8;
+  static constexpr int NLEG = DIVB == GLM ? 9 : (D == 3 ? 5 : 6);
+  static constexpr int NLDF = DIVB == GLM ? 0 : D * N - NM1;
+  static constexpr int NMODES = NLEG * N + NLDF;
+  // conserved variable of Legendre block j
+  __host__ __device__ static constexpr int legvar(int j) { return (DIVB == POWELL && j == 5) ? 7 : j; }
+};
+
+template <typename T, int D, int DEG, int DIVB>
+struct Tile {
+  using C = Cfg<D, DEG, DIVB>;
+  static constexpr int NT = (sizeof(T) == 8 && D == 3) ? 128 : 256;
+  static constexpr int SF = D * C::NV * NT * (int)sizeof(T);
+  static constexpr int fit(int tc) { return C::NMODES * tc * (int)sizeof(T) + SF <= 60 * 1024; }
+  static constexpr int TC = fit(64) ? 64 : fit(32) ? 32 : fit(16) ? 16 : fit(8) ? 8 : fit(4) ? 4 : fit(2) ? 2 : 1;
+  static constexpr int QCH = NT / TC;
+};
+
+template <typename T>
+struct DevTab {
+  const T *V, *GW, *TF, *LF, *Minv, *PV, *PGW, *PTF, *PLF, *Pmean, *Plin;
+};
+
+__device__ __forceinline__ int64_t nbr(int64_t K, int a, int s, const Grid& g) {
+  int64_t i = K % g.n0;
+  int64_t t = K / g.n0;
+  int64_t j = t % g.n1;
+  int64_t k = t / g.n1;
+  if (a == 0) i = (i + s + g.n0) % g.n0;
+  else if (a == 1) j = (j + s + g.n1) % g.n1;
+  else k = (k + s + g.n2) % g.n2;
+  return i + (int64_t)g.n0 * (j + (int64_t)g.n1 * k);
+}
+
+__device__ __forceinline__ void atomic_max_pos(unsigned long long* addr, double v) {
+  // non-negative doubles order like their bit patterns; NaN is mapped above +inf
+  unsigned long long b = __double_as_longlong(v);
+  if (!(v == v)) b = 0x7ff8000000000000ULL;
+  atomicMax(addr, b);
+}
+
+// ---------------------------------------------------------------------------
+// face kernel
+
+template <typename T, int D, int DEG, int DIVB>
+__global__ void __launch_bounds__(256) k_face(const T* __restrict__ w, T* __restrict__ ff, T* __restrict__ jp,
+                                              DevTab<T> tb, Grid g, const Scal* __restrict__ sc, double gamma) {
+  using C = Cfg<D, DEG, DIVB>;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)D * C::FP * g.C;
+  if (gid >= total) return;
+  const int64_t f = gid % g.C;
+  const int64_t t = gid / g.C;
+  const int r = (int)(t % C::FP);
+  const int a = (int)(t / C::FP);
+  const int64_t L = f, R = nbr(f, a, +1, g);
+  const int64_t ld = g.ld;
+  T uL[9], uR[9];
+  const T* tl = tb.TF + ((a * 2 + 1) * C::FP + r) * C::N;
+  const T* tr = tb.TF + ((a * 2 + 0) * C::FP + r) * C::N;
+#pragma unroll
+  for (int j = 0; j < C::NLEG; ++j) {
+    T sL = 0, sR = 0;
+#pragma unroll
+    for (int l = 0; l < C::N; ++l) {
+      sL += tl[l] * w[(int64_t)(j * C::N + l) * ld + L];
+      sR += tr[l] * w[(int64_t)(j * C::N + l) * ld + R];
+    }
+    uL[C::legvar(j)] = sL;
+    uR[C::legvar(j)] = sR;
+  }
+  if constexpr (C::NLDF > 0) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const T* pl = tb.PTF + (((a * 2 + 1) * D + c) * C::FP + r) * C::NLDF;
+      const T* pr = tb.PTF + (((a * 2 + 0) * D + c) * C::FP + r) * C::NLDF;
+      T sL = 0, sR = 0;
+      for (int l = 0; l < C::NLDF; ++l) {
+        sL += pl[l] * w[(int64_t)(C::NLEG * C::N + l) * ld + L];
+        sR += pr[l] * w[(int64_t)(C::NLEG * C::N + l) * ld + R];
+      }
+      uL[5 + c] = sL;
+      uR[5 + c] = sR;
+    }
+  }
+  T F[9];
+  const T bnF = face_flux<T, C::NV>(uL, uR, a, gamma, (T)sc->ch, F);
+#pragma unroll
+  for (int v = 0; v < C::NV; ++v) ff[((int64_t)(a * C::NV + v) * C::FP + r) * ld + f] = F[v];
+  if constexpr (DIVB == POWELL) {
+    jp[((int64_t)(a * 2 + 0) * C::FP + r) * ld + f] = bnF - uL[5 + a];
+    jp[((int64_t)(a * 2 + 1) * C::FP + r) * ld + f] = uR[5 + a] - bnF;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// cell kernel
+
+template <typename T, int D, int DEG, int DIVB>
+__device__ __forceinline__ T safe_mode_value(int m) {
+  using C = Cfg<D, DEG, DIVB>;
+  return (m == 0 || m == 4 * C::N) ? T(1) : T(0);
+}
+
+template <typename T, int D, int DEG, int DIVB>
+__global__ void __launch_bounds__((Tile<T, D, DEG, DIVB>::NT))
+    k_cell(const T* w, const T* w0, T* out, const T* __restrict__ ff, const T* __restrict__ jp, DevTab<T> tb,
+           Grid g, const Scal* __restrict__ sc, double gamma, double a0, double b0, int mode) {
+  using C = Cfg<D, DEG, DIVB>;
+  using TL = Tile<T, D, DEG, DIVB>;
+  constexpr int NT = TL::NT, TC = TL::TC, QCH = TL::QCH;
+  constexpr int NOUT = C::NMODES * TC;
+  constexpr int NACC = (NOUT + NT - 1) / NT;
+  __shared__ T sw[C::NMODES * TC];
+  __shared__ T sf[D * C::NV * QCH * TC];
+  const int64_t c0 = (int64_t)blockIdx.x * TC;
+  const int tid = threadIdx.x;
+  const int64_t ld = g.ld;
+  for (int i = tid; i < NOUT; i += NT) {
+    const int m = i / TC, c = i % TC;
+    const int64_t K = c0 + c;
+    sw[i] = K < g.C ? w[(int64_t)m * ld + K] : safe_mode_value<T, D, DEG, DIVB>(m);
+  }
+  const T ch = (T)sc->ch;
+  const T ch2 = ch * ch;
+  T acc[NACC];
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) acc[k] = 0;
+
+  for (int qb = 0; qb < C::Q; qb += QCH) {
+    __syncthreads();
+    {
+      const int c = tid % TC, qq = tid / TC, q = qb + qq;
+      if (q < C::Q) {
+        T u[9];
+#pragma unroll
+        for (int j = 0; j < C::NLEG; ++j) {
+          T s = 0;
+#pragma unroll
+          for (int l = 0; l < C::N; ++l) s += tb.V[q * C::N + l] * sw[(j * C::N + l) * TC + c];
+          u[C::legvar(j)] = s;
+        }
+        if constexpr (C::NLDF > 0) {
+#pragma unroll
+          for (int cc = 0; cc < D; ++cc) {
+            T s = 0;
+            for (int l = 0; l < C::NLDF; ++l) s += tb.PV[(cc * C::Q + q) * C::NLDF + l] * sw[(C::NLEG * C::N + l) * TC + c];
+            u[5 + cc] = s;
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          T f[9];
+          mhd_flux<T, C::NV>(u, a, gamma, ch2, f);
+#pragma unroll
+          for (int v = 0; v < C::NV; ++v) sf[((a * C::NV + v) * QCH + qq) * TC + c] = f[v];
+        }
+      }
+    }
+    __syncthreads();
+    const int qmax = (C::Q - qb) < QCH ? (C::Q - qb) : QCH;
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) {
+      const int o = tid + k * NT;
+      if (o < NOUT) {
+        const int m = o / TC, c = o % TC;
+        T s = acc[k];
+        if (m < C::NLEG * C::N) {
+          const int j = m / C::N, l = m % C::N, v = C::legvar(j);
+          for (int a = 0; a < D; ++a)
+            for (int qq = 0; qq < qmax; ++qq)
+              s += tb.GW[(a * C::Q + qb + qq) * C::N + l] * sf[((a * C::NV + v) * QCH + qq) * TC + c];
+        } else {
+          const int l = m - C::NLEG * C::N;
+          for (int a = 0; a < D; ++a)
+            for (int cc = 0; cc < D; ++cc)
+              for (int qq = 0; qq < qmax; ++qq)
+                s += tb.PGW[((a * D + cc) * C::Q + qb + qq) * C::NLDF + l] *
+                     sf[((a * C::NV + 5 + cc) * QCH + qq) * TC + c];
+        }
+        acc[k] = s;
+      }
+    }
+  }
+
+  const double dt = sc->dt;
+  const T kappa = (T)sc->kappa;
+  const T two_h = T(2.0 / g.h);
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) {
+    const int o = tid + k * NT;
+    if (o >= NOUT) continue;
+    const int m = o / TC, c = o % TC;
+    const int64_t K = c0 + c;
+    if (K >= g.C) continue;
+    T s = acc[k];
+    // cell-average state for the Powell term
+    T qv[8];
+    if constexpr (DIVB == POWELL) {
+      const T rho = sw[0 * TC + c];
+      T bm[3];
+      for (int cc = 0; cc < D; ++cc) {
+        T b = 0;
+        for (int l = 0; l < C::NLDF; ++l) b += tb.Pmean[cc * C::NLDF + l] * sw[(C::NLEG * C::N + l) * TC + c];
+        bm[cc] = b;
+      }
+      if (D == 2) bm[2] = sw[(5 * C::N) * TC + c];
+      const T v0 = sw[(1 * C::N) * TC + c] / rho, v1 = sw[(2 * C::N) * TC + c] / rho, v2 = sw[(3 * C::N) * TC + c] / rho;
+      qv[0] = 0; qv[1] = bm[0]; qv[2] = bm[1]; qv[3] = bm[2];
+      qv[4] = v0 * bm[0] + v1 * bm[1] + v2 * bm[2];
+      qv[5] = v0; qv[6] = v1; qv[7] = v2;
+    }
+    for (int a = 0; a < D; ++a) {
+      const int64_t Km = nbr(K, a, -1, g);
+      if (m < C::NLEG * C::N) {
+        const int j = m / C::N, l = m % C::N, v = C::legvar(j);
+        const T* fv = ff + (int64_t)(a * C::NV + v) * C::FP * ld;
+        T sp = 0, sm = 0;
+        for (int r = 0; r < C::FP; ++r) {
+          sp += tb.LF[((a * 2 + 1) * C::FP + r) * C::N + l] * fv[(int64_t)r * ld + K];
+          sm += tb.LF[((a * 2 + 0) * C::FP + r) * C::N + l] * fv[(int64_t)r * ld + Km];
+        }
+        s += sm - sp;
+        if constexpr (DIVB == POWELL) {
+          T pp = 0, pm = 0;
+          const T* jl = jp + (int64_t)(a * 2 + 0) * C::FP * ld;
+          const T* jr = jp + (int64_t)(a * 2 + 1) * C::FP * ld;
+          for (int r = 0; r < C::FP; ++r) {
+            pp += tb.LF[((a * 2 + 1) * C::FP + r) * C::N + l] * jl[(int64_t)r * ld + K];
+            pm += tb.LF[((a * 2 + 0) * C::FP + r) * C::N + l] * jr[(int64_t)r * ld + Km];
+          }
+          s -= qv[v] * (pp + pm);
+        }
+      } else {
+        const int l = m - C::NLEG * C::N;
+        for (int cc = 0; cc < D; ++cc) {
+          const T* fv = ff + (int64_t)(a * C::NV + 5 + cc) * C::FP * ld;
+          T sp = 0, sm = 0;
+          for (int r = 0; r < C::FP; ++r) {
+            sp += tb.PLF[(((a * 2 + 1) * D + cc) * C::FP + r) * C::NLDF + l] * fv[(int64_t)r * ld + K];
+            sm += tb.PLF[(((a * 2 + 0) * D + cc) * C::FP + r) * C::NLDF + l] * fv[(int64_t)r * ld + Km];
+          }
+          s += sm - sp;
+          if constexpr (DIVB == POWELL) {
+            T pp = 0, pm = 0;
+            const T* jl = jp + (int64_t)(a * 2 + 0) * C::FP * ld;
+            const T* jr = jp + (int64_t)(a * 2 + 1) * C::FP * ld;
+            for (int r = 0; r < C::FP; ++r) {
+              pp += tb.PLF[(((a * 2 + 1) * D + cc) * C::FP + r) * C::NLDF + l] * jl[(int64_t)r * ld + K];
+              pm += tb.PLF[(((a * 2 + 0) * D + cc) * C::FP + r) * C::NLDF + l] * jr[(int64_t)r * ld + Km];
+            }
+            s -= qv[5 + cc] * (pp + pm);
+          }
+        }
+      }
+    }
+    T dw = s * two_h * tb.Minv[m];
+    const T wm = sw[m * TC + c];
+    if constexpr (DIVB == GLM) {
+      if (m >= 8 * C::N) dw -= kappa * wm;
+    }
+    if (mode == 0) {
+      out[(int64_t)m * ld + K] = dw;
+    } else {
+      const T base = w0[(int64_t)m * ld + K];
+      out[(int64_t)m * ld + K] = (T)a0 * base + (T)b0 * (wm + (T)dt * dw);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// max signal speed over volume and face points (eq. cfl; reading: max over
+// the cell's quadrature points)
+
+template <typename T, int D, int DEG, int DIVB>
+__device__ __forceinline__ void eval_point(const T* sw, int TC, int c, const T* vl, const T* pv, int pvs, T* u) {
+  using C = Cfg<D, DEG, DIVB>;
+#pragma unroll
+  for (int j = 0; j < C::NLEG; ++j) {
+    T s = 0;
+#pragma unroll
+    for (int l = 0; l < C::N; ++l) s += vl[l] * sw[(j * C::N + l) * TC + c];
+    u[C::legvar(j)] = s;
+  }
+  if constexpr (C::NLDF > 0) {
+    for (int cc = 0; cc < D; ++cc) {
+      T s = 0;
+      for (int l = 0; l < C::NLDF; ++l) s += pv[cc * pvs + l] * sw[(C::NLEG * C::N + l) * TC + c];
+      u[5 + cc] = s;
+    }
+  }
+}
+
+template <typename T, int D, int DEG, int DIVB>
+__global__ void __launch_bounds__(256) k_maxsig(const T* __restrict__ w, DevTab<T> tb, Grid g, Scal* sc,
+                                                double gamma) {
+  using C = Cfg<D, DEG, DIVB>;
+  constexpr int TC = Tile<T, D, DEG, DIVB>::TC;
+  constexpr int NPT = C::Q + 2 * D * C::FP;
+  __shared__ T sw[C::NMODES * TC];
+  __shared__ double red[256];
+  const int64_t c0 = (int64_t)blockIdx.x * TC;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < C::NMODES * TC; i += 256) {
+    const int m = i / TC, c = i % TC;
+    const int64_t K = c0 + c;
+    sw[i] = K < g.C ? w[(int64_t)m * g.ld + K] : safe_mode_value<T, D, DEG, DIVB>(m);
+  }
+  __syncthreads();
+  double smax = 0.0;
+  for (int i = tid; i < NPT * TC; i += 256) {
+    const int c = i % TC, p = i / TC;
+    if (c0 + c >= g.C) continue;
+    T u[9];
+    if (p < C::Q) {
+      eval_point<T, D, DEG, DIVB>(sw, TC, c, tb.V + p * C::N, C::NLDF ? tb.PV + p * C::NLDF : nullptr,
+                                  C::Q * C::NLDF, u);
+    } else {
+      const int fpi = p - C::Q;  // (a*2+s)*FP + r
+      const int as = fpi / C::FP, r = fpi % C::FP;
+      eval_point<T, D, DEG, DIVB>(sw, TC, c, tb.TF + fpi * C::N,
+                                  C::NLDF ? tb.PTF + ((as * D) * C::FP + r) * C::NLDF : nullptr, C::FP * C::NLDF, u);
+    }
+    double s = signal_sum<T, D>(u, gamma);
+    if (!(s == s)) s = __longlong_as_double(0x7ff8000000000000ULL);
+    smax = (s > smax || !(s == s)) ? s : smax;
+  }
+  red[tid] = smax;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st) {
+      double o = red[tid + st];
+      if (o > red[tid] || !(o == o)) red[tid] = o;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    atomic_max_pos(&sc->maxsig_bits, red[0]);
+    atomic_max_pos(&sc->maxrate_bits, red[0] / g.h);
+    if (!(red[0] == red[0])) atomicAdd(&sc->nonfinite, 1ULL);
+  }
+}
+
+// Powell time-step cap (eq. powell_dt with |div B|_K of eq. divb-cell).
+template <typename T, int D, int DEG, int DIVB>
+__global__ void __launch_bounds__(256) k_face_jump(const T* __restrict__ w, double* __restrict__ js, DevTab<T> tb,
+                                                   Grid g, double gamma) {
+  using C = Cfg<D, DEG, DIVB>;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)D * g.C) return;
+  const int64_t f = gid % g.C;
+  const int a = (int)(gid / g.C);
+  const int64_t L = f, R = nbr(f, a, +1, g);
+  const int64_t ld = g.ld;
+  double jl = 0.0, jr = 0.0;
+  for (int r = 0; r < C::FP; ++r) {
+    T bl = 0, br = 0, rl = 0, rr = 0;
+    const T* tl = tb.TF + ((a * 2 + 1) * C::FP + r) * C::N;
+    const T* tr = tb.TF + ((a * 2 + 0) * C::FP + r) * C::N;
+    for (int l = 0; l < C::N; ++l) {
+      rl += tl[l] * w[(int64_t)l * ld + L];
+      rr += tr[l] * w[(int64_t)l * ld + R];
+    }
+    const T* pl = tb.PTF + (((a * 2 + 1) * D + a) * C::FP + r) * C::NLDF;
+    const T* pr = tb.PTF + (((a * 2 + 0) * D + a) * C::FP + r) * C::NLDF;
+    for (int l = 0; l < C::NLDF; ++l) {
+      bl += pl[l] * w[(int64_t)(C::NLEG * C::N + l) * ld + L];
+      br += pr[l] * w[(int64_t)(C::NLEG * C::N + l) * ld + R];
+    }
+    const double iL = 1.0 / sqrt((double)rl), iR = 1.0 / sqrt((double)rr);
+    const double bnF = ((double)bl * iL + (double)br * iR) / (iL + iR);
+    double wgt = tb.LF[((a * 2 + 1) * C::FP + r) * C::N + 0];  // w_r * P_0
+    jl += wgt * fabs(bnF - (double)bl);
+    jr += wgt * fabs((double)br - bnF);
+  }
+  js[(int64_t)(a * 2 + 0) * g.C + f] = jl;
+  js[(int64_t)(a * 2 + 1) * g.C + f] = jr;
+}
+
+template <typename T, int D, int DEG, int DIVB>
+__global__ void __launch_bounds__(256) k_powell_rate(const T* __restrict__ w, const double* __restrict__ js,
+                                                     DevTab<T> tb, Grid g, Scal* sc) {
+  using C = Cfg<D, DEG, DIVB>;
+  __shared__ double red[256];
+  const int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double rate = 0.0;
+  if (K < g.C) {
+    double div = 0.0;
+    for (int a = 0; a < D; ++a) div += js[(int64_t)(a * 2 + 0) * g.C + K] + js[(int64_t)(a * 2 + 1) * g.C + nbr(K, a, -1, g)];
+    // (1/V_K) int dS with dS = (h/2)^(D-1) dS_xi
+    div *= pow(0.5 * g.h, D - 1) / pow(g.h, D);
+    const int64_t ld = g.ld;
+    const double rho = (double)w[K];
+    const double m0 = (double)w[(int64_t)(1 * C::N) * ld + K], m1 = (double)w[(int64_t)(2 * C::N) * ld + K],
+                 m2 = (double)w[(int64_t)(3 * C::N) * ld + K];
+    const double E = (double)w[(int64_t)(4 * C::N) * ld + K];
+    double bm[3] = {0, 0, 0};
+    for (int cc = 0; cc < D; ++cc)
+      for (int l = 0; l < C::NLDF; ++l) bm[cc] += (double)tb.Pmean[cc * C::NLDF + l] * (double)w[(int64_t)(C::NLEG * C::N + l) * ld + K];
+    if (D == 2) bm[2] = (double)w[(int64_t)(5 * C::N) * ld + K];
+    const double vb = (m0 * bm[0] + m1 * bm[1] + m2 * bm[2]) / rho;
+    const double prod = div * fabs(vb);
+    if (prod > 0.0) rate = prod / E;
+  }
+  red[threadIdx.x] = rate;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomic_max_pos(&sc->powell_rate_bits, red[0]);
+}
+
+// ---------------------------------------------------------------------------
+// projection of pointwise primitive values (d+3 rule)
+
+template <typename T, int D, int DEG, int DIVB>
+__global__ void __launch_bounds__(256) k_project(const double* __restrict__ prim, int64_t cell0, int64_t ncell,
+                                                 T* __restrict__ w, const double* __restrict__ vpw,
+                                                 const double* __restrict__ pvpw, const double* __restrict__ minv,
+                                                 int npts, int64_t ld, double gamma) {
+  using C = Cfg<D, DEG, DIVB>;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)C::NMODES * ncell) return;
+  const int64_t c = gid % ncell;
+  const int m = (int)(gid / ncell);
+  auto P = [&](int v, int p) { return prim[((int64_t)v * ncell + c) * npts + p]; };
+  double s = 0.0;
+  for (int p = 0; p < npts; ++p) {
+    const double rho = P(0, p), vx = P(1, p), vy = P(2, p), vz = P(3, p), pr = P(4, p);
+    const double bx = P(5, p), by = P(6, p), bz = P(7, p);
+    double u[9] = {rho, rho * vx, rho * vy, rho * vz,
+                   pr / (gamma - 1.0) + 0.5 * rho * (vx * vx + vy * vy + vz * vz) + 0.5 * (bx * bx + by * by + bz * bz),
+                   bx, by, bz, P(8, p)};
+    if (m < C::NLEG * C::N) {
+      const int j = m / C::N, l = m % C::N;
+      s += vpw[p * C::N + l] * u[C::legvar(j)];
+    } else {
+      const int l = m - C::NLEG * C::N;
+      for (int cc = 0; cc < D; ++cc) s += pvpw[(cc * npts + p) * C::NLDF + l] * u[5 + cc];
+    }
+  }
+  w[(int64_t)m * ld + cell0 + c] = (T)(s * minv[m]);
+}
+
+// ---------------------------------------------------------------------------
+// scalar kernels
+
+__global__ void k_reset_step(Scal* sc) {
+  sc->maxrate_bits = 0ULL;
+  sc->maxsig_bits = 0ULL;
+  sc->powell_rate_bits = 0ULL;
+}
+
+__global__ void k_finalize_dt(Scal* sc, SchemeParams sp, int D, int d, int divb, double hmin) {
+  const double s = __longlong_as_double(sc->maxsig_bits);
+  const double rate = __longlong_as_double(sc->maxrate_bits);
+  double dt = sp.cfl / (2 * d + 1) / rate;
+  double ch = 0.0, kappa = 0.0;
+  if (!(s == s) || !(rate > 0.0)) sc->nonfinite += 1ULL;
+  if (divb == GLM) {
+    if (sp.glm_ch_fixed > 0.0) {
+      ch = sp.glm_ch_fixed;
+      const double cap = sp.cfl_glm * hmin / ((2 * d + 1) * D * ch);
+      dt = fmin(dt, cap);
+      if (ch < 2.0 * s / D) sc->n_ch_violation += 1ULL;
+    } else {
+      ch = (sp.cfl_glm / sp.cfl) * s / D;
+    }
+    kappa = fmin(ch / sp.glm_cr, 1.0 / (3.0 * dt));
+  } else {
+    const double pr = __longlong_as_double(sc->powell_rate_bits);
+    if (pr > 0.0) dt = fmin(dt, sp.powell_eta / pr);
+  }
+  sc->dt = dt;
+  sc->ch = ch;
+  sc->kappa = kappa;
+  sc->t += dt;
+  sc->last_maxsig = s / D;
+}
+
+__global__ void k_set_scalars(Scal* sc, double ch, double kappa, double dt) {
+  sc->ch = ch;
+  sc->kappa = kappa;
+  sc->dt = dt;
+}
+
+__global__ void k_set_time(Scal* sc, double t) { sc->t = t; }
+
+void launch_set_time(Scal* sc, double t, hipStream_t s) { k_set_time<<<1, 1, 0, s>>>(sc, t); }
+void launch_reset_step(Scal* sc, hipStream_t s) { k_reset_step<<<1, 1, 0, s>>>(sc); }
+void launch_finalize_dt(Scal* sc, const SchemeParams& sp, int D, int d, int divb, double hmin, hipStream_t s) {
+  k_finalize_dt<<<1, 1, 0, s>>>(sc, sp, D, d, divb, hmin);
+}
+void launch_set_scalars(Scal* sc, double ch, double kappa, double dt, hipStream_t s) {
+  k_set_scalars<<<1, 1, 0, s>>>(sc, ch, kappa, dt);
+}
+
+}  // namespace dgmhd
+
+#include "dg_limiters.inc"
+
+namespace dgmhd {
+
+// ---------------------------------------------------------------------------
+// launcher
+
+template <typename T, int D, int DEG, int DIVB>
+struct LauncherImpl : Launcher {
+  using C = Cfg<D, DEG, DIVB>;
+  using TL = Tile<T, D, DEG, DIVB>;
+  std::vector<void*> bufs;
+  DevTab<T> tb{};
+  double *vpw = nullptr, *pvpw = nullptr, *minv64 = nullptr;
+
+  template <typename U>
+  hipError_t up(const std::vector<double>& src, const U*& dst) {
+    if (src.empty()) { dst = nullptr; return hipSuccess; }
+    std::vector<U> tmp(src.begin(), src.end());
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, tmp.size() * sizeof(U));
+    if (e != hipSuccess) return e;
+    bufs.push_back(p);
+    e = hipMemcpy(p, tmp.data(), tmp.size() * sizeof(U), hipMemcpyHostToDevice);
+    dst = (const U*)p;
+    return e;
+  }
+
+  hipError_t upload_tables(const Tables& t) override {
+    if (t.N != C::N || t.Q != C::Q || t.FP != C::FP || t.NMODES != C::NMODES) return hipErrorInvalidValue;
+    hipError_t e;
+#define UP(src, dst) if ((e = up<T>(t.src, tb.dst)) != hipSuccess) return e;
+    UP(V, V) UP(GW, GW) UP(TF, TF) UP(LF, LF) UP(Minv, Minv) UP(PV, PV) UP(PGW, PGW) UP(PTF, PTF) UP(PLF, PLF)
+    UP(Pmean, Pmean) UP(Plin, Plin)
+#undef UP
+    const double* d1 = nullptr;
+    if ((e = up<double>(t.VPW, d1)) != hipSuccess) return e;
+    vpw = (double*)d1;
+    if ((e = up<double>(t.PVPW, d1)) != hipSuccess) return e;
+    pvpw = (double*)d1;
+    if ((e = up<double>(t.Minv, d1)) != hipSuccess) return e;
+    minv64 = (double*)d1;
+    return hipSuccess;
+  }
+  void free_tables() override {
+    for (void* p : bufs) (void)hipFree(p);
+    bufs.clear();
+  }
+  size_t face_buffer_elems(const Grid& g) const override { return (size_t)D * C::NV * C::FP * g.ld; }
+  size_t jump_buffer_elems(const Grid& g) const override {
+    return DIVB == POWELL ? (size_t)D * 2 * C::FP * g.ld : 0;
+  }
+  int nmodes() const override { return C::NMODES; }
+
+  void face(const void* w, void* ff, void* jp, const Grid& g, const Scal* sc, const SchemeParams& sp,
+            hipStream_t s) override {
+    const int64_t total = (int64_t)D * C::FP * g.C;
+    const int nb = (int)((total + 255) / 256);
+    k_face<T, D, DEG, DIVB><<<nb, 256, 0, s>>>((const T*)w, (T*)ff, (T*)jp, tb, g, sc, sp.gamma);
+  }
+  void cell(const void* w, const void* w0, void* out, const void* ff, const void* jp, const Grid& g, const Scal* sc,
+            const SchemeParams& sp, double a0, double b0, int mode, hipStream_t s) override {
+    const int nb = (int)((g.C + TL::TC - 1) / TL::TC);
+    k_cell<T, D, DEG, DIVB><<<nb, TL::NT, 0, s>>>((const T*)w, (const T*)w0, (T*)out, (const T*)ff, (const T*)jp, tb,
+                                                   g, sc, sp.gamma, a0, b0, mode);
+  }
+  void maxsig(const void* w, const Grid& g, Scal* sc, const SchemeParams& sp, hipStream_t s) override {
+    const int nb = (int)((g.C + TL::TC - 1) / TL::TC);
+    k_maxsig<T, D, DEG, DIVB><<<nb, 256, 0, s>>>((const T*)w, tb, g, sc, sp.gamma);
+  }
+  void powell_cap(const void* w, void* jsum, const Grid& g, Scal* sc, const SchemeParams& sp,
+                  hipStream_t s) override {
+    if constexpr (DIVB == POWELL) {
+      const int64_t nf = (int64_t)D * g.C;
+      k_face_jump<T, D, DEG, DIVB><<<(int)((nf + 255) / 256), 256, 0, s>>>((const T*)w, (double*)jsum, tb, g, sp.gamma);
+      k_powell_rate<T, D, DEG, DIVB><<<(int)((g.C + 255) / 256), 256, 0, s>>>((const T*)w, (const double*)jsum, tb, g, sc);
+    }
+  }
+  void project(const double* prim, int64_t cell0, int64_t ncell, void* w, const Grid& g, const SchemeParams& sp,
+               hipStream_t s) override {
+    const int64_t total = (int64_t)C::NMODES * ncell;
+    const int npts = (D == 2) ? (DEG + 3) * (DEG + 3) : (DEG + 3) * (DEG + 3) * (DEG + 3);
+    k_project<T, D, DEG, DIVB><<<(int)((total + 255) / 256), 256, 0, s>>>(prim, cell0, ncell, (T*)w, vpw, pvpw,
+                                                                         minv64, npts, g.ld, sp.gamma);
+  }
+  void limit(void* w, void* scratch, const Grid& g, Scal* sc, const SchemeParams& sp, hipStream_t s) override {
+    launch_limit<T, D, DEG, DIVB>(w, scratch, tb, g, sc, sp, s);
+  }
+  size_t limit_scratch_bytes(const Grid& g) const override { return limit_scratch<T, D, DEG, DIVB>(g); }
+  ~LauncherImpl() override { free_tables(); }
+};
+
+Launcher* make_launcher(int precision, int D, int d, int divb) {
+#define CASE(T, DD, DEG, DIV) \
+  if (D == DD && d == DEG && divb == DIV) return new LauncherImpl<T, DD, DEG, DIV>();
+#define ALL(T)                                                                               \
+  CASE(T, 2, 1, GLM) CASE(T, 2, 2, GLM) CASE(T, 2, 3, GLM) CASE(T, 3, 1, GLM) CASE(T, 3, 2, GLM) \
+  CASE(T, 3, 3, GLM) CASE(T, 3, 1, POWELL) CASE(T, 3, 2, POWELL) CASE(T, 3, 3, POWELL)
+  if (precision == 0) { ALL(double) }
+  else { ALL(float) }
+#undef ALL
+#undef CASE
+  return nullptr;
+}
+
+}  // namespace dgmhd

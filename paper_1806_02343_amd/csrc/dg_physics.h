@@ -1,0 +1,196 @@
+// Pointwise ideal-MHD physics on the device: equation of state, analytic flux
+// (eq. mhd-flux), signal speed (eq. cfl), face normal field
+// (eq. bxface-average-alfven), HLLD (Miyoshi & Kusano 2005) and the GLM
+// upwind fluxes (Sec. 4.1.5).  T is the arithmetic type of the path; the
+// thermal pressure is always recovered from the total energy in FP64.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace dgmhd {
+
+enum { V_RHO = 0, V_M1 = 1, V_E = 4, V_B1 = 5, V_PSI = 8 };
+
+// p = (gamma-1)(E - m^2/(2 rho) - B^2/2), evaluated in FP64.
+template <typename T>
+__device__ __forceinline__ double pressure64(const T* u, double gamma) {
+  double r = (double)u[0];
+  double m2 = (double)u[1] * (double)u[1] + (double)u[2] * (double)u[2] + (double)u[3] * (double)u[3];
+  double b2 = (double)u[5] * (double)u[5] + (double)u[6] * (double)u[6] + (double)u[7] * (double)u[7];
+  return (gamma - 1.0) * ((double)u[4] - 0.5 * m2 / r - 0.5 * b2);
+}
+
+// Analytic flux along axis a of the NV-component state u (NV = 9: GLM).
+template <typename T, int NV>
+__device__ __forceinline__ void mhd_flux(const T* u, int a, double gamma, T ch2, T* f) {
+  const T r = u[0];
+  const T ir = T(1) / r;
+  const T v0 = u[1] * ir, v1 = u[2] * ir, v2 = u[3] * ir;
+  const T b0 = u[5], b1 = u[6], b2 = u[7];
+  const T p = (T)pressure64(u, gamma);
+  const T pt = p + T(0.5) * (b0 * b0 + b1 * b1 + b2 * b2);
+  const T vb = v0 * b0 + v1 * b1 + v2 * b2;
+  const T va = a == 0 ? v0 : (a == 1 ? v1 : v2);
+  const T ba = a == 0 ? b0 : (a == 1 ? b1 : b2);
+  f[0] = r * va;
+  f[1] = u[1] * va - b0 * ba;
+  f[2] = u[2] * va - b1 * ba;
+  f[3] = u[3] * va - b2 * ba;
+  f[1 + a] += pt;
+  f[4] = (u[4] + pt) * va - vb * ba;
+  f[5] = b0 * va - v0 * ba;
+  f[6] = b1 * va - v1 * ba;
+  f[7] = b2 * va - v2 * ba;
+  if (NV == 9) {
+    f[5 + a] += u[8];
+    f[8] = ch2 * ba;
+  }
+}
+
+// sum_a (|v_a| + c), c = sqrt(gamma p / rho + B^2 / rho), over the first D axes.
+template <typename T, int D>
+__device__ __forceinline__ double signal_sum(const T* u, double gamma) {
+  double r = (double)u[0];
+  double p = pressure64(u, gamma);
+  double b2 = (double)u[5] * (double)u[5] + (double)u[6] * (double)u[6] + (double)u[7] * (double)u[7];
+  double c = sqrt((gamma * p + b2) / r);
+  double s = 0.0;
+  for (int a = 0; a < D; ++a) s += fabs((double)u[1 + a] / r) + c;
+  return s;
+}
+
+// HLLD in the face frame.  wl/wr: (rho, u, v, w, p, By, Bz); bx common normal
+// field.  Output flux of (rho, m_n, m_t1, m_t2, E, B_t1, B_t2) (the normal-B
+// flux is zero and not returned).
+template <typename T>
+__device__ __forceinline__ void hlld_flux(const T* wl, const T* wr, T bx, double gamma, T* out) {
+  const T g = (T)gamma;
+  T UL[7], UR[7], FL[7], FR[7], EL, ER, ptL, ptR, cfL, cfR;
+  auto cf = [&](const T* W, T* U, T* F, T& E, T& pt, T& c) {
+    const T rho = W[0], u = W[1], v = W[2], w = W[3], p = W[4], by = W[5], bz = W[6];
+    const T bb = bx * bx + by * by + bz * bz;
+    E = p / (g - T(1)) + T(0.5) * rho * (u * u + v * v + w * w) + T(0.5) * bb;
+    pt = p + T(0.5) * bb;
+    const T vb = u * bx + v * by + w * bz;
+    U[0] = rho; U[1] = rho * u; U[2] = rho * v; U[3] = rho * w; U[4] = E; U[5] = by; U[6] = bz;
+    F[0] = rho * u;
+    F[1] = rho * u * u + pt - bx * bx;
+    F[2] = rho * v * u - bx * by;
+    F[3] = rho * w * u - bx * bz;
+    F[4] = (E + pt) * u - vb * bx;
+    F[5] = by * u - v * bx;
+    F[6] = bz * u - w * bx;
+    const T gp = g * p;
+    const T s = (gp + bb) / rho;
+    T disc = s * s - T(4) * gp * bx * bx / (rho * rho);
+    disc = disc > T(0) ? disc : T(0);
+    c = sqrt(T(0.5) * (s + sqrt(disc)));
+  };
+  cf(wl, UL, FL, EL, ptL, cfL);
+  cf(wr, UR, FR, ER, ptR, cfR);
+  const T uL = wl[1], uR = wr[1], rL = wl[0], rR = wr[0];
+  const T cmax = cfL > cfR ? cfL : cfR;
+  const T SL = (uL < uR ? uL : uR) - cmax;
+  const T SR = (uL > uR ? uL : uR) + cmax;
+  if (SL > T(0)) { for (int k = 0; k < 7; ++k) out[k] = FL[k]; return; }
+  if (SR <= T(0)) { for (int k = 0; k < 7; ++k) out[k] = FR[k]; return; }
+  const T dL = (SL - uL) * rL, dR = (SR - uR) * rR;
+  const T den = dR - dL;
+  const T SM = (dR * uR - dL * uL - ptR + ptL) / den;
+  const T ptS = (dR * ptL - dL * ptR + rL * rR * (SR - uR) * (SL - uL) * (uR - uL)) / den;
+  // outer star states
+  T Us[2][7], rs[2], vs[2], ws[2], bys[2], bzs[2], Es[2], vbs[2];
+  for (int side = 0; side < 2; ++side) {
+    const T* W = side ? wr : wl;
+    const T* U = side ? UR : UL;
+    const T S = side ? SR : SL;
+    const T d = side ? dR : dL;
+    const T E = side ? ER : EL, pt = side ? ptR : ptL;
+    const T rho = W[0], u = W[1], v = W[2], w = W[3], by = W[5], bz = W[6];
+    const T r_s = d / (S - SM);
+    const T dd = d * (S - SM) - bx * bx;
+    const T sc = rho * (S - u) * (S - u);
+    const T thr = T(1e-12) * (sc > bx * bx ? sc : bx * bx);
+    T v_s, w_s, by_s, bz_s;
+    if (fabs(dd) <= thr) {
+      v_s = v; w_s = w; by_s = by; bz_s = bz;
+    } else {
+      const T idd = T(1) / dd;
+      v_s = v - bx * by * (SM - u) * idd;
+      w_s = w - bx * bz * (SM - u) * idd;
+      const T fac = (d * (S - u) - bx * bx) * idd;
+      by_s = by * fac;
+      bz_s = bz * fac;
+    }
+    const T vb = u * bx + v * by + w * bz;
+    const T vb_s = SM * bx + v_s * by_s + w_s * bz_s;
+    const T E_s = ((S - u) * E - pt * u + ptS * SM + bx * (vb - vb_s)) / (S - SM);
+    rs[side] = r_s; vs[side] = v_s; ws[side] = w_s; bys[side] = by_s; bzs[side] = bz_s;
+    Es[side] = E_s; vbs[side] = vb_s;
+    Us[side][0] = r_s; Us[side][1] = r_s * SM; Us[side][2] = r_s * v_s; Us[side][3] = r_s * w_s;
+    Us[side][4] = E_s; Us[side][5] = by_s; Us[side][6] = bz_s;
+    (void)U;
+  }
+  const T sqL = sqrt(rs[0]), sqR = sqrt(rs[1]);
+  const T SsL = SM - fabs(bx) / sqL, SsR = SM + fabs(bx) / sqR;
+  if (SsL > T(0)) {
+    for (int k = 0; k < 7; ++k) out[k] = FL[k] + SL * (Us[0][k] - UL[k]);
+    return;
+  }
+  if (SsR <= T(0)) {
+    for (int k = 0; k < 7; ++k) out[k] = FR[k] + SR * (Us[1][k] - UR[k]);
+    return;
+  }
+  const T s = bx >= T(0) ? T(1) : T(-1);
+  const T isum = T(1) / (sqL + sqR);
+  const T vss = (sqL * vs[0] + sqR * vs[1] + (bys[1] - bys[0]) * s) * isum;
+  const T wss = (sqL * ws[0] + sqR * ws[1] + (bzs[1] - bzs[0]) * s) * isum;
+  const T byss = (sqL * bys[1] + sqR * bys[0] + sqL * sqR * (vs[1] - vs[0]) * s) * isum;
+  const T bzss = (sqL * bzs[1] + sqR * bzs[0] + sqL * sqR * (ws[1] - ws[0]) * s) * isum;
+  const T vbss = SM * bx + vss * byss + wss * bzss;
+  if (SM > T(0)) {
+    const T Ess = Es[0] - sqL * (vbs[0] - vbss) * s;
+    const T Uss[7] = {rs[0], rs[0] * SM, rs[0] * vss, rs[0] * wss, Ess, byss, bzss};
+    for (int k = 0; k < 7; ++k) out[k] = FL[k] + SL * (Us[0][k] - UL[k]) + SsL * (Uss[k] - Us[0][k]);
+  } else {
+    const T Ess = Es[1] + sqR * (vbs[1] - vbss) * s;
+    const T Uss[7] = {rs[1], rs[1] * SM, rs[1] * vss, rs[1] * wss, Ess, byss, bzss};
+    for (int k = 0; k < 7; ++k) out[k] = FR[k] + SR * (Us[1][k] - UR[k]) + SsR * (Uss[k] - Us[1][k]);
+  }
+}
+
+// Numerical flux through a face with normal +e_a between traces uL and uR
+// (global components).  Writes F (NV components) and returns B^n_F.
+template <typename T, int NV>
+__device__ __forceinline__ T face_flux(const T* uL, const T* uR, int a, double gamma, T ch, T* F) {
+  const int n = a, t1 = (a + 1) % 3, t2 = (a + 2) % 3;
+  T wl[7], wr[7];
+  {
+    const T ir = T(1) / uL[0];
+    wl[0] = uL[0]; wl[1] = uL[1 + n] * ir; wl[2] = uL[1 + t1] * ir; wl[3] = uL[1 + t2] * ir;
+    wl[4] = (T)pressure64(uL, gamma); wl[5] = uL[5 + t1]; wl[6] = uL[5 + t2];
+  }
+  {
+    const T ir = T(1) / uR[0];
+    wr[0] = uR[0]; wr[1] = uR[1 + n] * ir; wr[2] = uR[1 + t1] * ir; wr[3] = uR[1 + t2] * ir;
+    wr[4] = (T)pressure64(uR, gamma); wr[5] = uR[5 + t1]; wr[6] = uR[5 + t2];
+  }
+  const T bnL = uL[5 + n], bnR = uR[5 + n];
+  const T iL = T(1) / sqrt(uL[0]), iR = T(1) / sqrt(uR[0]);
+  const T bnF = (bnL * iL + bnR * iR) / (iL + iR);
+  T fn[7];
+  hlld_flux<T>(wl, wr, bnF, gamma, fn);
+  F[0] = fn[0];
+  F[1 + n] = fn[1]; F[1 + t1] = fn[2]; F[1 + t2] = fn[3];
+  F[4] = fn[4];
+  F[5 + n] = T(0); F[5 + t1] = fn[5]; F[5 + t2] = fn[6];
+  if (NV == 9) {
+    const T psL = uL[8], psR = uR[8];
+    const T bn_s = T(0.5) * (bnL + bnR) - (psR - psL) / (T(2) * ch);
+    const T ps_s = T(0.5) * (psL + psR) - T(0.5) * ch * (bnR - bnL);
+    F[5 + n] = ps_s;
+    F[8] = ch * ch * bn_s;
+  }
+  return bnF;
+}
+
+}  // namespace dgmhd
