@@ -331,10 +331,10 @@ class DG:
     # SSP-RK3
 
     def step(self, w, limiter=None):
-        """One SSP-RK3 step (Shu-Osher form).  limiter(w) -> w applied after
-        every stage.  Returns (w_new, dt, ch, kappa)."""
+        """One SSP-RK3 step (Shu-Osher form).  limiter(w, ch) -> w is applied
+        after every stage with the step's c_h.  Returns (w_new, dt, ch, kappa)."""
         dt, ch, kappa = self.timestep(w)
-        lim = limiter if limiter is not None else (lambda x: x)
+        lim = (lambda x: limiter(x, ch)) if limiter is not None else (lambda x: x)
         u1 = lim(w + dt * self.rhs(w, ch, kappa))
         u2 = lim(0.75 * w + 0.25 * (u1 + dt * self.rhs(u1, ch, kappa)))
         u3 = lim(w / 3.0 + 2.0 / 3.0 * (u2 + dt * self.rhs(u2, ch, kappa)))

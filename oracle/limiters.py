@@ -1,0 +1,193 @@
+"""Slope and positivity limiters (oracle; test infrastructure only).
+
+TVB slope limiter (Sec. 4.2.1, eq. tvb-limiter): per cell and direction, the
+slope a (the weight of the degree-1 Legendre mode along that direction) is
+compared with the neighbour mean differences Delta = (mean_{i+1} - mean_i)/2
+and (mean_i - mean_{i-1})/2; with the threshold M = M~/dx kept at M~ constant,
+sigma = a if |a| <= M~ dx, else minmod(a, beta Delta_L, beta Delta_R); the
+cell is troubled when |sigma - a| > eps for some direction and variable.
+Characteristic limiting (Sec. 4.2.2) applies this to L(mean) . a and maps the
+limited slopes back with R.  A troubled cell gets the limited slopes in the
+directions that triggered, keeps its other slopes unchanged and loses all
+modes of degree >= 2 (all variables).
+
+LDF slope fix (Sec. 4.2.4): diagonal slopes rescaled so that their sum is
+zero (delta+- rule), then the linear field is L2-projected on the LDF basis.
+
+Positivity limiter (Sec. 4.3, eq. wtilde, eq. tau_rho, eq. tau_press): floors
+on the cell averages (tallied), then w <- tau w + (1 - tau) w_mean with tau
+the smallest of (rho_bar - eps)/(rho_bar - rho_q) over points with
+rho_q < eps and (p_bar - eps)/(p_bar - p_q) over points with p_q < eps,
+over all volume and face quadrature points.  Reading: p_q only counts where
+rho_q > 0; a second pass is made if the first one leaves any point below
+the floors.
+"""
+import numpy as np
+
+from . import eigen
+from . import physics as ph
+from .dg import GLM, POWELL
+
+
+def minmod(a, b, c):
+    out = np.zeros(np.broadcast(a, b, c).shape)
+    pos = (a > 0) & (b > 0) & (c > 0)
+    neg = (a < 0) & (b < 0) & (c < 0)
+    out = np.where(pos, np.minimum(np.minimum(a, b), c), out)
+    out = np.where(neg, np.maximum(np.maximum(a, b), c), out)
+    return out
+
+
+def tvb_sigma(a, dl, dr, Mtilde, h, beta):
+    """Limited slope of eq. tvb-limiter with M = M~/h."""
+    return np.where(np.abs(a) <= Mtilde * h, a, minmod(a, beta * dl, beta * dr))
+
+
+def slope_limit(s, w, Mtilde=5.0, beta=2.0, eps=1e-8, characteristic=True, ch=1.0):
+    """TVB (characteristic) slope limiter on a uniform grid (GLM, Legendre
+    basis).  Returns (w_new, troubled flags)."""
+    assert s.divb == GLM
+    D, n = s.D, s.n
+    C = w.shape[0]
+    h = s.mesh.h
+    means = s.cell_means(w)  # [var, C]
+    out = w.copy()
+    troubled = np.zeros(C, dtype=bool)
+    new_slopes = {}
+    for a in range(D):
+        up = s.mesh.neighbor(a, +1)
+        dn = s.mesh.neighbor(a, -1)
+        lslope = 1 + a  # Legendre mode with exponent e_a
+        slope = w[:, [v * n + lslope for v in range(9)]].T  # [var, C]
+        dl = 0.5 * (means[:, up] - means)
+        dr = 0.5 * (means - means[:, dn])
+        sig_cons = np.empty_like(slope)
+        trig = np.zeros(C, dtype=bool)
+        for c in range(C):
+            if characteristic:
+                L, R = eigen.char_matrices(means[:, c], a, s.gamma, ch)
+            else:
+                L = R = np.eye(9)
+            ca, cl, cr = L @ slope[:, c], L @ dl[:, c], L @ dr[:, c]
+            sig = tvb_sigma(ca, cl, cr, Mtilde, h[c], beta)
+            t = np.abs(sig - ca) > eps
+            trig[c] = t.any()
+            sig_cons[:, c] = R @ np.where(t, sig, ca)
+        new_slopes[a] = (trig, sig_cons)
+        troubled |= trig
+    for a in range(D):
+        trig, sig_cons = new_slopes[a]
+        sel = troubled & trig
+        for v in range(9):
+            out[sel, v * n + 1 + a] = sig_cons[v, sel]
+    hi = [v * n + l for v in range(9) for l in range(D + 1, n)]
+    out[np.ix_(troubled, hi)] = 0.0
+    return out, troubled
+
+
+def ldf_divfree_fix(S):
+    """delta+- rescaling of Sec. 4.2.4 on a slope matrix S[c, b] = dB_c/dxi_b:
+    returns S with corrected diagonal (sum zero, |sigma~| <= |sigma|)."""
+    S = np.array(S, dtype=np.float64)
+    D = S.shape[0]
+    sig = np.diag(S).copy()
+    dp = np.maximum(sig, 0.0).sum()
+    dm = np.maximum(-sig, 0.0).sum()
+    delta = dp - dm
+    if delta > 0:
+        sig = np.where(sig > 0, sig * (dm / dp), sig)
+    elif delta < 0:
+        sig = np.where(sig < 0, sig * (dp / dm), sig)
+    for c in range(D):
+        S[c, c] = sig[c]
+    return S
+
+
+def ldf_project_linear(s, Bmean, S):
+    """LDF weights of the linear field B_c = Bmean_c + sum_b S[c, b] xi_b
+    (divergence-free) by L2 projection onto the LDF basis."""
+    from .quadrature import tensor_rule
+    xq, wq = tensor_rule(s.d + 1, s.D)
+    Bq = Bmean[:, None] + S @ xq.T  # [c, q]
+    return np.einsum("cq,cql,q->l", Bq, s.Phi, wq) / s.Mldf
+
+
+def positivity(s, w, eps_rho=1e-12, eps_p=1e-12):
+    """Positivity limiter on all volume and face points.  Returns
+    (w_new, stats dict)."""
+    g = s.gamma
+    out = w.copy()
+    C = w.shape[0]
+    vol = s.mesh.h ** s.D
+    stats = dict(n_floor=0, n_pos_scaled=0, injected_mass=0.0, injected_energy=0.0)
+    n = s.n
+    eidx = s.leg_vars.index(ph.EN) * n
+    # floors on the cell averages
+    Ub = s.cell_means(out)
+    low = Ub[ph.RHO] < eps_rho
+    if low.any():
+        stats["injected_mass"] += float(((eps_rho - Ub[ph.RHO][low]) * vol[low]).sum())
+        out[low, 0] = eps_rho
+        stats["n_floor"] += int(low.sum())
+        Ub = s.cell_means(out)
+    pb = ph.pressure(Ub, g)
+    lowp = pb < eps_p
+    if lowp.any():
+        ke = 0.5 * (Ub[ph.M1] ** 2 + Ub[ph.M2] ** 2 + Ub[ph.M3] ** 2) / Ub[ph.RHO]
+        me = 0.5 * (Ub[ph.B1] ** 2 + Ub[ph.B2] ** 2 + Ub[ph.B3] ** 2)
+        Enew = eps_p / (g - 1.0) + ke + me
+        stats["injected_energy"] += float(((Enew - Ub[ph.EN])[lowp] * vol[lowp]).sum())
+        out[lowp, eidx] = Enew[lowp]
+        stats["n_floor"] += int(lowp.sum())
+        Ub = s.cell_means(out)
+        pb = ph.pressure(Ub, g)
+    # modes that carry the cell mean (kept by the scaling)
+    keep = np.zeros(s.nmodes, dtype=bool)
+    keep[[j * n for j in range(len(s.leg_vars))]] = True
+    if s.nldf:
+        from . import basis as Bm
+        degs = Bm.ldf_degrees(s.D, s.d)
+        o = len(s.leg_vars) * n
+        for l, dgl in enumerate(degs):
+            if dgl == 0:
+                keep[o + l] = True
+    for _ in range(2):
+        pts = np.concatenate(s.all_point_states(out), axis=2)  # [var, C, P]
+        rq = pts[ph.RHO]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            pq = ph.pressure(pts, g)
+        tau = np.ones(C)
+        rb = Ub[ph.RHO][:, None]
+        m = rq < eps_rho
+        with np.errstate(divide="ignore", invalid="ignore"):
+            tr = np.where(m, (rb - eps_rho) / (rb - rq), 1.0)
+            mp = (rq > 0) & (pq < eps_p)
+            tp = np.where(mp, (pb[:, None] - eps_p) / (pb[:, None] - pq), 1.0)
+        tau = np.minimum(tau, np.minimum(tr.min(axis=1), tp.min(axis=1)))
+        sel = tau < 1.0
+        if not sel.any():
+            break
+        stats["n_pos_scaled"] += int(sel.sum())
+        out[np.ix_(sel, ~keep)] *= tau[sel][:, None]
+    return out, stats
+
+
+def make_stage_limiter(s, limiter, Mtilde=5.0, beta=2.0, eps=1e-8, eps_rho=1e-12, eps_p=1e-12, stats=None):
+    """Limiter applied after every RK stage: slope limiter, then positivity.
+    limiter: bit flags 1 = TVB, 2 = characteristic variables, 4 = positivity.
+    Called as lim(w, ch) with the step's c_h (GLM block of the eigensystem);
+    ch = None takes c_h from the time-step rule applied to w itself."""
+    def lim(w, ch=None):
+        if ch is None:
+            ch = s.timestep(w)[1] if s.divb == GLM else 0.0
+        if limiter & 1:
+            w, tr = slope_limit(s, w, Mtilde, beta, eps, characteristic=bool(limiter & 2), ch=ch)
+            if stats is not None:
+                stats["n_tvb"] = stats.get("n_tvb", 0) + int(tr.sum())
+        if limiter & 4:
+            w, st = positivity(s, w, eps_rho, eps_p)
+            if stats is not None:
+                for k, v in st.items():
+                    stats[k] = stats.get(k, 0) + v
+        return w
+    return lim

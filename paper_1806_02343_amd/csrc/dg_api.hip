@@ -69,6 +69,13 @@ int dg_init(const dg_params* p, const dg_mesh* m, void* hip_stream, dg_handle* o
   if (p->rk_stages != 3) return fail(nullptr, DG_EUNSUPPORTED, "only SSP-RK3 (rk_stages = 3)");
   if (!(p->gamma > 1.0) || !(p->cfl > 0.0) || !(p->cfl < 1.0)) return fail(nullptr, DG_EINVAL, "gamma/cfl");
   if (m->kind != DG_MESH_UNIFORM) return fail(nullptr, DG_EUNSUPPORTED, "octree meshes not built yet");
+  if (p->limiter & ~(DG_LIM_TVB | DG_LIM_CHAR | DG_LIM_POS | DG_LIM_LEARNED))
+    return fail(nullptr, DG_EINVAL, "unknown limiter flags");
+  if ((p->limiter & DG_LIM_TVB) && p->divb == DG_POWELL)
+    return fail(nullptr, DG_EUNSUPPORTED, "slope limiter with the Powell/LDF basis not built");
+  if ((p->limiter & (DG_LIM_CHAR | DG_LIM_LEARNED)) && !(p->limiter & DG_LIM_TVB))
+    return fail(nullptr, DG_EINVAL, "characteristic/learned flags need DG_LIM_TVB");
+  if (p->limiter & DG_LIM_LEARNED) return fail(nullptr, DG_EUNSUPPORTED, "learned indicator not built yet");
   for (int a = 0; a < p->dim; ++a)
     if (m->n[a] < 1 || !(m->box[a] > 0.0)) return fail(nullptr, DG_EINVAL, "mesh size");
   for (int a = 1; a < p->dim; ++a)
@@ -183,6 +190,11 @@ int dg_rhs(dg_handle h, const void* w, void* dwdt, double ch, double kappa) {
 
 int dg_limit(dg_handle h, void* w, dg_limit_stats* stats) {
   if (int r = valid_state(h, w)) return r;
+  launch_reset_stats(h->sc, h->stream);
+  // the characteristic GLM block needs c_h: take it from this state's time-step rule
+  if ((h->p.limiter & DG_LIM_TVB) && h->p.divb == DG_GLM) {
+    if (int r = dt_sequence(h, w)) return r;
+  }
   if (h->p.limiter) h->L->limit(w, h->lscr, h->g, h->sc, h->sp, h->stream);
   if (int r = check_launch(h, "limit")) return r;
   if (stats) {
@@ -208,6 +220,7 @@ int dg_step(dg_handle h, void* w, int32_t nsteps, double* t) {
   if (nsteps < 0) return fail(h, DG_EINVAL, "nsteps < 0");
   const bool lim = h->p.limiter != 0;
   launch_set_time(h->sc, 0.0, h->stream);  // device clock of this call
+  launch_reset_stats(h->sc, h->stream);
   for (int32_t n = 0; n < nsteps; ++n) {
     if (int r = dt_sequence(h, w)) return r;
     // stage 1: S1 = w + dt L(w)

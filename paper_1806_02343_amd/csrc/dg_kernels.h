@@ -69,5 +69,6 @@ void launch_reset_step(Scal* sc, hipStream_t s);
 void launch_finalize_dt(Scal* sc, const SchemeParams& sp, int D, int d, int divb, double hmin, hipStream_t s);
 void launch_set_scalars(Scal* sc, double ch, double kappa, double dt, hipStream_t s);
 void launch_set_time(Scal* sc, double t, hipStream_t s);
+void launch_reset_stats(Scal* sc, hipStream_t s);
 
 }  // namespace dgmhd

@@ -525,6 +525,13 @@ __global__ void k_set_scalars(Scal* sc, double ch, double kappa, double dt) {
 
 __global__ void k_set_time(Scal* sc, double t) { sc->t = t; }
 
+__global__ void k_reset_stats(Scal* sc) {
+  sc->n_tvb = sc->n_pos = sc->n_floor = sc->n_mlp = sc->n_fallback = 0ULL;
+  sc->inj_mass = sc->inj_energy = 0.0;
+}
+
+void launch_reset_stats(Scal* sc, hipStream_t s) { k_reset_stats<<<1, 1, 0, s>>>(sc); }
+
 void launch_set_time(Scal* sc, double t, hipStream_t s) { k_set_time<<<1, 1, 0, s>>>(sc, t); }
 void launch_reset_step(Scal* sc, hipStream_t s) { k_reset_step<<<1, 1, 0, s>>>(sc); }
 void launch_finalize_dt(Scal* sc, const SchemeParams& sp, int D, int d, int divb, double hmin, hipStream_t s) {

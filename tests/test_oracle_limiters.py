@@ -1,0 +1,197 @@
+"""Pins of the oracle's limiters and eigensystem (no GPU): the statements of
+Sec. 4.2-4.3 (means kept, linear data untouched, positivity at every point,
+tau = 1 leaves the cell bitwise unchanged, LDF fix divergence-free and
+non-increasing), and L A R = diag(lambda) against a finite-difference flux
+Jacobian."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import dg, eigen, limiters
+from oracle import physics as ph
+from oracle.quadrature import tensor_rule
+
+G = 5.0 / 3.0
+
+
+def test_minmod_and_tvb_sigma():
+    a = np.array([1.0, -1.0, 1.0, 0.5, 3.0])
+    b = np.array([2.0, -0.5, -1.0, 0.2, 4.0])
+    c = np.array([3.0, -2.0, 2.0, 0.9, 5.0])
+    assert np.array_equal(limiters.minmod(a, b, c), [1.0, -0.5, 0.0, 0.2, 3.0])
+    # linear data never changes: minmod(a, 2a, 2a) = a
+    x = np.linspace(-2, 2, 9)
+    assert np.array_equal(limiters.tvb_sigma(x, x, x, 0.0, 0.1, 2.0), x)
+    # below the threshold |a| <= M~ h the slope is kept even at an extremum
+    assert limiters.tvb_sigma(np.array([0.4]), np.array([1.0]), np.array([-1.0]), 5.0, 0.1, 2.0)[0] == 0.4
+    assert limiters.tvb_sigma(np.array([0.6]), np.array([1.0]), np.array([-1.0]), 5.0, 0.1, 2.0)[0] == 0.0
+
+
+def _fd_jacobian7(u, a, bn):
+    perm = eigen.frame_permutation(a)[:8]
+    sel = [0, 1, 2, 3, 4, 6, 7]
+
+    def F7(x7):
+        uf = np.zeros(8)
+        uf[sel] = x7
+        uf[5] = bn
+        ug = np.zeros(8)
+        ug[perm] = uf
+        return ph.flux(ug[:, None], a, G)[:, 0][perm][sel]
+    uf = u[perm][sel]
+    J = np.zeros((7, 7))
+    for k in range(7):
+        e = np.zeros(7)
+        hh = 1e-6 * max(1.0, abs(uf[k]))
+        e[k] = hh
+        J[:, k] = (F7(uf + e) - F7(uf - e)) / (2 * hh)
+    return J
+
+
+@pytest.mark.parametrize("kind", ["generic", "bt_zero", "bn_zero", "triple"])
+def test_eigensystem_diagonalises_flux_jacobian(kind):
+    rng = np.random.default_rng({"generic": 1, "bt_zero": 2, "bn_zero": 3, "triple": 4}[kind])
+    for _ in range(4):
+        rho, v, p, B = rng.uniform(0.5, 2), rng.uniform(-1, 1, 3), rng.uniform(0.1, 2), rng.uniform(-1, 1, 3)
+        for a in range(3):
+            BB = B.copy()
+            n, t1, t2 = ph.face_frame(a)
+            if kind == "bt_zero":
+                BB[t1] = BB[t2] = 0.0
+            if kind == "bn_zero":
+                BB[n] = 0.0
+            if kind == "triple":
+                BB[t1] = BB[t2] = 0.0
+                BB[n] = np.sqrt(G * p)  # c_A = a
+            u = ph.prim_to_cons(np.array(rho), v, np.array(p), BB, G, np.array(0.2))
+            L, R = eigen.char_matrices(u, a, G, 1.7)
+            assert np.abs(L @ R - np.eye(9)).max() < 1e-12
+            assert np.linalg.cond(R) < 1e4
+            perm = eigen.frame_permutation(a)
+            rows = [perm[i] for i in eigen.IDX7]
+            J = _fd_jacobian7(u[:8], a, u[perm[5]])
+            Dm = L[eigen.IDX7][:, rows] @ J @ R[rows][:, eigen.IDX7]
+            off = Dm - np.diag(np.diag(Dm))
+            assert np.abs(off).max() < 1e-7 * max(1.0, np.abs(Dm).max())
+            # eigenvalues sorted u-cf <= u-ca <= u-cs <= u <= ...
+            lam = np.diag(Dm)
+            assert np.all(np.diff(lam) > -1e-7)
+            # GLM pair (B_n, psi): L_g [[0, 1], [c_h^2, 0]] R_g = diag(c_h, -c_h)
+            gi = [perm[5], perm[8]]
+            A2 = np.array([[0.0, 1.0], [1.7 ** 2, 0.0]])
+            cols = [i for i in range(9) if np.abs(R[gi, i]).max() > 0 and i not in eigen.IDX7]
+            Dg = L[np.ix_(cols, gi)] @ A2 @ R[np.ix_(gi, cols)]
+            assert np.allclose(Dg, np.diag([1.7, -1.7]), atol=1e-14)
+
+
+def _blast_state(n=6, d=2, seed=2000):
+    s = dg.DG(dg.Mesh.uniform(3, n), d)
+    w = s.project(dg.conserved_field(wl.Blast(seed), G, 9))
+    return s, w
+
+
+def test_slope_limiter_keeps_means_and_untriggered_cells():
+    s, w = _blast_state()
+    w2, tr = limiters.slope_limit(s, w, ch=2.0)
+    assert tr.any() and not tr.all()
+    mean_cols = [v * s.n for v in range(9)]
+    assert np.array_equal(w2[:, mean_cols], w[:, mean_cols])
+    assert np.array_equal(w2[~tr], w[~tr])
+    hi = [v * s.n + l for v in range(9) for l in range(4, s.n)]
+    assert np.all(w2[np.ix_(tr, hi)] == 0.0)
+
+
+def test_slope_limiter_leaves_smooth_state_alone_with_large_threshold():
+    s = dg.DG(dg.Mesh.uniform(2, 16), 2)
+    w = s.project(dg.conserved_field(wl.Smooth(3, 2), G, 9))
+    w2, tr = limiters.slope_limit(s, w, Mtilde=1e6, ch=2.0)
+    assert not tr.any() and np.array_equal(w, w2)
+
+
+def test_componentwise_mode_is_identity_eigensystem():
+    s, w = _blast_state(n=5)
+    w_c, tr_c = limiters.slope_limit(s, w, characteristic=False)
+    # recompute by hand with L = R = I on one triggered cell
+    c = int(np.argmax(tr_c))
+    assert tr_c[c]
+    n = s.n
+    for a in range(3):
+        up, dn = s.mesh.neighbor(a, 1)[c], s.mesh.neighbor(a, -1)[c]
+        means = s.cell_means(w)
+        for v in range(9):
+            slope = w[c, v * n + 1 + a]
+            sig = limiters.tvb_sigma(np.array([slope]), np.array([0.5 * (means[v, up] - means[v, c])]),
+                                     np.array([0.5 * (means[v, c] - means[v, dn])]), 5.0, s.mesh.h[c], 2.0)[0]
+            trig_dir = any(abs(limiters.tvb_sigma(
+                np.array([w[c, vv * n + 1 + a]]), np.array([0.5 * (means[vv, up] - means[vv, c])]),
+                np.array([0.5 * (means[vv, c] - means[vv, dn])]), 5.0, s.mesh.h[c], 2.0)[0] - w[c, vv * n + 1 + a])
+                > 1e-8 for vv in range(9))
+            want = sig if (trig_dir and abs(sig - slope) > 1e-8) else slope
+            assert w_c[c, v * n + 1 + a] == pytest.approx(want, abs=1e-15)
+
+
+def test_positivity_limiter_invariants():
+    s, w = _blast_state(n=6, d=3)
+    # make some points negative: sharpen the IC
+    w = w.copy()
+    hi = [4 * s.n + l for l in range(1, s.n)]
+    w[:, hi] *= 3.0
+    pts0 = np.concatenate(s.all_point_states(w), axis=2)
+    assert (ph.pressure(pts0, G) < 0).any()
+    w2, st = limiters.positivity(s, w)
+    assert st["n_pos_scaled"] > 0 and st["n_floor"] == 0
+    pts = np.concatenate(s.all_point_states(w2), axis=2)
+    assert pts[ph.RHO].min() >= 1e-12 * (1 - 1e-9)
+    assert ph.pressure(pts, G).min() >= -1e-13
+    mean_cols = [v * s.n for v in range(9)]
+    assert np.array_equal(w2[:, mean_cols], w[:, mean_cols])
+    # tau = 1 cells are bitwise unchanged
+    ok = (ph.pressure(pts0, G).min(axis=1) >= 1e-12) & (pts0[ph.RHO].min(axis=1) >= 1e-12)
+    assert ok.any()
+    assert np.array_equal(w2[ok], w[ok])
+
+
+def test_positivity_floors_tally():
+    s = dg.DG(dg.Mesh.uniform(2, 4), 1)
+    w = s.project(dg.conserved_field(wl.Smooth(4, 2), G, 9))
+    w[3, 0] = -0.5           # negative mean density (at rest, so only the density floor fires)
+    w[3, [s.n, 2 * s.n, 3 * s.n]] = 0.0
+    w[5, 4 * s.n] = 0.0      # zero total energy -> negative mean pressure
+    w2, st = limiters.positivity(s, w)
+    assert st["n_floor"] == 2
+    assert st["injected_mass"] == pytest.approx((1e-12 + 0.5) * s.mesh.h[3] ** 2)
+    assert st["injected_energy"] > 0
+    Ub = s.cell_means(w2)
+    assert Ub[0].min() >= 1e-12 and ph.pressure(Ub, G).min() >= 1e-12 * (1 - 1e-6)
+
+
+def test_ldf_divergence_fix_invariants():
+    rng = np.random.default_rng(9)
+    for _ in range(50):
+        S = rng.normal(size=(3, 3))
+        S2 = limiters.ldf_divfree_fix(S)
+        assert abs(np.trace(S2)) < 1e-14 * np.abs(S).max()
+        assert np.all(np.abs(np.diag(S2)) <= np.abs(np.diag(S)) + 1e-15)
+        off = ~np.eye(3, dtype=bool)
+        assert np.array_equal(S2[off], S[off])
+        # the untouched sign class keeps its slopes exactly
+        d, d2 = np.diag(S), np.diag(S2)
+        if np.trace(S) > 0:
+            assert np.array_equal(d2[d <= 0], d[d <= 0])
+        else:
+            assert np.array_equal(d2[d >= 0], d[d >= 0])
+
+
+def test_ldf_projection_of_divfree_linear_field_is_exact():
+    s = dg.DG(dg.Mesh.uniform(3, 2), 2, divb=dg.POWELL)
+    rng = np.random.default_rng(10)
+    S = limiters.ldf_divfree_fix(rng.normal(size=(3, 3)))
+    Bm = rng.normal(size=3)
+    wl_ = limiters.ldf_project_linear(s, Bm, S)
+    from oracle import basis as Bb
+    degs = np.array(Bb.ldf_degrees(3, 2))
+    assert np.abs(wl_[degs >= 2]).max() < 1e-14   # no higher-degree contamination
+    xq, _ = tensor_rule(4, 3)
+    Phi = Bb.ldf_values(3, 2, xq)
+    Bq = np.einsum("cpl,l->cp", Phi, wl_)
+    assert np.allclose(Bq, Bm[:, None] + S @ xq.T, atol=1e-13)
