@@ -20,7 +20,8 @@ the smallest of (rho_bar - eps)/(rho_bar - rho_q) over points with
 rho_q < eps and (p_bar - eps)/(p_bar - p_q) over points with p_q < eps,
 over all volume and face quadrature points.  Reading: p_q only counts where
 rho_q > 0; a second pass is made if the first one leaves any point below
-the floors.
+half the floors (rounding at the floor level after the first pass is not
+re-limited).
 """
 import numpy as np
 
@@ -151,17 +152,21 @@ def positivity(s, w, eps_rho=1e-12, eps_p=1e-12):
         for l, dgl in enumerate(degs):
             if dgl == 0:
                 keep[o + l] = True
-    for _ in range(2):
+    for npass in range(2):
         pts = np.concatenate(s.all_point_states(out), axis=2)  # [var, C, P]
         rq = pts[ph.RHO]
         with np.errstate(divide="ignore", invalid="ignore"):
             pq = ph.pressure(pts, g)
         tau = np.ones(C)
         rb = Ub[ph.RHO][:, None]
-        m = rq < eps_rho
+        # the second pass acts on points below half the floors only: after the
+        # first pass, values at the floor carry rounding from the cancellation
+        # in E - m^2/(2 rho) - B^2/2 and must not decide anything
+        f = 1.0 if npass == 0 else 0.5
+        m = rq < eps_rho * f
         with np.errstate(divide="ignore", invalid="ignore"):
             tr = np.where(m, (rb - eps_rho) / (rb - rq), 1.0)
-            mp = (rq > 0) & (pq < eps_p)
+            mp = (rq > 0) & (pq < eps_p * f)
             tp = np.where(mp, (pb[:, None] - eps_p) / (pb[:, None] - pq), 1.0)
         tau = np.minimum(tau, np.minimum(tr.min(axis=1), tp.min(axis=1)))
         sel = tau < 1.0

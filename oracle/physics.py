@@ -57,15 +57,21 @@ def flux(U, a, gamma, glm=False, ch=0.0):
 
 
 def signal_speed_sum(U, gamma, D):
-    """sum_a (|v_a| + c) with c = sqrt(c_s^2 + c_A^2) (Sec. 3.6, eq. cfl)."""
+    """sum_a (|v_a| + c) with c = sqrt(c_s^2 + c_A^2) (Sec. 3.6, eq. cfl).
+
+    Reading for states that the positivity limiter has not yet seen (an
+    unlimited initial projection): the sound speed uses max(p, 0) and points
+    with rho <= 0 do not contribute."""
     rho = U[RHO]
-    p = pressure(U, gamma)
+    ok = rho > 0.0
+    rs = np.where(ok, rho, 1.0)
+    p = np.maximum(pressure(np.where(ok, U, 1.0), gamma), 0.0)
     bsq = U[B1] ** 2 + U[B2] ** 2 + U[B3] ** 2
-    c = np.sqrt((gamma * p + bsq) / rho)
+    c = np.sqrt((gamma * p + bsq) / rs)
     s = np.zeros_like(rho)
     for a in range(D):
-        s = s + np.abs(U[M1 + a] / rho) + c
-    return s
+        s = s + np.abs(U[M1 + a] / rs) + c
+    return np.where(ok, s, 0.0)
 
 
 def face_normal_field(bnL, rhoL, bnR, rhoR):

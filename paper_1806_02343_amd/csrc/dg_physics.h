@@ -46,11 +46,14 @@ __device__ __forceinline__ void mhd_flux(const T* u, int a, double gamma, T ch2,
   }
 }
 
-// sum_a (|v_a| + c), c = sqrt(gamma p / rho + B^2 / rho), over the first D axes.
+// sum_a (|v_a| + c), c = sqrt(gamma p / rho + B^2 / rho), over the first D
+// axes; max(p, 0) in the sound speed and no contribution where rho <= 0 (a
+// state that the positivity limiter has not seen yet).
 template <typename T, int D>
 __device__ __forceinline__ double signal_sum(const T* u, double gamma) {
   double r = (double)u[0];
-  double p = pressure64(u, gamma);
+  if (!(r > 0.0)) return (r == r) ? 0.0 : r;
+  double p = fmax(pressure64(u, gamma), 0.0);
   double b2 = (double)u[5] * (double)u[5] + (double)u[6] * (double)u[6] + (double)u[7] * (double)u[7];
   double c = sqrt((gamma * p + b2) / r);
   double s = 0.0;

@@ -43,14 +43,18 @@ def rel_l1(orc, w_test, w_ref, ch=1.0):
     return out
 
 
-def block_rel_max(a, b, orc):
-    """max |a-b| / max |b| per variable block (modal arrays [cell][mode])."""
+def block_rel_max(a, b, orc, floor=1e-3):
+    """max |a-b| / max |b| per variable block (modal arrays [cell][mode]).
+    The denominator is floored at `floor` x the largest block maximum, so a
+    block that is zero in exact arithmetic (e.g. momentum of a state at rest)
+    is judged against the state's scale instead of its own rounding noise."""
     res = []
     n = orc.n
+    gmax = max(np.abs(b).max(), 1e-300)
     for j in range(len(orc.leg_vars)):
         sl = slice(j * n, (j + 1) * n)
-        res.append(np.abs(a[:, sl] - b[:, sl]).max() / max(np.abs(b[:, sl]).max(), 1e-300))
+        res.append(np.abs(a[:, sl] - b[:, sl]).max() / max(np.abs(b[:, sl]).max(), floor * gmax))
     if orc.nldf:
         sl = slice(len(orc.leg_vars) * n, None)
-        res.append(np.abs(a[:, sl] - b[:, sl]).max() / max(np.abs(b[:, sl]).max(), 1e-300))
+        res.append(np.abs(a[:, sl] - b[:, sl]).max() / max(np.abs(b[:, sl]).max(), floor * gmax))
     return np.array(res)
