@@ -26,6 +26,8 @@ WORKLOADS = {
     "cfg1": (3, 2, 64, 1, 0, 1, "3-D periodic 64^3, degree 2, Powell scheme with the LDF basis for B, "
                                  "smooth seeded IC (random Fourier modes, B = curl A), SSP-RK3, CFL 0.3"),
     "cfg0": (2, 1, 32, 0, 0, 0, "2-D periodic 32^2, degree 1, GLM, smooth seeded IC, SSP-RK3, CFL 0.3"),
+    "cfg2": (3, 3, 128, 0, 7, 2, "3-D periodic 128^3, degree 3, GLM, 8 seeded over-pressured spheres, "
+                                  "characteristic TVB + positivity limiters, SSP-RK3, CFL 0.3"),
 }
 
 
@@ -77,6 +79,7 @@ def main():
         gpu.project_field(field, w0)
         if limiter:
             gpu.limit(w0)
+        variant = gpu.autotune(w0)
         w = w0.clone()
         gpu.step(w, args.warmup)
         w.copy_(w0)
@@ -91,15 +94,18 @@ def main():
         wall = time.perf_counter() - t0
         ms = e0.elapsed_time(e1)
         ndof = gpu.nmodes * gpu.ncells
-        results[prec] = dict(ms=ms, wall=wall, ndof=ndof, value=ndof * 3 * args.steps / (ms / 1e3), gpu=gpu)
+        results[prec] = dict(ms=ms, wall=wall, ndof=ndof, value=ndof * 3 * args.steps / (ms / 1e3), gpu=gpu,
+                             variant=variant)
         states[prec] = w
         # kernel timings (mean ms per launch)
         results[prec]["k_face"] = gpu.time_kernel(w0, 0, 5)
         results[prec]["k_cell"] = gpu.time_kernel(w0, 1, 5)
         results[prec]["k_dt"] = gpu.time_kernel(w0, 2, 5)
+        results[prec]["k_limit"] = gpu.time_kernel(w0, 3, 5) if limiter else 0.0
         print(f"# prec={'fp64' if prec == 0 else 'fp32'} ms/step={ms / args.steps:.3f} "
               f"face={results[prec]['k_face']:.3f}ms cell={results[prec]['k_cell']:.3f}ms "
-              f"dt={results[prec]['k_dt']:.3f}ms", file=sys.stderr, flush=True)
+              f"dt={results[prec]['k_dt']:.3f}ms limit={results[prec]['k_limit']:.3f}ms variant={variant}",
+              file=sys.stderr, flush=True)
 
     r64 = results[0]
     gpu = r64["gpu"]

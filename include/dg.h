@@ -161,6 +161,16 @@ int dg_set_mlp(dg_handle h, const void* w_bf16, const float* b /*[host]*/, int32
  * only the handle's workspaces.  Synchronous. */
 int dg_time_kernel(dg_handle h, const void* w, int32_t which, int32_t reps, double* ms /*[host]*/);
 
+/* Tile-shape autotuner of the cell kernel (cells per block x threads per
+ * block).  *variant >= 0 forces that variant (DG_EINVAL if it is not built
+ * for this configuration); *variant < 0 times every built variant on the
+ * state w (read only; the handle's workspaces are written) and keeps the
+ * fastest.  cache_path (may be NULL): a JSON file of earlier choices keyed by
+ * precision, dimension, degree, divergence scheme and cell count; an entry
+ * found there is used without timing and new choices are appended.  On
+ * return *variant holds the variant in use.  Synchronous. */
+int dg_autotune(dg_handle h, const void* w, const char* cache_path, int32_t* variant /*[host] in/out*/);
+
 const char* dg_last_error(dg_handle h);
 void dg_destroy(dg_handle h);
 

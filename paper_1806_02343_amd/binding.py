@@ -12,7 +12,7 @@ DG_LIM_TVB, DG_LIM_CHAR, DG_LIM_POS, DG_LIM_LEARNED = 1, 2, 4, 8
 DG_MESH_UNIFORM, DG_MESH_OCTREE = 0, 1
 
 EXPORTS = ["dg_init", "dg_layout", "dg_proj_points", "dg_project", "dg_dt", "dg_rhs", "dg_limit", "dg_step",
-           "dg_set_mlp", "dg_time_kernel", "dg_last_error", "dg_destroy"]
+           "dg_set_mlp", "dg_time_kernel", "dg_autotune", "dg_last_error", "dg_destroy"]
 
 
 class dg_params(ctypes.Structure):
@@ -66,6 +66,7 @@ def load_library(path=LIB_PATH):
     lib.dg_step.argtypes = [P, P, I32, ctypes.POINTER(D)]
     lib.dg_set_mlp.argtypes = [P, P, ctypes.POINTER(ctypes.c_float), I32]
     lib.dg_time_kernel.argtypes = [P, P, I32, I32, ctypes.POINTER(D)]
+    lib.dg_autotune.argtypes = [P, P, ctypes.c_char_p, ctypes.POINTER(I32)]
     lib.dg_last_error.argtypes = [P]
     lib.dg_last_error.restype = ctypes.c_char_p
     lib.dg_destroy.argtypes = [P]
@@ -174,6 +175,13 @@ class DG:
         ms = ctypes.c_double()
         self._check(self.lib.dg_time_kernel(self.h, _ptr(w), which, reps, ctypes.byref(ms)))
         return ms.value
+
+    def autotune(self, w, variant=-1, cache_path=None):
+        """Pick (variant < 0) or force the cell-kernel tile variant; returns it."""
+        v = ctypes.c_int32(variant)
+        cp = cache_path.encode() if cache_path else None
+        self._check(self.lib.dg_autotune(self.h, _ptr(w), cp, ctypes.byref(v)))
+        return v.value
 
     def step_async(self, w, nsteps=1):
         self._check(self.lib.dg_step(self.h, _ptr(w), nsteps, None))

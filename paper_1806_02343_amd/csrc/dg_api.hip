@@ -4,8 +4,11 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <new>
+#include <sstream>
 #include <string>
 
 #include "../../include/dg.h"
@@ -284,6 +287,87 @@ int dg_time_kernel(dg_handle h, const void* w, int32_t which, int32_t reps, doub
   if (rc == DG_OK) rc = check_launch(h, "time_kernel");
   *ms = (double)t / reps;
   return rc;
+}
+
+static std::string tune_key(dg_handle h) {
+  std::ostringstream k;
+  k << "cell/p" << h->p.precision << "/D" << h->p.dim << "/d" << h->p.degree << "/b" << h->p.divb << "/C" << h->g.C;
+  return k.str();
+}
+
+// Minimal JSON object of "key": integer pairs, one per line.
+static bool tune_cache_lookup(const char* path, const std::string& key, int& v) {
+  std::ifstream f(path);
+  if (!f) return false;
+  std::string line, want = "\"" + key + "\"";
+  while (std::getline(f, line)) {
+    size_t p = line.find(want);
+    if (p == std::string::npos) continue;
+    size_t c = line.find(':', p + want.size());
+    if (c == std::string::npos) continue;
+    v = std::atoi(line.c_str() + c + 1);
+    return true;
+  }
+  return false;
+}
+
+static void tune_cache_store(const char* path, const std::string& key, int v, double ms) {
+  std::vector<std::string> entries;
+  {
+    std::ifstream f(path);
+    std::string line;
+    while (f && std::getline(f, line)) {
+      size_t q = line.find('"');
+      if (q == std::string::npos || line.find(':') == std::string::npos) continue;
+      if (line.find("\"" + key + "\"") != std::string::npos) continue;
+      std::string e = line.substr(q);
+      while (!e.empty() && (e.back() == ',' || e.back() == ' ' || e.back() == '\r')) e.pop_back();
+      entries.push_back(e);
+    }
+  }
+  std::ostringstream e;
+  e << "\"" << key << "\": " << v;
+  entries.push_back(e.str());
+  std::ofstream o(path, std::ios::trunc);
+  o << "{\n";
+  for (size_t i = 0; i < entries.size(); ++i) o << "  " << entries[i] << (i + 1 < entries.size() ? ",\n" : "\n");
+  o << "}\n";
+  (void)ms;
+}
+
+int dg_autotune(dg_handle h, const void* w, const char* cache_path, int32_t* variant) {
+  if (int r = valid_state(h, w)) return r;
+  if (!variant) return fail(h, DG_EINVAL, "null variant");
+  Launcher* L = h->L;
+  if (*variant >= 0) {
+    if (*variant >= L->cell_variant_count() || !L->cell_variant_valid(*variant))
+      return fail(h, DG_EINVAL, "cell variant not built for this configuration");
+    L->set_cell_variant(*variant);
+    return DG_OK;
+  }
+  const std::string key = tune_key(h);
+  int cached = -1;
+  if (cache_path && tune_cache_lookup(cache_path, key, cached) && cached >= 0 && cached < L->cell_variant_count() &&
+      L->cell_variant_valid(cached)) {
+    L->set_cell_variant(cached);
+    *variant = cached;
+    return DG_OK;
+  }
+  int best = -1;
+  double best_ms = 1e300;
+  for (int v = 0; v < L->cell_variant_count(); ++v) {
+    if (!L->cell_variant_valid(v)) continue;
+    L->set_cell_variant(v);
+    double ms = 0.0;
+    if (int r = dg_time_kernel(h, w, 1, 1, &ms)) return r;  // warm-up
+    if (int r = dg_time_kernel(h, w, 1, 3, &ms)) return r;
+    if (ms < best_ms) { best_ms = ms; best = v; }
+  }
+  if (best < 0) return fail(h, DG_EUNSUPPORTED, "no cell variant built");
+  L->set_cell_variant(best);
+  *variant = best;
+  if (cache_path) tune_cache_store(cache_path, key, best, best_ms);
+  return DG_OK;
 }
 
 const char* dg_last_error(dg_handle h) { return h ? h->err.c_str() : g_err.c_str(); }

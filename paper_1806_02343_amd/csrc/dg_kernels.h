@@ -49,6 +49,11 @@ struct Launcher {
   // mode 0: out = M^-1 R;  mode 1: out = a0 w0 + b0 (w + dt M^-1 R)
   virtual void cell(const void* w, const void* w0, void* out, const void* ff, const void* jp, const Grid& g,
                     const Scal* sc, const SchemeParams& sp, double a0, double b0, int mode, hipStream_t s) = 0;
+  // tile-shape variants of the cell kernel (autotuner)
+  virtual int cell_variant_count() const = 0;
+  virtual bool cell_variant_valid(int v) const = 0;
+  virtual void set_cell_variant(int v) = 0;
+  virtual int get_cell_variant() const = 0;
   // per-cell signal speeds -> atomic maxima in sc
   virtual void maxsig(const void* w, const Grid& g, Scal* sc, const SchemeParams& sp, hipStream_t s) = 0;
   // Powell dt cap: per-face normal-field jumps then per-cell rate

@@ -81,44 +81,79 @@ __device__ __forceinline__ void atomic_max_pos(unsigned long long* addr, double 
 // face kernel
 
 template <typename T, int D, int DEG, int DIVB>
-__global__ void __launch_bounds__(256) k_face(const T* __restrict__ w, T* __restrict__ ff, T* __restrict__ jp,
-                                              DevTab<T> tb, Grid g, const Scal* __restrict__ sc, double gamma) {
+__device__ __forceinline__ T safe_mode_value(int m) {
   using C = Cfg<D, DEG, DIVB>;
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t total = (int64_t)D * C::FP * g.C;
-  if (gid >= total) return;
-  const int64_t f = gid % g.C;
-  const int64_t t = gid / g.C;
-  const int r = (int)(t % C::FP);
-  const int a = (int)(t / C::FP);
-  const int64_t L = f, R = nbr(f, a, +1, g);
+  return (m == 0 || m == 4 * C::N) ? T(1) : T(0);
+}
+
+// Face tile: TF consecutive faces of one axis (left cells f0 .. f0+TF-1) per
+// block; the modes of the TF left and TF right cells are staged in LDS with
+// coalesced loads, then each thread evaluates one (face, point) pair.
+template <typename T, int D, int DEG, int DIVB>
+struct FaceTile {
+  using C = Cfg<D, DEG, DIVB>;
+  static constexpr int R = 256 / C::FP;
+  static constexpr int TF = R >= 64 ? 64 : R >= 32 ? 32 : R >= 16 ? 16 : 8;
+  static constexpr int NT = TF * C::FP;
+};
+
+template <typename T, int D, int DEG, int DIVB>
+__global__ void __launch_bounds__((FaceTile<T, D, DEG, DIVB>::NT))
+    k_face(const T* __restrict__ w, T* __restrict__ ff, T* __restrict__ jp, DevTab<T> tb, Grid g,
+           const Scal* __restrict__ sc, double gamma) {
+  using C = Cfg<D, DEG, DIVB>;
+  constexpr int TF = FaceTile<T, D, DEG, DIVB>::TF, NT = FaceTile<T, D, DEG, DIVB>::NT;
+  constexpr int NM = C::NMODES, N = C::N;
+  __shared__ T sL[NM * TF];
+  __shared__ T sR[NM * TF];
+  const int a = blockIdx.y;
+  const int64_t f0 = (int64_t)blockIdx.x * TF;
+  const int tid = threadIdx.x;
   const int64_t ld = g.ld;
+  for (int i = tid; i < NM * TF; i += NT) {
+    const int m = i / TF, fl = i % TF;
+    const int64_t F = f0 + fl;
+    if (F < g.C) {
+      sL[i] = w[(int64_t)m * ld + F];
+      sR[i] = w[(int64_t)m * ld + nbr(F, a, +1, g)];
+    } else {
+      sL[i] = safe_mode_value<T, D, DEG, DIVB>(m);
+      sR[i] = safe_mode_value<T, D, DEG, DIVB>(m);
+    }
+  }
+  __syncthreads();
+  const int fl = tid % TF, r = tid / TF;
+  const int64_t f = f0 + fl;
+  if (f >= g.C) return;
   T uL[9], uR[9];
-  const T* tl = tb.TF + ((a * 2 + 1) * C::FP + r) * C::N;
-  const T* tr = tb.TF + ((a * 2 + 0) * C::FP + r) * C::N;
+  const T* tl = tb.TF + ((a * 2 + 1) * C::FP + r) * N;
+  const T* tr = tb.TF + ((a * 2 + 0) * C::FP + r) * N;
+  T rowL[N], rowR[N];
+#pragma unroll
+  for (int l = 0; l < N; ++l) { rowL[l] = tl[l]; rowR[l] = tr[l]; }
 #pragma unroll
   for (int j = 0; j < C::NLEG; ++j) {
-    T sL = 0, sR = 0;
+    T sLv = 0, sRv = 0;
 #pragma unroll
-    for (int l = 0; l < C::N; ++l) {
-      sL += tl[l] * w[(int64_t)(j * C::N + l) * ld + L];
-      sR += tr[l] * w[(int64_t)(j * C::N + l) * ld + R];
+    for (int l = 0; l < N; ++l) {
+      sLv += rowL[l] * sL[(j * N + l) * TF + fl];
+      sRv += rowR[l] * sR[(j * N + l) * TF + fl];
     }
-    uL[C::legvar(j)] = sL;
-    uR[C::legvar(j)] = sR;
+    uL[C::legvar(j)] = sLv;
+    uR[C::legvar(j)] = sRv;
   }
   if constexpr (C::NLDF > 0) {
 #pragma unroll
     for (int c = 0; c < D; ++c) {
       const T* pl = tb.PTF + (((a * 2 + 1) * D + c) * C::FP + r) * C::NLDF;
       const T* pr = tb.PTF + (((a * 2 + 0) * D + c) * C::FP + r) * C::NLDF;
-      T sL = 0, sR = 0;
+      T sLv = 0, sRv = 0;
       for (int l = 0; l < C::NLDF; ++l) {
-        sL += pl[l] * w[(int64_t)(C::NLEG * C::N + l) * ld + L];
-        sR += pr[l] * w[(int64_t)(C::NLEG * C::N + l) * ld + R];
+        sLv += pl[l] * sL[(C::NLEG * N + l) * TF + fl];
+        sRv += pr[l] * sR[(C::NLEG * N + l) * TF + fl];
       }
-      uL[5 + c] = sL;
-      uR[5 + c] = sR;
+      uL[5 + c] = sLv;
+      uR[5 + c] = sRv;
     }
   }
   T F[9];
@@ -134,36 +169,55 @@ __global__ void __launch_bounds__(256) k_face(const T* __restrict__ w, T* __rest
 // ---------------------------------------------------------------------------
 // cell kernel
 
-template <typename T, int D, int DEG, int DIVB>
-__device__ __forceinline__ T safe_mode_value(int m) {
-  using C = Cfg<D, DEG, DIVB>;
-  return (m == 0 || m == 4 * C::N) ? T(1) : T(0);
-}
 
-template <typename T, int D, int DEG, int DIVB>
-__global__ void __launch_bounds__((Tile<T, D, DEG, DIVB>::NT))
-    k_cell(const T* w, const T* w0, T* out, const T* __restrict__ ff, const T* __restrict__ jp, DevTab<T> tb,
-           Grid g, const Scal* __restrict__ sc, double gamma, double a0, double b0, int mode) {
+// Tile shape of the cell kernel: TC cells per block, NT threads.  The flux
+// phase gives every thread one (cell, point) pair of a chunk of QCH = NT/TC
+// points; the contraction phases give every thread IPT items, an item being
+// one (Legendre variable or LDF chunk, cell) with N register accumulators.
+template <typename T, int D, int DEG, int DIVB, int TC, int NT>
+struct CellTile {
   using C = Cfg<D, DEG, DIVB>;
-  using TL = Tile<T, D, DEG, DIVB>;
-  constexpr int NT = TL::NT, TC = TL::TC, QCH = TL::QCH;
-  constexpr int NOUT = C::NMODES * TC;
-  constexpr int NACC = (NOUT + NT - 1) / NT;
-  __shared__ T sw[C::NMODES * TC];
+  static constexpr int QCH = NT / TC;
+  static constexpr int NLC = C::NLDF ? (C::NLDF + C::N - 1) / C::N : 0;  // LDF chunks of N modes
+  static constexpr int NBLK = C::NLEG + NLC;
+  static constexpr int NITEM = NBLK * TC;
+  static constexpr int IPT = (NITEM + NT - 1) / NT;
+  static constexpr int LDS = (C::NMODES * TC + D * C::NV * QCH * TC) * (int)sizeof(T);
+  static constexpr bool valid = (NT % TC == 0) && (QCH >= 1) && (LDS <= 160 * 1024) && (IPT <= 4);
+};
+
+template <typename T, int D, int DEG, int DIVB, int TC, int NT>
+__global__ void __launch_bounds__(NT)
+    k_cell(const T* w, const T* w0, T* out, const T* __restrict__ ff, const T* __restrict__ jp,
+           const T* __restrict__ tV, const T* __restrict__ tGW, const T* __restrict__ tLF,
+           const T* __restrict__ tMinv, const T* __restrict__ tPV, const T* __restrict__ tPGW,
+           const T* __restrict__ tPLF, const T* __restrict__ tPmean, Grid g, const Scal* __restrict__ sc,
+           double gamma, double a0, double b0, int mode) {
+  using C = Cfg<D, DEG, DIVB>;
+  using CT = CellTile<T, D, DEG, DIVB, TC, NT>;
+  // tables as restrict-qualified arguments: wave-uniform reads become scalar loads
+  struct {
+    const T *V, *GW, *LF, *Minv, *PV, *PGW, *PLF, *Pmean;
+  } tb = {tV, tGW, tLF, tMinv, tPV, tPGW, tPLF, tPmean};
+  constexpr int N = C::N, QCH = CT::QCH, IPT = CT::IPT, NITEM = CT::NITEM;
+  constexpr int NM = C::NMODES;
+  __shared__ T sw[NM * TC];
   __shared__ T sf[D * C::NV * QCH * TC];
   const int64_t c0 = (int64_t)blockIdx.x * TC;
   const int tid = threadIdx.x;
   const int64_t ld = g.ld;
-  for (int i = tid; i < NOUT; i += NT) {
+  for (int i = tid; i < NM * TC; i += NT) {
     const int m = i / TC, c = i % TC;
     const int64_t K = c0 + c;
     sw[i] = K < g.C ? w[(int64_t)m * ld + K] : safe_mode_value<T, D, DEG, DIVB>(m);
   }
   const T ch = (T)sc->ch;
   const T ch2 = ch * ch;
-  T acc[NACC];
+  T acc[IPT][N];
 #pragma unroll
-  for (int k = 0; k < NACC; ++k) acc[k] = 0;
+  for (int k = 0; k < IPT; ++k)
+#pragma unroll
+    for (int l = 0; l < N; ++l) acc[k][l] = 0;
 
   for (int qb = 0; qb < C::Q; qb += QCH) {
     __syncthreads();
@@ -171,18 +225,21 @@ __global__ void __launch_bounds__((Tile<T, D, DEG, DIVB>::NT))
       const int c = tid % TC, qq = tid / TC, q = qb + qq;
       if (q < C::Q) {
         T u[9];
+        T vrow[N];
+#pragma unroll
+        for (int l = 0; l < N; ++l) vrow[l] = tb.V[q * N + l];
 #pragma unroll
         for (int j = 0; j < C::NLEG; ++j) {
           T s = 0;
 #pragma unroll
-          for (int l = 0; l < C::N; ++l) s += tb.V[q * C::N + l] * sw[(j * C::N + l) * TC + c];
+          for (int l = 0; l < N; ++l) s += vrow[l] * sw[(j * N + l) * TC + c];
           u[C::legvar(j)] = s;
         }
         if constexpr (C::NLDF > 0) {
 #pragma unroll
           for (int cc = 0; cc < D; ++cc) {
             T s = 0;
-            for (int l = 0; l < C::NLDF; ++l) s += tb.PV[(cc * C::Q + q) * C::NLDF + l] * sw[(C::NLEG * C::N + l) * TC + c];
+            for (int l = 0; l < C::NLDF; ++l) s += tb.PV[(cc * C::Q + q) * C::NLDF + l] * sw[(C::NLEG * N + l) * TC + c];
             u[5 + cc] = s;
           }
         }
@@ -198,25 +255,30 @@ __global__ void __launch_bounds__((Tile<T, D, DEG, DIVB>::NT))
     __syncthreads();
     const int qmax = (C::Q - qb) < QCH ? (C::Q - qb) : QCH;
 #pragma unroll
-    for (int k = 0; k < NACC; ++k) {
-      const int o = tid + k * NT;
-      if (o < NOUT) {
-        const int m = o / TC, c = o % TC;
-        T s = acc[k];
-        if (m < C::NLEG * C::N) {
-          const int j = m / C::N, l = m % C::N, v = C::legvar(j);
-          for (int a = 0; a < D; ++a)
-            for (int qq = 0; qq < qmax; ++qq)
-              s += tb.GW[(a * C::Q + qb + qq) * C::N + l] * sf[((a * C::NV + v) * QCH + qq) * TC + c];
-        } else {
-          const int l = m - C::NLEG * C::N;
-          for (int a = 0; a < D; ++a)
-            for (int cc = 0; cc < D; ++cc)
-              for (int qq = 0; qq < qmax; ++qq)
-                s += tb.PGW[((a * D + cc) * C::Q + qb + qq) * C::NLDF + l] *
-                     sf[((a * C::NV + 5 + cc) * QCH + qq) * TC + c];
-        }
-        acc[k] = s;
+    for (int k = 0; k < IPT; ++k) {
+      const int it = tid + k * NT;
+      if (it >= NITEM) continue;
+      const int blk = it / TC, c = it % TC;
+      if (blk < C::NLEG) {
+        const int v = C::legvar(blk);
+        for (int a = 0; a < D; ++a)
+          for (int qq = 0; qq < qmax; ++qq) {
+            const T f = sf[((a * C::NV + v) * QCH + qq) * TC + c];
+            const T* gw = tb.GW + (a * C::Q + qb + qq) * N;
+#pragma unroll
+            for (int l = 0; l < N; ++l) acc[k][l] += gw[l] * f;
+          }
+      } else if constexpr (C::NLDF > 0) {
+        const int h = blk - C::NLEG;
+        for (int a = 0; a < D; ++a)
+          for (int cc = 0; cc < D; ++cc)
+            for (int qq = 0; qq < qmax; ++qq) {
+              const T f = sf[((a * C::NV + 5 + cc) * QCH + qq) * TC + c];
+              const T* pg = tb.PGW + ((a * D + cc) * C::Q + qb + qq) * C::NLDF + h * N;
+#pragma unroll
+              for (int i = 0; i < N; ++i)
+                if (h * N + i < C::NLDF) acc[k][i] += pg[i] * f;
+            }
       }
     }
   }
@@ -225,86 +287,89 @@ __global__ void __launch_bounds__((Tile<T, D, DEG, DIVB>::NT))
   const T kappa = (T)sc->kappa;
   const T two_h = T(2.0 / g.h);
 #pragma unroll
-  for (int k = 0; k < NACC; ++k) {
-    const int o = tid + k * NT;
-    if (o >= NOUT) continue;
-    const int m = o / TC, c = o % TC;
+  for (int k = 0; k < IPT; ++k) {
+    const int it = tid + k * NT;
+    if (it >= NITEM) continue;
+    const int blk = it / TC, c = it % TC;
     const int64_t K = c0 + c;
     if (K >= g.C) continue;
-    T s = acc[k];
-    // cell-average state for the Powell term
     T qv[8];
     if constexpr (DIVB == POWELL) {
+      // q(<u>_K) = (0, B, v.B, v) from the cell means (eq. powellq-average)
       const T rho = sw[0 * TC + c];
       T bm[3];
       for (int cc = 0; cc < D; ++cc) {
         T b = 0;
-        for (int l = 0; l < C::NLDF; ++l) b += tb.Pmean[cc * C::NLDF + l] * sw[(C::NLEG * C::N + l) * TC + c];
+        for (int l = 0; l < C::NLDF; ++l) b += tb.Pmean[cc * C::NLDF + l] * sw[(C::NLEG * N + l) * TC + c];
         bm[cc] = b;
       }
-      if (D == 2) bm[2] = sw[(5 * C::N) * TC + c];
-      const T v0 = sw[(1 * C::N) * TC + c] / rho, v1 = sw[(2 * C::N) * TC + c] / rho, v2 = sw[(3 * C::N) * TC + c] / rho;
+      if (D == 2) bm[2] = sw[(5 * N) * TC + c];
+      const T v0 = sw[(1 * N) * TC + c] / rho, v1 = sw[(2 * N) * TC + c] / rho, v2 = sw[(3 * N) * TC + c] / rho;
       qv[0] = 0; qv[1] = bm[0]; qv[2] = bm[1]; qv[3] = bm[2];
       qv[4] = v0 * bm[0] + v1 * bm[1] + v2 * bm[2];
       qv[5] = v0; qv[6] = v1; qv[7] = v2;
     }
     for (int a = 0; a < D; ++a) {
       const int64_t Km = nbr(K, a, -1, g);
-      if (m < C::NLEG * C::N) {
-        const int j = m / C::N, l = m % C::N, v = C::legvar(j);
+      const T* jl = jp + (int64_t)(a * 2 + 0) * C::FP * ld;
+      const T* jr = jp + (int64_t)(a * 2 + 1) * C::FP * ld;
+      if (blk < C::NLEG) {
+        const int v = C::legvar(blk);
         const T* fv = ff + (int64_t)(a * C::NV + v) * C::FP * ld;
-        T sp = 0, sm = 0;
         for (int r = 0; r < C::FP; ++r) {
-          sp += tb.LF[((a * 2 + 1) * C::FP + r) * C::N + l] * fv[(int64_t)r * ld + K];
-          sm += tb.LF[((a * 2 + 0) * C::FP + r) * C::N + l] * fv[(int64_t)r * ld + Km];
-        }
-        s += sm - sp;
-        if constexpr (DIVB == POWELL) {
-          T pp = 0, pm = 0;
-          const T* jl = jp + (int64_t)(a * 2 + 0) * C::FP * ld;
-          const T* jr = jp + (int64_t)(a * 2 + 1) * C::FP * ld;
-          for (int r = 0; r < C::FP; ++r) {
-            pp += tb.LF[((a * 2 + 1) * C::FP + r) * C::N + l] * jl[(int64_t)r * ld + K];
-            pm += tb.LF[((a * 2 + 0) * C::FP + r) * C::N + l] * jr[(int64_t)r * ld + Km];
+          const T fp = fv[(int64_t)r * ld + K], fm = fv[(int64_t)r * ld + Km];
+          const T* lfp = tb.LF + ((a * 2 + 1) * C::FP + r) * N;
+          const T* lfm = tb.LF + ((a * 2 + 0) * C::FP + r) * N;
+#pragma unroll
+          for (int l = 0; l < N; ++l) acc[k][l] += lfm[l] * fm - lfp[l] * fp;
+          if constexpr (DIVB == POWELL) {
+            const T ql = qv[v] * jl[(int64_t)r * ld + K], qr = qv[v] * jr[(int64_t)r * ld + Km];
+#pragma unroll
+            for (int l = 0; l < N; ++l) acc[k][l] -= lfp[l] * ql + lfm[l] * qr;
           }
-          s -= qv[v] * (pp + pm);
         }
-      } else {
-        const int l = m - C::NLEG * C::N;
+      } else if constexpr (C::NLDF > 0) {
+        const int h = blk - C::NLEG;
         for (int cc = 0; cc < D; ++cc) {
           const T* fv = ff + (int64_t)(a * C::NV + 5 + cc) * C::FP * ld;
-          T sp = 0, sm = 0;
           for (int r = 0; r < C::FP; ++r) {
-            sp += tb.PLF[(((a * 2 + 1) * D + cc) * C::FP + r) * C::NLDF + l] * fv[(int64_t)r * ld + K];
-            sm += tb.PLF[(((a * 2 + 0) * D + cc) * C::FP + r) * C::NLDF + l] * fv[(int64_t)r * ld + Km];
-          }
-          s += sm - sp;
-          if constexpr (DIVB == POWELL) {
-            T pp = 0, pm = 0;
-            const T* jl = jp + (int64_t)(a * 2 + 0) * C::FP * ld;
-            const T* jr = jp + (int64_t)(a * 2 + 1) * C::FP * ld;
-            for (int r = 0; r < C::FP; ++r) {
-              pp += tb.PLF[(((a * 2 + 1) * D + cc) * C::FP + r) * C::NLDF + l] * jl[(int64_t)r * ld + K];
-              pm += tb.PLF[(((a * 2 + 0) * D + cc) * C::FP + r) * C::NLDF + l] * jr[(int64_t)r * ld + Km];
-            }
-            s -= qv[5 + cc] * (pp + pm);
+            const T fp = fv[(int64_t)r * ld + K], fm = fv[(int64_t)r * ld + Km];
+            const T* pp = tb.PLF + (((a * 2 + 1) * D + cc) * C::FP + r) * C::NLDF + h * N;
+            const T* pm = tb.PLF + (((a * 2 + 0) * D + cc) * C::FP + r) * C::NLDF + h * N;
+            const T ql = qv[5 + cc] * jl[(int64_t)r * ld + K], qr = qv[5 + cc] * jr[(int64_t)r * ld + Km];
+#pragma unroll
+            for (int i = 0; i < N; ++i)
+              if (h * N + i < C::NLDF) acc[k][i] += pm[i] * fm - pp[i] * fp - (pp[i] * ql + pm[i] * qr);
           }
         }
       }
     }
-    T dw = s * two_h * tb.Minv[m];
-    const T wm = sw[m * TC + c];
-    if constexpr (DIVB == GLM) {
-      if (m >= 8 * C::N) dw -= kappa * wm;
-    }
-    if (mode == 0) {
-      out[(int64_t)m * ld + K] = dw;
-    } else {
-      const T base = w0[(int64_t)m * ld + K];
-      out[(int64_t)m * ld + K] = (T)a0 * base + (T)b0 * (wm + (T)dt * dw);
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      const int m = blk < C::NLEG ? blk * N + l : C::NLEG * N + (blk - C::NLEG) * N + l;
+      if (m >= NM) continue;
+      T dw = acc[k][l] * two_h * tb.Minv[m];
+      const T wm = sw[m * TC + c];
+      if constexpr (DIVB == GLM) {
+        if (m >= 8 * N) dw -= kappa * wm;
+      }
+      if (mode == 0) {
+        out[(int64_t)m * ld + K] = dw;
+      } else {
+        const T base = w0[(int64_t)m * ld + K];
+        out[(int64_t)m * ld + K] = (T)a0 * base + (T)b0 * (wm + (T)dt * dw);
+      }
     }
   }
 }
+
+// tile-shape variants of the cell kernel offered to the autotuner
+template <typename T, int D, int DEG, int DIVB>
+struct CellVariants {
+  static constexpr int count = 4;
+  static constexpr int tc(int i) { return i == 0 ? 16 : i == 1 ? 32 : i == 2 ? 32 : 64; }
+  static constexpr int nt(int i) { return i == 0 ? 256 : i == 1 ? 256 : i == 2 ? 512 : 512; }
+};
 
 // ---------------------------------------------------------------------------
 // max signal speed over volume and face points (eq. cfl; reading: max over
@@ -599,15 +664,51 @@ struct LauncherImpl : Launcher {
 
   void face(const void* w, void* ff, void* jp, const Grid& g, const Scal* sc, const SchemeParams& sp,
             hipStream_t s) override {
-    const int64_t total = (int64_t)D * C::FP * g.C;
-    const int nb = (int)((total + 255) / 256);
-    k_face<T, D, DEG, DIVB><<<nb, 256, 0, s>>>((const T*)w, (T*)ff, (T*)jp, tb, g, sc, sp.gamma);
+    using FT = FaceTile<T, D, DEG, DIVB>;
+    dim3 grid((unsigned)((g.C + FT::TF - 1) / FT::TF), D);
+    k_face<T, D, DEG, DIVB><<<grid, FT::NT, 0, s>>>((const T*)w, (T*)ff, (T*)jp, tb, g, sc, sp.gamma);
   }
+  int cell_variant = -1;  // -1: default
+
+  template <int V>
+  bool launch_cell_v(const void* w, const void* w0, void* out, const void* ff, const void* jp, const Grid& g,
+                     const Scal* sc, const SchemeParams& sp, double a0, double b0, int mode, hipStream_t s) {
+    constexpr int TC = CellVariants<T, D, DEG, DIVB>::tc(V), NT = CellVariants<T, D, DEG, DIVB>::nt(V);
+    if constexpr (CellTile<T, D, DEG, DIVB, TC, NT>::valid) {
+      const int nb = (int)((g.C + TC - 1) / TC);
+      k_cell<T, D, DEG, DIVB, TC, NT><<<nb, NT, 0, s>>>((const T*)w, (const T*)w0, (T*)out, (const T*)ff,
+                                                        (const T*)jp, tb.V, tb.GW, tb.LF, tb.Minv, tb.PV, tb.PGW,
+                                                        tb.PLF, tb.Pmean, g, sc, sp.gamma, a0, b0, mode);
+      return true;
+    } else {
+      return false;
+    }
+  }
+  bool cell_variant_valid(int v) const override {
+    switch (v) {
+      case 0: return CellTile<T, D, DEG, DIVB, CellVariants<T, D, DEG, DIVB>::tc(0), CellVariants<T, D, DEG, DIVB>::nt(0)>::valid;
+      case 1: return CellTile<T, D, DEG, DIVB, CellVariants<T, D, DEG, DIVB>::tc(1), CellVariants<T, D, DEG, DIVB>::nt(1)>::valid;
+      case 2: return CellTile<T, D, DEG, DIVB, CellVariants<T, D, DEG, DIVB>::tc(2), CellVariants<T, D, DEG, DIVB>::nt(2)>::valid;
+      case 3: return CellTile<T, D, DEG, DIVB, CellVariants<T, D, DEG, DIVB>::tc(3), CellVariants<T, D, DEG, DIVB>::nt(3)>::valid;
+      default: return false;
+    }
+  }
+  int cell_variant_count() const override { return CellVariants<T, D, DEG, DIVB>::count; }
+  void set_cell_variant(int v) override { cell_variant = v; }
+  int get_cell_variant() const override { return cell_variant; }
   void cell(const void* w, const void* w0, void* out, const void* ff, const void* jp, const Grid& g, const Scal* sc,
             const SchemeParams& sp, double a0, double b0, int mode, hipStream_t s) override {
-    const int nb = (int)((g.C + TL::TC - 1) / TL::TC);
-    k_cell<T, D, DEG, DIVB><<<nb, TL::NT, 0, s>>>((const T*)w, (const T*)w0, (T*)out, (const T*)ff, (const T*)jp, tb,
-                                                   g, sc, sp.gamma, a0, b0, mode);
+    int v = cell_variant;
+    if (v < 0 || !cell_variant_valid(v)) {
+      v = 0;
+      while (v < 4 && !cell_variant_valid(v)) ++v;
+    }
+    switch (v) {
+      case 0: launch_cell_v<0>(w, w0, out, ff, jp, g, sc, sp, a0, b0, mode, s); break;
+      case 1: launch_cell_v<1>(w, w0, out, ff, jp, g, sc, sp, a0, b0, mode, s); break;
+      case 2: launch_cell_v<2>(w, w0, out, ff, jp, g, sc, sp, a0, b0, mode, s); break;
+      default: launch_cell_v<3>(w, w0, out, ff, jp, g, sc, sp, a0, b0, mode, s); break;
+    }
   }
   void maxsig(const void* w, const Grid& g, Scal* sc, const SchemeParams& sp, hipStream_t s) override {
     const int nb = (int)((g.C + TL::TC - 1) / TL::TC);

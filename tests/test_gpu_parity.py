@@ -126,3 +126,29 @@ def test_step_is_deterministic():
     gpu.step(wg, 2)
     gpu.step(w2, 2)
     assert torch.equal(wg, w2)
+
+
+@pytest.mark.parametrize("case", [(3, 2, 6, dg.GLM), (3, 3, 5, dg.GLM), (3, 2, 6, dg.POWELL), (2, 2, 12, dg.GLM)],
+                         ids=ids)
+def test_every_cell_tile_variant_matches_oracle(case):
+    """Each tile shape the autotuner may pick gives the same right-hand side."""
+    D, d, n, divb = case
+    _announce("variants", case)
+    gpu, wg, orc, wo = make_pair(D, d, n, divb)
+    dt, ch, kappa = orc.timestep(wo)
+    r_o = orc.rhs(wo, ch, kappa)
+    ran = 0
+    for v in range(4):
+        try:
+            gpu.autotune(wg, variant=v)
+        except Exception:
+            continue
+        out = gpu.empty_state()
+        gpu.rhs(wg, out, ch, kappa)
+        torch.cuda.synchronize()
+        err = block_rel_max(to_cells(out, orc.mesh.ncells), r_o, orc)
+        assert np.all(err < 1e-12), (v, err)
+        ran += 1
+    assert ran >= 2
+    chosen = gpu.autotune(wg)
+    assert 0 <= chosen < 4
