@@ -90,7 +90,9 @@ class DG:
 
     def __init__(self, dim, degree, n, box=1.0, divb=DG_GLM, precision=DG_FP64, limiter=0, gamma=5.0 / 3.0,
                  cfl=0.3, cfl_glm=0.0, glm_cr=0.18, glm_ch_fixed=0.0, tvb_Mtilde=5.0, tvb_beta=2.0, tvb_eps=1e-8,
-                 eps_rho=1e-12, eps_p=1e-12, powell_eta=0.2, mlp_lo=0.0, mlp_hi=0.0, stream=None):
+                 eps_rho=1e-12, eps_p=1e-12, powell_eta=0.2, mlp_lo=0.0, mlp_hi=0.0, stream=None, octree=None):
+        """octree: optional (level[int8, C], ijk[int32, C x 3]) leaves on the level
+        grids of the base grid n (kind DG_MESH_OCTREE)."""
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -101,7 +103,16 @@ class DG:
         bb = list(box) if hasattr(box, "__len__") else [box] * dim
         nn += [1] * (3 - len(nn))
         bb += [1.0] * (3 - len(bb))
-        m = dg_mesh(DG_MESH_UNIFORM, (ctypes.c_int32 * 3)(*nn), (ctypes.c_double * 3)(*bb), 0, None, None)
+        if octree is None:
+            m = dg_mesh(DG_MESH_UNIFORM, (ctypes.c_int32 * 3)(*nn), (ctypes.c_double * 3)(*bb), 0, None, None)
+            self.level = self.ijk = None
+        else:
+            import numpy as np
+            self.level = np.ascontiguousarray(octree[0], dtype=np.int8)
+            self.ijk = np.ascontiguousarray(octree[1], dtype=np.int32).reshape(-1, 3)
+            m = dg_mesh(DG_MESH_OCTREE, (ctypes.c_int32 * 3)(*nn), (ctypes.c_double * 3)(*bb), len(self.level),
+                        self.level.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
+                        self.ijk.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
         self.n, self.box = nn[:dim], bb[:dim]
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
@@ -187,8 +198,14 @@ class DG:
         self._check(self.lib.dg_step(self.h, _ptr(w), nsteps, None))
 
     def cell_centers(self, c0, nc):
-        """Centres of uniform-grid cells c0 .. c0+nc-1 (index i + n0 (j + n1 k))."""
+        """Centres and sizes of cells c0 .. c0+nc-1 (uniform: index i + n0 (j + n1 k);
+        octree: the leaves given at construction)."""
         torch = self.torch
+        if self.level is not None:
+            lv = torch.as_tensor(self.level[c0:c0 + nc].astype("int64"), device="cuda")
+            ijk = torch.as_tensor(self.ijk[c0:c0 + nc, :self.dim].astype("float64"), device="cuda")
+            h = (self.box[0] / self.n[0]) / (2.0 ** lv.to(torch.float64))
+            return (ijk + 0.5) * h[:, None], h[:, None, None]
         idx = torch.arange(c0, c0 + nc, device="cuda", dtype=torch.int64)
         h = self.box[0] / self.n[0]
         cols, stride = [], 1
@@ -206,7 +223,7 @@ class DG:
         for c0 in range(0, self.ncells, chunk):
             nc = min(chunk, self.ncells - c0)
             ctr, h = self.cell_centers(c0, nc)
-            x = (ctr[:, None, :] + 0.5 * h * xi[None, :, :]).reshape(-1, self.dim)
+            x = (ctr[:, None, :] + 0.5 * h * xi[None, :, :]).reshape(-1, self.dim)  # h: scalar or [nc,1,1]
             pr = field(x)
             comps = [pr["rho"], pr["v"][0], pr["v"][1], pr["v"][2], pr["p"], pr["B"][0], pr["B"][1], pr["B"][2],
                      pr["psi"]]

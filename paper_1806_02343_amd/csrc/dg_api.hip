@@ -10,6 +10,8 @@
 #include <new>
 #include <sstream>
 #include <string>
+#include <unordered_map>
+#include <vector>
 
 #include "../../include/dg.h"
 #include "dg_kernels.h"
@@ -30,6 +32,9 @@ struct dg_handle_s {
   void* jsum = nullptr;   // Powell per-face jump integrals
   void* lscr = nullptr;   // limiter scratch
   Scal* sc = nullptr;     // device scalars
+  std::vector<void*> mesh_bufs;  // octree face lists on the device
+  std::vector<int8_t> h_level;   // octree: host copy of the leaf levels
+  std::vector<int32_t> h_ijk;    // octree: host copy of the leaf coordinates
   double hmin = 0.0;
   size_t elem = 8;
   std::string err;
@@ -59,6 +64,131 @@ int valid_state(dg_handle h, const void* w) {
 
 }  // namespace
 
+// Face lists of a periodic 2:1 octree (Sec. 4.4).  Faces are enumerated once,
+// from the left cell's +a side, sorted by axis: same level (both full), a
+// finer right region (one face per fine neighbour, the coarse left side on
+// quarter q), or a coarser right cell (the coarse side on quarter q), q
+// having bit t set when the fine face is in the upper half of the t-th
+// tangential axis.  Returns an error message or "".
+static std::string build_octree(dg_handle h, const dg_mesh* m) {
+  const int D = h->p.dim;
+  const int64_t C = m->nleaves;
+  if (C <= 0 || !m->level || !m->ijk) return "octree: leaves missing";
+  const int NQ = 1 << (D - 1);
+  std::vector<int8_t> lev(m->level, m->level + C);
+  std::vector<int32_t> ijk(m->ijk, m->ijk + 3 * C);
+  int lmax = 0;
+  for (int64_t c = 0; c < C; ++c) {
+    if (lev[c] < 0 || lev[c] > 20) return "octree: level out of range";
+    lmax = std::max(lmax, (int)lev[c]);
+  }
+  auto key = [](int l, int64_t i, int64_t j, int64_t k) -> uint64_t {
+    return ((uint64_t)l << 60) | ((uint64_t)i << 40) | ((uint64_t)j << 20) | (uint64_t)k;
+  };
+  std::unordered_map<uint64_t, int32_t> idx;
+  idx.reserve((size_t)C * 2);
+  for (int64_t c = 0; c < C; ++c) {
+    const int l = lev[c];
+    for (int a = 0; a < 3; ++a) {
+      const int64_t n = a < D ? ((int64_t)m->n[a] << l) : 1;
+      if (ijk[3 * c + a] < 0 || ijk[3 * c + a] >= n) return "octree: coordinate outside the level grid";
+    }
+    if (!idx.emplace(key(l, ijk[3 * c], ijk[3 * c + 1], ijk[3 * c + 2]), (int32_t)c).second)
+      return "octree: duplicate leaf";
+  }
+  auto find = [&](int l, int64_t* c) -> int32_t {
+    if (l < 0) return -1;
+    int64_t w[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) {
+      const int64_t n = (int64_t)m->n[a] << l;
+      w[a] = ((c[a] % n) + n) % n;
+    }
+    auto it = idx.find(key(l, w[0], w[1], w[2]));
+    return it == idx.end() ? -1 : it->second;
+  };
+  std::vector<int32_t> fL, fR;
+  std::vector<int8_t> sL, sR;
+  int64_t face0[4] = {0, 0, 0, 0};
+  for (int a = 0; a < D; ++a) {
+    face0[a] = (int64_t)fL.size();
+    int tang[2], nt = 0;
+    for (int b = 0; b < D; ++b)
+      if (b != a) tang[nt++] = b;
+    for (int64_t c = 0; c < C; ++c) {
+      const int l = lev[c];
+      int64_t nc[3] = {ijk[3 * c], ijk[3 * c + 1], ijk[3 * c + 2]};
+      nc[a] += 1;
+      int32_t r = find(l, nc);
+      if (r >= 0) { fL.push_back((int32_t)c); fR.push_back(r); sL.push_back(-1); sR.push_back(-1); continue; }
+      int64_t pc[3] = {0, 0, 0};
+      for (int b = 0; b < D; ++b) {
+        const int64_t n = (int64_t)m->n[b] << l;
+        pc[b] = (((nc[b] % n) + n) % n) >> 1;
+      }
+      r = l > 0 ? find(l - 1, pc) : -1;
+      if (r >= 0) {
+        int q = 0;
+        for (int t = 0; t < nt; ++t) q |= (int)(ijk[3 * c + tang[t]] & 1) << t;
+        fL.push_back((int32_t)c); fR.push_back(r); sL.push_back(-1); sR.push_back((int8_t)q);
+        continue;
+      }
+      for (int q = 0; q < NQ; ++q) {
+        int64_t ch[3] = {0, 0, 0};
+        for (int b = 0; b < D; ++b) {
+          const int64_t n = (int64_t)m->n[b] << l;
+          ch[b] = 2 * (((nc[b] % n) + n) % n);
+        }
+        for (int t = 0; t < nt; ++t) ch[tang[t]] += (q >> t) & 1;
+        r = find(l + 1, ch);
+        if (r < 0) return "octree: leaves do not tile the box or are not 2:1 balanced";
+        fL.push_back((int32_t)c); fR.push_back(r); sL.push_back((int8_t)q); sR.push_back(-1);
+      }
+    }
+  }
+  face0[D] = (int64_t)fL.size();
+  const int64_t NF = (int64_t)fL.size();
+  // side slots and coverage check
+  std::vector<int32_t> slots((size_t)C * D * 2 * 4, -1);
+  std::vector<int> cnt((size_t)C * D * 2, 0), full((size_t)C * D * 2, 0);
+  for (int a = 0; a < D; ++a)
+    for (int64_t f = face0[a]; f < face0[a + 1]; ++f) {
+      const size_t kl = ((size_t)fL[f] * D + a) * 2 + 1, kr = ((size_t)fR[f] * D + a) * 2 + 0;
+      if (cnt[kl] >= 4 || cnt[kr] >= 4) return "octree: too many faces on a cell side";
+      slots[kl * 4 + cnt[kl]++] = (int32_t)f;
+      slots[kr * 4 + cnt[kr]++] = (int32_t)f;
+      full[kl] += sL[f] < 0;
+      full[kr] += sR[f] < 0;
+    }
+  for (size_t k = 0; k < cnt.size(); ++k) {
+    const bool ok = (cnt[k] == 1 && full[k] == 1) || (cnt[k] == NQ && full[k] == 0);
+    if (!ok) return "octree: a cell side is not covered by one full face or 2^(D-1) quarter faces";
+  }
+  // upload
+  auto up = [&](const void* src, size_t bytes) -> void* {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    h->mesh_bufs.push_back(p);
+    if (hipMemcpy(p, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+    return p;
+  };
+  Grid& g = h->g;
+  g.level = (const int8_t*)up(lev.data(), lev.size());
+  g.faceL = (const int32_t*)up(fL.data(), fL.size() * 4);
+  g.faceR = (const int32_t*)up(fR.data(), fR.size() * 4);
+  g.subL = (const int8_t*)up(sL.data(), sL.size());
+  g.subR = (const int8_t*)up(sR.data(), sR.size());
+  g.slots = (const int32_t*)up(slots.data(), slots.size() * 4);
+  if (!g.level || !g.faceL || !g.faceR || !g.subL || !g.subR || !g.slots) return "octree: device allocation";
+  g.NF = NF;
+  g.ldf = (NF + 63) / 64 * 64;
+  for (int a = 0; a <= 3; ++a) g.face0[a] = a <= D ? face0[a] : NF;
+  g.hbase = m->box[0] / m->n[0];
+  h->hmin = g.hbase / (double)(1 << lmax);
+  h->h_level = lev;
+  h->h_ijk = ijk;
+  return "";
+}
+
 extern "C" {
 
 int dg_init(const dg_params* p, const dg_mesh* m, void* hip_stream, dg_handle* out) {
@@ -71,7 +201,13 @@ int dg_init(const dg_params* p, const dg_mesh* m, void* hip_stream, dg_handle* o
   if (p->precision != DG_FP64 && p->precision != DG_FP32) return fail(nullptr, DG_EINVAL, "unknown precision");
   if (p->rk_stages != 3) return fail(nullptr, DG_EUNSUPPORTED, "only SSP-RK3 (rk_stages = 3)");
   if (!(p->gamma > 1.0) || !(p->cfl > 0.0) || !(p->cfl < 1.0)) return fail(nullptr, DG_EINVAL, "gamma/cfl");
-  if (m->kind != DG_MESH_UNIFORM) return fail(nullptr, DG_EUNSUPPORTED, "octree meshes not built yet");
+  if (m->kind != DG_MESH_UNIFORM && m->kind != DG_MESH_OCTREE) return fail(nullptr, DG_EINVAL, "unknown mesh kind");
+  if (m->kind == DG_MESH_OCTREE) {
+    if (p->divb != DG_GLM) return fail(nullptr, DG_EUNSUPPORTED, "octree meshes are built for GLM cleaning");
+    if (p->limiter) return fail(nullptr, DG_EUNSUPPORTED, "limiters on octree meshes not built");
+    if (!(p->glm_ch_fixed > 0.0)) return fail(nullptr, DG_EINVAL, "octree meshes need a fixed c_h (glm_ch_fixed)");
+    if (m->nleaves <= 0 || !m->level || !m->ijk) return fail(nullptr, DG_EINVAL, "octree leaves missing");
+  }
   if (p->limiter & ~(DG_LIM_TVB | DG_LIM_CHAR | DG_LIM_POS | DG_LIM_LEARNED))
     return fail(nullptr, DG_EINVAL, "unknown limiter flags");
   if ((p->limiter & DG_LIM_TVB) && p->divb == DG_POWELL)
@@ -94,10 +230,14 @@ int dg_init(const dg_params* p, const dg_mesh* m, void* hip_stream, dg_handle* o
   g.n0 = m->n[0];
   g.n1 = m->n[1];
   g.n2 = p->dim == 3 ? m->n[2] : 1;
-  g.C = (int64_t)g.n0 * g.n1 * g.n2;
+  g.C = m->kind == DG_MESH_OCTREE ? m->nleaves : (int64_t)g.n0 * g.n1 * g.n2;
   g.ld = (g.C + 63) / 64 * 64;
   g.h = m->box[0] / m->n[0];
   h->hmin = g.h;
+  if (m->kind == DG_MESH_OCTREE) {
+    std::string e = build_octree(h, m);
+    if (!e.empty()) { g_err = e; for (void* q : h->mesh_bufs) (void)hipFree(q); delete h; return DG_EINVAL; }
+  }
   SchemeParams& sp = h->sp;
   sp.gamma = p->gamma;
   sp.cfl = p->cfl;
@@ -381,6 +521,7 @@ void dg_destroy(dg_handle h) {
   if (h->S1) (void)hipFree(h->S1);
   if (h->lscr) (void)hipFree(h->lscr);
   if (h->sc) (void)hipFree(h->sc);
+  for (void* q : h->mesh_bufs) (void)hipFree(q);
   delete h;
 }
 

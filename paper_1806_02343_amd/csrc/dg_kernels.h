@@ -28,6 +28,16 @@ struct Grid {
   int64_t C;        // number of cells
   int64_t ld;       // leading dimension of state arrays
   double h;         // cell size (uniform grids)
+  // octree meshes (level == nullptr on uniform grids)
+  const int8_t* level;     // [C] refinement level of each leaf
+  double hbase;            // level-0 cell size
+  const int32_t* faceL;    // [NF] left cell of each face (faces sorted by axis)
+  const int32_t* faceR;    // [NF] right cell
+  const int8_t* subL;      // [NF] quarter of the left cell's +a face (-1: full face)
+  const int8_t* subR;      // [NF] quarter of the right cell's -a face (-1: full face)
+  const int32_t* slots;    // [C][D][2][4] faces touching each cell side (side 1: +a), -1 = none
+  int64_t NF, ldf;         // number of faces, leading dimension of face arrays
+  int64_t face0[4];        // first face of each axis; face0[D] = NF
 };
 
 struct SchemeParams {

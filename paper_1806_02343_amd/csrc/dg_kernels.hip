@@ -56,8 +56,12 @@ struct Tile {
 
 template <typename T>
 struct DevTab {
-  const T *V, *GW, *TF, *LF, *Minv, *PV, *PGW, *PTF, *PLF, *Pmean, *Plin;
+  const T *V, *GW, *TF, *LF, *Minv, *PV, *PGW, *PTF, *PLF, *Pmean, *Plin, *TFS, *LFS;
 };
+
+__device__ __forceinline__ double cell_h(const Grid& g, int64_t K) {
+  return g.level ? g.hbase / (double)(1 << g.level[K]) : g.h;
+}
 
 __device__ __forceinline__ int64_t nbr(int64_t K, int a, int s, const Grid& g) {
   int64_t i = K % g.n0;
@@ -166,6 +170,44 @@ __global__ void __launch_bounds__((FaceTile<T, D, DEG, DIVB>::NT))
   }
 }
 
+// Face kernel on octree meshes: one thread per (face, point) over the face
+// list (sorted by axis); a coarse side evaluates its trace at the points of
+// its quarter of the face (L2 prolongation of the coarse trace).
+template <typename T, int D, int DEG>
+__global__ void __launch_bounds__(256) k_face_amr(const T* __restrict__ w, T* __restrict__ ffa, DevTab<T> tb,
+                                                  Grid g, const Scal* __restrict__ sc, double gamma) {
+  using C = Cfg<D, DEG, GLM>;
+  constexpr int N = C::N, NSUB = 1 + (1 << (D - 1));
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)C::FP * g.NF) return;
+  const int64_t f = gid % g.NF;
+  const int r = (int)(gid / g.NF);
+  int a = 0;
+  if (D == 3 && f >= g.face0[2]) a = 2;
+  else if (f >= g.face0[1]) a = 1;
+  const int64_t L = g.faceL[f], R = g.faceR[f];
+  const int sl = g.subL[f] + 1, sr = g.subR[f] + 1;
+  const int64_t ld = g.ld;
+  const T* tl = tb.TFS + (((a * 2 + 1) * NSUB + sl) * C::FP + r) * N;
+  const T* tr = tb.TFS + (((a * 2 + 0) * NSUB + sr) * C::FP + r) * N;
+  T uL[9], uR[9];
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    T sLv = 0, sRv = 0;
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      sLv += tl[l] * w[(int64_t)(j * N + l) * ld + L];
+      sRv += tr[l] * w[(int64_t)(j * N + l) * ld + R];
+    }
+    uL[j] = sLv;
+    uR[j] = sRv;
+  }
+  T F[9];
+  (void)face_flux<T, 9>(uL, uR, a, gamma, (T)sc->ch, F);
+#pragma unroll
+  for (int v = 0; v < 9; ++v) ffa[((int64_t)v * C::FP + r) * g.ldf + f] = F[v];
+}
+
 // ---------------------------------------------------------------------------
 // cell kernel
 
@@ -186,13 +228,13 @@ struct CellTile {
   static constexpr bool valid = (NT % TC == 0) && (QCH >= 1) && (LDS <= 160 * 1024) && (IPT <= 4);
 };
 
-template <typename T, int D, int DEG, int DIVB, int TC, int NT>
+template <typename T, int D, int DEG, int DIVB, int TC, int NT, int AMR>
 __global__ void __launch_bounds__(NT)
     k_cell(const T* w, const T* w0, T* out, const T* __restrict__ ff, const T* __restrict__ jp,
            const T* __restrict__ tV, const T* __restrict__ tGW, const T* __restrict__ tLF,
            const T* __restrict__ tMinv, const T* __restrict__ tPV, const T* __restrict__ tPGW,
-           const T* __restrict__ tPLF, const T* __restrict__ tPmean, Grid g, const Scal* __restrict__ sc,
-           double gamma, double a0, double b0, int mode) {
+           const T* __restrict__ tPLF, const T* __restrict__ tPmean, const T* __restrict__ tLFS, Grid g,
+           const Scal* __restrict__ sc, double gamma, double a0, double b0, int mode) {
   using C = Cfg<D, DEG, DIVB>;
   using CT = CellTile<T, D, DEG, DIVB, TC, NT>;
   // tables as restrict-qualified arguments: wave-uniform reads become scalar loads
@@ -285,7 +327,6 @@ __global__ void __launch_bounds__(NT)
 
   const double dt = sc->dt;
   const T kappa = (T)sc->kappa;
-  const T two_h = T(2.0 / g.h);
 #pragma unroll
   for (int k = 0; k < IPT; ++k) {
     const int it = tid + k * NT;
@@ -293,6 +334,28 @@ __global__ void __launch_bounds__(NT)
     const int blk = it / TC, c = it % TC;
     const int64_t K = c0 + c;
     if (K >= g.C) continue;
+    const T two_h = T(2.0 / cell_h(g, K));
+    if constexpr (AMR) {
+      // owner gather over the faces of each side (1 full face or 2^(D-1) quarters)
+      constexpr int NSUB = 1 + (1 << (D - 1)), NQ = 1 << (D - 1);
+      const int v = C::legvar(blk);
+      for (int a = 0; a < D; ++a)
+        for (int sd = 0; sd < 2; ++sd) {
+          const int32_t* sl = g.slots + (((int64_t)K * D + a) * 2 + sd) * 4;
+          for (int q = 0; q < NQ; ++q) {
+            const int32_t f = sl[q];
+            if (f < 0) break;
+            const int sub = 1 + (sd ? g.subL[f] : g.subR[f]);
+            const T sign = sd ? T(-1) : T(1);
+            for (int r = 0; r < C::FP; ++r) {
+              const T fv = sign * ff[((int64_t)v * C::FP + r) * g.ldf + f];
+              const T* lf = tLFS + (((a * 2 + sd) * NSUB + sub) * C::FP + r) * N;
+#pragma unroll
+              for (int l = 0; l < N; ++l) acc[k][l] += lf[l] * fv;
+            }
+          }
+        }
+    }
     T qv[8];
     if constexpr (DIVB == POWELL) {
       // q(<u>_K) = (0, B, v.B, v) from the cell means (eq. powellq-average)
@@ -309,7 +372,7 @@ __global__ void __launch_bounds__(NT)
       qv[4] = v0 * bm[0] + v1 * bm[1] + v2 * bm[2];
       qv[5] = v0; qv[6] = v1; qv[7] = v2;
     }
-    for (int a = 0; a < D; ++a) {
+    for (int a = 0; a < (AMR ? 0 : D); ++a) {
       const int64_t Km = nbr(K, a, -1, g);
       const T* jl = jp + (int64_t)(a * 2 + 0) * C::FP * ld;
       const T* jr = jp + (int64_t)(a * 2 + 1) * C::FP * ld;
@@ -401,7 +464,7 @@ __global__ void __launch_bounds__(256) k_maxsig(const T* __restrict__ w, DevTab<
   constexpr int TC = Tile<T, D, DEG, DIVB>::TC;
   constexpr int NPT = C::Q + 2 * D * C::FP;
   __shared__ T sw[C::NMODES * TC];
-  __shared__ double red[256];
+  __shared__ double red[256], red2[256];
   const int64_t c0 = (int64_t)blockIdx.x * TC;
   const int tid = threadIdx.x;
   for (int i = tid; i < C::NMODES * TC; i += 256) {
@@ -410,10 +473,11 @@ __global__ void __launch_bounds__(256) k_maxsig(const T* __restrict__ w, DevTab<
     sw[i] = K < g.C ? w[(int64_t)m * g.ld + K] : safe_mode_value<T, D, DEG, DIVB>(m);
   }
   __syncthreads();
-  double smax = 0.0;
+  double smax = 0.0, rmax = 0.0;
   for (int i = tid; i < NPT * TC; i += 256) {
     const int c = i % TC, p = i / TC;
     if (c0 + c >= g.C) continue;
+    const double ih = 1.0 / cell_h(g, c0 + c);
     T u[9];
     if (p < C::Q) {
       eval_point<T, D, DEG, DIVB>(sw, TC, c, tb.V + p * C::N, C::NLDF ? tb.PV + p * C::NLDF : nullptr,
@@ -427,19 +491,24 @@ __global__ void __launch_bounds__(256) k_maxsig(const T* __restrict__ w, DevTab<
     double s = signal_sum<T, D>(u, gamma);
     if (!(s == s)) s = __longlong_as_double(0x7ff8000000000000ULL);
     smax = (s > smax || !(s == s)) ? s : smax;
+    const double rt = s * ih;
+    rmax = (rt > rmax || !(rt == rt)) ? rt : rmax;
   }
   red[tid] = smax;
+  red2[tid] = rmax;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
     if (tid < st) {
       double o = red[tid + st];
       if (o > red[tid] || !(o == o)) red[tid] = o;
+      o = red2[tid + st];
+      if (o > red2[tid] || !(o == o)) red2[tid] = o;
     }
     __syncthreads();
   }
   if (tid == 0) {
     atomic_max_pos(&sc->maxsig_bits, red[0]);
-    atomic_max_pos(&sc->maxrate_bits, red[0] / g.h);
+    atomic_max_pos(&sc->maxrate_bits, red2[0]);
     if (!(red[0] == red[0])) atomicAdd(&sc->nonfinite, 1ULL);
   }
 }
@@ -641,7 +710,7 @@ struct LauncherImpl : Launcher {
     hipError_t e;
 #define UP(src, dst) if ((e = up<T>(t.src, tb.dst)) != hipSuccess) return e;
     UP(V, V) UP(GW, GW) UP(TF, TF) UP(LF, LF) UP(Minv, Minv) UP(PV, PV) UP(PGW, PGW) UP(PTF, PTF) UP(PLF, PLF)
-    UP(Pmean, Pmean) UP(Plin, Plin)
+    UP(Pmean, Pmean) UP(Plin, Plin) UP(TFS, TFS) UP(LFS, LFS)
 #undef UP
     const double* d1 = nullptr;
     if ((e = up<double>(t.VPW, d1)) != hipSuccess) return e;
@@ -656,7 +725,9 @@ struct LauncherImpl : Launcher {
     for (void* p : bufs) (void)hipFree(p);
     bufs.clear();
   }
-  size_t face_buffer_elems(const Grid& g) const override { return (size_t)D * C::NV * C::FP * g.ld; }
+  size_t face_buffer_elems(const Grid& g) const override {
+    return g.level ? (size_t)C::NV * C::FP * g.ldf : (size_t)D * C::NV * C::FP * g.ld;
+  }
   size_t jump_buffer_elems(const Grid& g) const override {
     return DIVB == POWELL ? (size_t)D * 2 * C::FP * g.ld : 0;
   }
@@ -664,6 +735,13 @@ struct LauncherImpl : Launcher {
 
   void face(const void* w, void* ff, void* jp, const Grid& g, const Scal* sc, const SchemeParams& sp,
             hipStream_t s) override {
+    if (g.level) {
+      if constexpr (DIVB == GLM) {
+        const int64_t total = (int64_t)C::FP * g.NF;
+        k_face_amr<T, D, DEG><<<(unsigned)((total + 255) / 256), 256, 0, s>>>((const T*)w, (T*)ff, tb, g, sc, sp.gamma);
+      }
+      return;
+    }
     using FT = FaceTile<T, D, DEG, DIVB>;
     dim3 grid((unsigned)((g.C + FT::TF - 1) / FT::TF), D);
     k_face<T, D, DEG, DIVB><<<grid, FT::NT, 0, s>>>((const T*)w, (T*)ff, (T*)jp, tb, g, sc, sp.gamma);
@@ -676,9 +754,16 @@ struct LauncherImpl : Launcher {
     constexpr int TC = CellVariants<T, D, DEG, DIVB>::tc(V), NT = CellVariants<T, D, DEG, DIVB>::nt(V);
     if constexpr (CellTile<T, D, DEG, DIVB, TC, NT>::valid) {
       const int nb = (int)((g.C + TC - 1) / TC);
-      k_cell<T, D, DEG, DIVB, TC, NT><<<nb, NT, 0, s>>>((const T*)w, (const T*)w0, (T*)out, (const T*)ff,
-                                                        (const T*)jp, tb.V, tb.GW, tb.LF, tb.Minv, tb.PV, tb.PGW,
-                                                        tb.PLF, tb.Pmean, g, sc, sp.gamma, a0, b0, mode);
+      if (g.level) {
+        if constexpr (DIVB == GLM)
+          k_cell<T, D, DEG, DIVB, TC, NT, 1><<<nb, NT, 0, s>>>(
+              (const T*)w, (const T*)w0, (T*)out, (const T*)ff, (const T*)jp, tb.V, tb.GW, tb.LF, tb.Minv, tb.PV,
+              tb.PGW, tb.PLF, tb.Pmean, tb.LFS, g, sc, sp.gamma, a0, b0, mode);
+      } else {
+        k_cell<T, D, DEG, DIVB, TC, NT, 0><<<nb, NT, 0, s>>>((const T*)w, (const T*)w0, (T*)out, (const T*)ff,
+                                                             (const T*)jp, tb.V, tb.GW, tb.LF, tb.Minv, tb.PV, tb.PGW,
+                                                             tb.PLF, tb.Pmean, tb.LFS, g, sc, sp.gamma, a0, b0, mode);
+      }
       return true;
     } else {
       return false;

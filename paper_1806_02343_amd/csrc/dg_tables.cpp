@@ -302,6 +302,34 @@ bool build_tables(int D, int d, int divb, Tables& t, std::string& err) {
           t.TF[((a * 2 + s) * FP + r) * N + l] = v;
           t.LF[((a * 2 + s) * FP + r) * N + l] = wf[r] * v;
         }
+  // sub-face tables for 2:1 hanging faces: the points of quarter j of a face
+  // are xi_t = (xi_t^GL + o)/2 with o = -1 / +1 by bit t of j (tangential
+  // axes in increasing order); index 0 is the full face
+  const int NSUB = 1 + (1 << (D - 1));
+  t.TFS.assign(D * 2 * NSUB * FP * N, 0.0);
+  t.LFS.assign(D * 2 * NSUB * FP * N, 0.0);
+  for (int a = 0; a < D; ++a)
+    for (int sd = 0; sd < 2; ++sd)
+      for (int sb = 0; sb < NSUB; ++sb)
+        for (int r = 0; r < FP; ++r) {
+          double xi[3] = {0, 0, 0};
+          xi[a] = sd ? 1.0 : -1.0;
+          int j = 0;
+          for (int b = 0; b < D; ++b) {
+            if (b == a) continue;
+            double x = t.xg[j == 0 ? r % P : r / P];
+            if (sb > 0) x = 0.5 * (x + (((sb - 1) >> j) & 1 ? 1.0 : -1.0));
+            xi[b] = x;
+            ++j;
+          }
+          const double scale = sb > 0 ? std::ldexp(1.0, -(D - 1)) : 1.0;
+          for (int l = 0; l < N; ++l) {
+            const double v = Pl(l, xi);
+            const size_t o = ((((size_t)a * 2 + sd) * NSUB + sb) * FP + r) * N + l;
+            t.TFS[o] = v;
+            t.LFS[o] = scale * wf[r] * v;
+          }
+        }
   // mass
   t.Mass.assign(t.NMODES, 0.0);
   t.Minv.assign(t.NMODES, 0.0);

@@ -27,6 +27,8 @@ struct Tables {
   std::vector<double> GW;              // [D][Q][N]      w_q dP_l/dxi_a (xi_q)
   std::vector<double> TF;              // [D][2][FP][N]  P_l at face points
   std::vector<double> LF;              // [D][2][FP][N]  w_r P_l at face points
+  std::vector<double> TFS;             // [D][2][1+2^(D-1)][FP][N]  P_l at (sub-)face points; sub+1
+  std::vector<double> LFS;             // [D][2][1+2^(D-1)][FP][N]  w_r P_l, times 2^-(D-1) on quarters
   std::vector<double> Minv;            // [NMODES]
   std::vector<double> Mass;            // [NMODES]
   // locally divergence-free basis (Powell)

@@ -243,3 +243,67 @@ def config_field(cfg, replicate=0):
     if cfg == 3:
         return Peaks(seed)
     raise ValueError(cfg)
+
+
+# ---------------------------------------------------------------------------
+# octree leaves of the Gaussian-peak workload (mesh input, no scheme arithmetic)
+
+
+def _morton_keys(level, ijk, lmax):
+    """Z-order keys of leaves (level, ijk[:, 3]) on the finest grid (int64)."""
+    c = ijk.astype(np.int64) << (lmax - level.astype(np.int64))[:, None]
+    key = np.zeros(len(level), dtype=np.int64)
+    for b in range(20):
+        for a in range(3):
+            key |= ((c[:, a] >> b) & 1) << (3 * b + a)
+    return key
+
+
+def _refine(level, ijk, flags):
+    keep_l, keep_c = level[~flags], ijk[~flags]
+    pl, pc = level[flags], ijk[flags]
+    kids_l, kids_c = [], []
+    for off in range(8):
+        o = np.array([(off >> a) & 1 for a in range(3)], dtype=np.int64)
+        kids_l.append(pl + 1)
+        kids_c.append(2 * pc + o)
+    return (np.concatenate([keep_l] + kids_l), np.concatenate([keep_c] + kids_c))
+
+
+def peaks_leaves(peaks, n0=64, r1=0.14, r2=0.10):
+    """Leaves (level[int8], ijk[int32, 3]) of the octree of the Gaussian-peak
+    workload on [0,1]^3: base n0^3 cells refined where the cell centre is
+    within r1 of a peak, their children again within r2; level-0 cells that
+    touch a level-2 cell are refined (2:1 balance across faces); Morton
+    order."""
+    g = np.stack(np.meshgrid(np.arange(n0), np.arange(n0), np.arange(n0), indexing="ij"), -1).reshape(-1, 3)
+    ijk = g[:, ::-1].astype(np.int64)   # x fastest
+    level = np.zeros(len(ijk), dtype=np.int64)
+
+    def centers(l, c):
+        h = 1.0 / (n0 << l)
+        return (c + 0.5) * h[:, None]
+
+    level, ijk = _refine(level, ijk, peaks.refine_flags(centers(level, ijk), r1))
+    f = peaks.refine_flags(centers(level, ijk), r2) & (level == 1)
+    level, ijk = _refine(level, ijk, f)
+    # 2:1 balance: a level-0 leaf must not touch a level-2 leaf
+    for _ in range(4):
+        l2 = ijk[level == 2] // 2          # level-1 parents of level-2 leaves
+        n1 = n0 * 2
+        nb = []
+        for a in range(3):
+            for s in (-1, 1):
+                q = l2.copy()
+                q[:, a] = (q[:, a] + s) % n1
+                nb.append(q)
+        nb = np.unique(np.concatenate(nb) // 2, axis=0)  # level-0 regions adjacent to refined level-1 cells
+        key = lambda c: (c[:, 0] * n0 + c[:, 1]) * n0 + c[:, 2]
+        is0 = level == 0
+        bad = np.zeros(len(level), dtype=bool)
+        bad[is0] = np.isin(key(ijk[is0]), key(nb))
+        if not bad.any():
+            break
+        level, ijk = _refine(level, ijk, bad)
+    order = np.argsort(_morton_keys(level, ijk, int(level.max())), kind="stable")
+    return level[order].astype(np.int8), ijk[order].astype(np.int32)
