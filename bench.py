@@ -73,8 +73,10 @@ def main():
     field = wl.config_field(cfg)
     results = {}
     states = {}
+    stream = torch.cuda.Stream()          # non-null stream: each step replays one captured hipGraph
+    torch.cuda.set_stream(stream)
     for prec in ([0] if args.no_fp32 else [0, 1]):
-        gpu = DG(D, d, n, divb=divb, precision=prec, limiter=limiter, cfl=0.3)
+        gpu = DG(D, d, n, divb=divb, precision=prec, limiter=limiter, cfl=0.3, stream=stream.cuda_stream)
         w0 = gpu.empty_state()
         gpu.project_field(field, w0)
         if limiter:

@@ -33,6 +33,9 @@ struct dg_handle_s {
   void* lscr = nullptr;   // limiter scratch
   Scal* sc = nullptr;     // device scalars
   std::vector<void*> mesh_bufs;  // octree face lists on the device
+  // one captured SSP-RK3 step per state pointer (non-null streams only)
+  hipGraphExec_t graph_exec = nullptr;
+  const void* graph_w = nullptr;
   std::vector<int8_t> h_level;   // octree: host copy of the leaf levels
   std::vector<int32_t> h_ijk;    // octree: host copy of the leaf coordinates
   double hmin = 0.0;
@@ -358,27 +361,66 @@ int dg_limit(dg_handle h, void* w, dg_limit_stats* stats) {
   return DG_OK;
 }
 
+// The launch sequence of one SSP-RK3 step: device time-step reduction, then
+// per stage the face kernel, the cell kernel (stage combination fused) and
+// the limiters.  Kernels only: the sequence can be captured into a graph.
+static void step_sequence(dg_handle h, void* w) {
+  const bool lim = h->p.limiter != 0;
+  launch_reset_step(h->sc, h->stream);
+  h->L->maxsig(w, h->g, h->sc, h->sp, h->stream);
+  if (h->p.divb == DG_POWELL) h->L->powell_cap(w, h->jsum, h->g, h->sc, h->sp, h->stream);
+  launch_finalize_dt(h->sc, h->sp, h->p.dim, h->p.degree, h->p.divb, h->hmin, h->stream);
+  // stage 1: S1 = w + dt L(w)
+  h->L->face(w, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
+  h->L->cell(w, w, h->S1, h->ff, h->jp, h->g, h->sc, h->sp, 0.0, 1.0, 1, h->stream);
+  if (lim) h->L->limit(h->S1, h->lscr, h->g, h->sc, h->sp, h->stream);
+  // stage 2: S1 = 3/4 w + 1/4 (S1 + dt L(S1))
+  h->L->face(h->S1, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
+  h->L->cell(h->S1, w, h->S1, h->ff, h->jp, h->g, h->sc, h->sp, 0.75, 0.25, 1, h->stream);
+  if (lim) h->L->limit(h->S1, h->lscr, h->g, h->sc, h->sp, h->stream);
+  // stage 3: w = 1/3 w + 2/3 (S1 + dt L(S1))
+  h->L->face(h->S1, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
+  h->L->cell(h->S1, w, w, h->ff, h->jp, h->g, h->sc, h->sp, 1.0 / 3.0, 2.0 / 3.0, 1, h->stream);
+  if (lim) h->L->limit(w, h->lscr, h->g, h->sc, h->sp, h->stream);
+}
+
+static void drop_graph(dg_handle h) {
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+  h->graph_exec = nullptr;
+  h->graph_w = nullptr;
+}
+
+// Capture one step for state w on the handle's (non-null) stream.
+static int capture_step(dg_handle h, void* w) {
+  drop_graph(h);
+  hipGraph_t graph = nullptr;
+  if (int r = check_hip(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal), "begin capture")) return r;
+  step_sequence(h, w);
+  hipError_t e = hipStreamEndCapture(h->stream, &graph);
+  if (e != hipSuccess) return check_hip(h, e, "end capture");
+  e = hipGraphInstantiate(&h->graph_exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) { h->graph_exec = nullptr; return check_hip(h, e, "graph instantiate"); }
+  h->graph_w = w;
+  return DG_OK;
+}
+
 int dg_step(dg_handle h, void* w, int32_t nsteps, double* t) {
   if (int r = valid_state(h, w)) return r;
   if (nsteps < 0) return fail(h, DG_EINVAL, "nsteps < 0");
-  const bool lim = h->p.limiter != 0;
   launch_set_time(h->sc, 0.0, h->stream);  // device clock of this call
   launch_reset_stats(h->sc, h->stream);
+  const bool graph = h->stream != nullptr && nsteps > 0;
+  if (graph && (h->graph_w != w || !h->graph_exec)) {
+    if (int r = capture_step(h, w)) return r;
+  }
   for (int32_t n = 0; n < nsteps; ++n) {
-    if (int r = dt_sequence(h, w)) return r;
-    // stage 1: S1 = w + dt L(w)
-    h->L->face(w, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
-    h->L->cell(w, w, h->S1, h->ff, h->jp, h->g, h->sc, h->sp, 0.0, 1.0, 1, h->stream);
-    if (lim) h->L->limit(h->S1, h->lscr, h->g, h->sc, h->sp, h->stream);
-    // stage 2: S1 = 3/4 w + 1/4 (S1 + dt L(S1))
-    h->L->face(h->S1, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
-    h->L->cell(h->S1, w, h->S1, h->ff, h->jp, h->g, h->sc, h->sp, 0.75, 0.25, 1, h->stream);
-    if (lim) h->L->limit(h->S1, h->lscr, h->g, h->sc, h->sp, h->stream);
-    // stage 3: w = 1/3 w + 2/3 (S1 + dt L(S1))
-    h->L->face(h->S1, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
-    h->L->cell(h->S1, w, w, h->ff, h->jp, h->g, h->sc, h->sp, 1.0 / 3.0, 2.0 / 3.0, 1, h->stream);
-    if (lim) h->L->limit(w, h->lscr, h->g, h->sc, h->sp, h->stream);
-    if (int r = check_launch(h, "step")) return r;
+    if (graph) {
+      if (int r = check_hip(h, hipGraphLaunch(h->graph_exec, h->stream), "graph launch")) return r;
+    } else {
+      step_sequence(h, w);
+      if (int r = check_launch(h, "step")) return r;
+    }
   }
   if (t) {
     Scal s;
@@ -483,6 +525,7 @@ int dg_autotune(dg_handle h, const void* w, const char* cache_path, int32_t* var
     if (*variant >= L->cell_variant_count() || !L->cell_variant_valid(*variant))
       return fail(h, DG_EINVAL, "cell variant not built for this configuration");
     L->set_cell_variant(*variant);
+    drop_graph(h);
     return DG_OK;
   }
   const std::string key = tune_key(h);
@@ -490,6 +533,7 @@ int dg_autotune(dg_handle h, const void* w, const char* cache_path, int32_t* var
   if (cache_path && tune_cache_lookup(cache_path, key, cached) && cached >= 0 && cached < L->cell_variant_count() &&
       L->cell_variant_valid(cached)) {
     L->set_cell_variant(cached);
+    drop_graph(h);
     *variant = cached;
     return DG_OK;
   }
@@ -505,6 +549,7 @@ int dg_autotune(dg_handle h, const void* w, const char* cache_path, int32_t* var
   }
   if (best < 0) return fail(h, DG_EUNSUPPORTED, "no cell variant built");
   L->set_cell_variant(best);
+  drop_graph(h);
   *variant = best;
   if (cache_path) tune_cache_store(cache_path, key, best, best_ms);
   return DG_OK;
@@ -514,6 +559,7 @@ const char* dg_last_error(dg_handle h) { return h ? h->err.c_str() : g_err.c_str
 
 void dg_destroy(dg_handle h) {
   if (!h) return;
+  drop_graph(h);
   if (h->L) { h->L->free_tables(); delete h->L; }
   if (h->ff) (void)hipFree(h->ff);
   if (h->jp) (void)hipFree(h->jp);
