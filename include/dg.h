@@ -150,9 +150,54 @@ int dg_limit(dg_handle h, void* w, dg_limit_stats* stats /*[host] or NULL*/);
  * the steps' dt; a non-NULL t synchronises. */
 int dg_step(dg_handle h, void* w, int32_t nsteps, double* t /*[host] in/out*/);
 
-/* Install the learned troubled-cell indicator: w_bf16 device array of BF16
- * weights (layout in dg_mlp_layout), b host FP32 biases. */
-int dg_set_mlp(dg_handle h, const void* w_bf16, const float* b /*[host]*/, int32_t in_dim);
+/* Learned troubled-cell indicator (GLM on uniform grids).  The network maps
+ * 256 features of a cell (its 9 x 20 modal weights and its 6 face
+ * neighbours' mean differences, each divided by s_v = |mean_v| + sigma_v,
+ * zero padded) through 256 -> 64 -> 64 -> 64 -> 1 (GELU, sigmoid) to the
+ * probability that the plain TVB detector (Sec. 4.2) fires.  With
+ * DG_LIM_LEARNED set, dg_limit / dg_step skip the slope limiter on cells with
+ * probability < mlp_lo, use the plain detector on the band [mlp_lo, mlp_hi)
+ * ("fallback") and count cells >= mlp_hi as flagged.  Matrix products run on
+ * BF16 matrix cores with FP32 accumulation; masters and Adam state are FP32.
+ *
+ * Parameters (public FP32 layout, 24833 values): for each layer W[in][out]
+ * row-major then b[out], layers 256x64, 64x64, 64x64, 64x1. */
+
+/* Feature scales from a state (normally the initial one): sigma_v = RMS over
+ * cells of the cell means of variable v, floored at 1e-2 of the largest;
+ * kept in the handle and copied to sigma (host, 9, may be NULL).  Sync. */
+int dg_mlp_scale(dg_handle h, const void* w, double* sigma /*[host] or NULL*/);
+/* Install parameters (params == NULL: W ~ U(+-1/sqrt(in)) from seed, b = 0)
+ * and feature scales (sigma == NULL keeps those of dg_mlp_scale).  Sync. */
+int dg_mlp_set(dg_handle h, const float* params /*[host] or NULL*/, const double* sigma /*[host] 9 or NULL*/,
+               uint64_t seed);
+/* Copy the current parameters to params (host, 24833 floats).  Synchronous. */
+int dg_mlp_get(dg_handle h, float* params /*[host]*/);
+/* Features of every cell of w into X (device BF16 [ncells][256]).  Async. */
+int dg_mlp_features(dg_handle h, const void* w, void* X);
+/* Plain TVB detector decisions of every cell of w into y (device FP32, 1/0),
+ * c_h from the time-step rule of w; w is not modified.  Async. */
+int dg_mlp_labels(dg_handle h, const void* w, float* y);
+/* Record (features, label) pairs of the pre-limiter state of every stage of
+ * later dg_step calls: positives kept with probability q_pos, negatives with
+ * q_neg (counter-based hash of cell, stage and seed), rows appended to X
+ * (device BF16 [cap][256]) and y (device FP32 [cap]) through the device
+ * counter (uint64, caller-cleared; it may exceed cap: rows beyond cap are
+ * dropped).  X == NULL stops recording. */
+int dg_mlp_record(dg_handle h, void* X, float* y, unsigned long long* counter, int64_t cap, double q_pos,
+                  double q_neg, uint64_t seed);
+/* Network output for nrows feature rows (device X BF16 [nrows][256]) into
+ * prob (device FP32 [nrows]).  Async. */
+int dg_mlp_forward(dg_handle h, const void* X, int64_t nrows, float* prob);
+/* Mean binary cross-entropy loss and its gradient w.r.t. the parameters
+ * (public layout, host) for one batch of nrows rows (device X, y).  Sync. */
+int dg_mlp_grad(dg_handle h, const void* X, const float* y, int64_t nrows, float* grads /*[host]*/,
+                float* loss /*[host] or NULL*/);
+/* Adam training (beta 0.9 / 0.999, eps 1e-8) for `epochs` passes over nrows
+ * rows in shuffled mini-batches of `batch`; per-epoch mean losses to
+ * losses (host, may be NULL).  Synchronous. */
+int dg_mlp_train(dg_handle h, const void* X, const float* y, int64_t nrows, int32_t batch, int32_t epochs, float lr,
+                 uint64_t seed, float* losses /*[host]*/);
 
 /* Measurement hook: launch one kernel of the step `reps` times back to back
  * on the handle's stream between two HIP events and return the mean time per

@@ -12,7 +12,9 @@ DG_LIM_TVB, DG_LIM_CHAR, DG_LIM_POS, DG_LIM_LEARNED = 1, 2, 4, 8
 DG_MESH_UNIFORM, DG_MESH_OCTREE = 0, 1
 
 EXPORTS = ["dg_init", "dg_layout", "dg_proj_points", "dg_project", "dg_dt", "dg_rhs", "dg_limit", "dg_step",
-           "dg_set_mlp", "dg_time_kernel", "dg_autotune", "dg_last_error", "dg_destroy"]
+           "dg_mlp_scale", "dg_mlp_set", "dg_mlp_get", "dg_mlp_features", "dg_mlp_labels", "dg_mlp_record", "dg_mlp_forward",
+           "dg_mlp_grad", "dg_mlp_train", "dg_time_kernel", "dg_autotune", "dg_last_error", "dg_destroy"]
+MLP_NPARAM = 24833
 
 
 class dg_params(ctypes.Structure):
@@ -64,7 +66,16 @@ def load_library(path=LIB_PATH):
     lib.dg_rhs.argtypes = [P, P, P, D, D]
     lib.dg_limit.argtypes = [P, P, ctypes.POINTER(dg_limit_stats)]
     lib.dg_step.argtypes = [P, P, I32, ctypes.POINTER(D)]
-    lib.dg_set_mlp.argtypes = [P, P, ctypes.POINTER(ctypes.c_float), I32]
+    F32P = ctypes.POINTER(ctypes.c_float)
+    lib.dg_mlp_scale.argtypes = [P, P, ctypes.POINTER(D)]
+    lib.dg_mlp_set.argtypes = [P, F32P, ctypes.POINTER(D), ctypes.c_uint64]
+    lib.dg_mlp_get.argtypes = [P, F32P]
+    lib.dg_mlp_features.argtypes = [P, P, P]
+    lib.dg_mlp_labels.argtypes = [P, P, P]
+    lib.dg_mlp_record.argtypes = [P, P, P, P, I64, D, D, ctypes.c_uint64]
+    lib.dg_mlp_forward.argtypes = [P, P, I64, P]
+    lib.dg_mlp_grad.argtypes = [P, P, P, I64, F32P, F32P]
+    lib.dg_mlp_train.argtypes = [P, P, P, I64, I32, I32, ctypes.c_float, ctypes.c_uint64, F32P]
     lib.dg_time_kernel.argtypes = [P, P, I32, I32, ctypes.POINTER(D)]
     lib.dg_autotune.argtypes = [P, P, ctypes.c_char_p, ctypes.POINTER(I32)]
     lib.dg_last_error.argtypes = [P]
@@ -193,6 +204,64 @@ class DG:
         cp = cache_path.encode() if cache_path else None
         self._check(self.lib.dg_autotune(self.h, _ptr(w), cp, ctypes.byref(v)))
         return v.value
+
+    # ---------------------------------------------------------------- learned indicator
+    def mlp_scale(self, w):
+        import numpy as np
+        out = np.zeros(9)
+        self._check(self.lib.dg_mlp_scale(self.h, _ptr(w), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def mlp_set(self, params, sigma=None, seed=0):
+        import numpy as np
+        sgp = None
+        if sigma is not None:
+            sg = np.ascontiguousarray(sigma, dtype=np.float64)
+            assert sg.shape == (9,)
+            sgp = sg.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        pp = None
+        if params is not None:
+            pp = np.ascontiguousarray(params, dtype=np.float32)
+            assert pp.shape == (MLP_NPARAM,)
+            pp = pp.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        self._check(self.lib.dg_mlp_set(self.h, pp, sgp, seed))
+
+    def mlp_get(self):
+        import numpy as np
+        out = np.zeros(MLP_NPARAM, dtype=np.float32)
+        self._check(self.lib.dg_mlp_get(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return out
+
+    def mlp_features(self, w, X):
+        self._check(self.lib.dg_mlp_features(self.h, _ptr(w), _ptr(X)))
+
+    def mlp_labels(self, w, y):
+        self._check(self.lib.dg_mlp_labels(self.h, _ptr(w), _ptr(y)))
+
+    def mlp_record(self, X=None, y=None, counter=None, q_pos=1.0, q_neg=0.0, seed=0):
+        if X is None:
+            self._check(self.lib.dg_mlp_record(self.h, None, None, None, 0, 0.0, 0.0, 0))
+        else:
+            self._check(self.lib.dg_mlp_record(self.h, _ptr(X), _ptr(y), _ptr(counter), X.shape[0], q_pos, q_neg,
+                                               seed))
+
+    def mlp_forward(self, X, nrows, prob):
+        self._check(self.lib.dg_mlp_forward(self.h, _ptr(X), nrows, _ptr(prob)))
+
+    def mlp_grad(self, X, y, nrows):
+        import numpy as np
+        g = np.zeros(MLP_NPARAM, dtype=np.float32)
+        loss = ctypes.c_float()
+        self._check(self.lib.dg_mlp_grad(self.h, _ptr(X), _ptr(y), nrows,
+                                         g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(loss)))
+        return loss.value, g
+
+    def mlp_train(self, X, y, nrows, batch=4096, epochs=4, lr=1e-3, seed=0):
+        import numpy as np
+        losses = np.zeros(epochs, dtype=np.float32)
+        self._check(self.lib.dg_mlp_train(self.h, _ptr(X), _ptr(y), nrows, batch, epochs, lr, seed,
+                                          losses.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return losses
 
     def step_async(self, w, nsteps=1):
         self._check(self.lib.dg_step(self.h, _ptr(w), nsteps, None))

@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdgmhd.so")
-SOURCES = ["dg_tables.cpp", "dg_kernels.hip", "dg_api.hip"]
+SOURCES = ["dg_tables.cpp", "dg_kernels.hip", "dg_mlp.hip", "dg_api.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
          # packed FP32 instructions are kept out of the device code

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <fstream>
 #include <new>
+#include <random>
 #include <sstream>
 #include <string>
 #include <unordered_map>
@@ -15,6 +16,7 @@
 
 #include "../../include/dg.h"
 #include "dg_kernels.h"
+#include "dg_mlp.h"
 #include "dg_tables.h"
 
 using namespace dgmhd;
@@ -33,6 +35,15 @@ struct dg_handle_s {
   void* lscr = nullptr;   // limiter scratch
   Scal* sc = nullptr;     // device scalars
   std::vector<void*> mesh_bufs;  // octree face lists on the device
+  MlpState mlp;              // learned troubled-cell indicator
+  int mlp_step = 0;          // Adam step counter
+  // recording of (features, label) pairs inside dg_step
+  uint16_t* rec_X = nullptr;
+  float* rec_y = nullptr;
+  unsigned long long* rec_counter = nullptr;
+  int64_t rec_cap = 0;
+  double rec_q = 0.0, rec_qpos = 1.0;
+  unsigned long long rec_seed = 0;
   // one captured SSP-RK3 step per state pointer (non-null streams only)
   hipGraphExec_t graph_exec = nullptr;
   const void* graph_w = nullptr;
@@ -217,7 +228,8 @@ int dg_init(const dg_params* p, const dg_mesh* m, void* hip_stream, dg_handle* o
     return fail(nullptr, DG_EUNSUPPORTED, "slope limiter with the Powell/LDF basis not built");
   if ((p->limiter & (DG_LIM_CHAR | DG_LIM_LEARNED)) && !(p->limiter & DG_LIM_TVB))
     return fail(nullptr, DG_EINVAL, "characteristic/learned flags need DG_LIM_TVB");
-  if (p->limiter & DG_LIM_LEARNED) return fail(nullptr, DG_EUNSUPPORTED, "learned indicator not built yet");
+  if ((p->limiter & DG_LIM_LEARNED) && (p->divb != DG_GLM || m->kind != DG_MESH_UNIFORM))
+    return fail(nullptr, DG_EUNSUPPORTED, "learned indicator is built for GLM on uniform grids");
   for (int a = 0; a < p->dim; ++a)
     if (m->n[a] < 1 || !(m->box[a] > 0.0)) return fail(nullptr, DG_EINVAL, "mesh size");
   for (int a = 1; a < p->dim; ++a)
@@ -254,6 +266,11 @@ int dg_init(const dg_params* p, const dg_mesh* m, void* hip_stream, dg_handle* o
   sp.eps_rho = p->eps_rho > 0.0 ? p->eps_rho : 1e-12;
   sp.eps_p = p->eps_p > 0.0 ? p->eps_p : 1e-12;
   sp.limiter = p->limiter;
+  sp.mlp_lo = p->mlp_lo;
+  sp.mlp_hi = p->mlp_hi > 0.0 ? p->mlp_hi : 0.5;
+  sp.mlp_Pb = nullptr;
+  sp.mlp_P = nullptr;
+  sp.mlp_sigma = nullptr;
 
   std::string err;
   if (!build_tables(p->dim, p->degree, p->divb, h->tabs, err)) { int r = fail(nullptr, DG_EINVAL, err); delete h; return r; }
@@ -370,17 +387,25 @@ static void step_sequence(dg_handle h, void* w) {
   h->L->maxsig(w, h->g, h->sc, h->sp, h->stream);
   if (h->p.divb == DG_POWELL) h->L->powell_cap(w, h->jsum, h->g, h->sc, h->sp, h->stream);
   launch_finalize_dt(h->sc, h->sp, h->p.dim, h->p.degree, h->p.divb, h->hmin, h->stream);
+  auto record = [&](void* u) {
+    if (h->rec_X)
+      (void)h->L->mlp_record(u, h->rec_X, h->rec_y, h->rec_counter, h->rec_cap, h->rec_qpos, h->rec_q, h->rec_seed,
+                             h->g, h->sc, h->sp, h->stream);
+  };
   // stage 1: S1 = w + dt L(w)
   h->L->face(w, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
   h->L->cell(w, w, h->S1, h->ff, h->jp, h->g, h->sc, h->sp, 0.0, 1.0, 1, h->stream);
+  record(h->S1);
   if (lim) h->L->limit(h->S1, h->lscr, h->g, h->sc, h->sp, h->stream);
   // stage 2: S1 = 3/4 w + 1/4 (S1 + dt L(S1))
   h->L->face(h->S1, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
   h->L->cell(h->S1, w, h->S1, h->ff, h->jp, h->g, h->sc, h->sp, 0.75, 0.25, 1, h->stream);
+  record(h->S1);
   if (lim) h->L->limit(h->S1, h->lscr, h->g, h->sc, h->sp, h->stream);
   // stage 3: w = 1/3 w + 2/3 (S1 + dt L(S1))
   h->L->face(h->S1, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
   h->L->cell(h->S1, w, w, h->ff, h->jp, h->g, h->sc, h->sp, 1.0 / 3.0, 2.0 / 3.0, 1, h->stream);
+  record(w);
   if (lim) h->L->limit(w, h->lscr, h->g, h->sc, h->sp, h->stream);
 }
 
@@ -432,11 +457,6 @@ int dg_step(dg_handle h, void* w, int32_t nsteps, double* t) {
   return DG_OK;
 }
 
-int dg_set_mlp(dg_handle h, const void* w_bf16, const float* b, int32_t in_dim) {
-  if (!h) return DG_EINVAL;
-  (void)w_bf16; (void)b; (void)in_dim;
-  return fail(h, DG_EUNSUPPORTED, "learned indicator not built yet");
-}
 
 int dg_time_kernel(dg_handle h, const void* w, int32_t which, int32_t reps, double* ms) {
   if (int r = valid_state(h, w)) return r;
@@ -555,11 +575,190 @@ int dg_autotune(dg_handle h, const void* w, const char* cache_path, int32_t* var
   return DG_OK;
 }
 
+static int mlp_ready(dg_handle h) {
+  if (h->p.divb != DG_GLM || h->g.level) return fail(h, DG_EUNSUPPORTED, "learned indicator: GLM on uniform grids");
+  std::string e;
+  if (!h->mlp.alloc_params(e)) return fail(h, DG_ENOMEM, e);
+  return DG_OK;
+}
+
+int dg_mlp_scale(dg_handle h, const void* w, double* sigma) {
+  if (int r = valid_state(h, w)) return r;
+  if (int r = mlp_ready(h)) return r;
+  double* part = nullptr;
+  const int64_t nblk = (h->g.C + 255) / 256;
+  if (int r = check_hip(h, hipMalloc(&part, (size_t)nblk * 9 * sizeof(double)), "scale buffer")) return r;
+  if (!h->L->mlp_scale(w, part, h->mlp.sigma, h->g, h->stream)) { (void)hipFree(part); return fail(h, DG_EUNSUPPORTED, "scale"); }
+  int rc = check_hip(h, hipStreamSynchronize(h->stream), "sync");
+  (void)hipFree(part);
+  if (rc) return rc;
+  h->mlp.have_sigma = true;
+  if (sigma) rc = check_hip(h, hipMemcpy(sigma, h->mlp.sigma, 9 * sizeof(double), hipMemcpyDeviceToHost), "sigma");
+  return rc;
+}
+
+int dg_mlp_set(dg_handle h, const float* params, const double* sigma, uint64_t seed) {
+  if (!h) return DG_EINVAL;
+  if (int r = mlp_ready(h)) return r;
+  if (!sigma && !h->mlp.have_sigma) return fail(h, DG_EINVAL, "no feature scales: pass sigma or call dg_mlp_scale");
+  std::vector<float> pub(MLP_NPARAM, 0.f), dev;
+  if (params) {
+    std::memcpy(pub.data(), params, sizeof(float) * MLP_NPARAM);
+  } else {
+    // W ~ U(-1/sqrt(fin), 1/sqrt(fin)), b = 0
+    std::mt19937_64 rng(seed);
+    std::uniform_real_distribution<double> U(-1.0, 1.0);
+    const int fin[4] = {256, 64, 64, 64}, fo[4] = {64, 64, 64, 1};
+    size_t q = 0;
+    for (int l = 0; l < 4; ++l) {
+      const double lim = 1.0 / std::sqrt((double)fin[l]);
+      for (int i = 0; i < fin[l] * fo[l]; ++i) pub[q++] = (float)(lim * U(rng));
+      q += fo[l];
+    }
+  }
+  mlp_pack(pub.data(), dev);
+  MlpState& M = h->mlp;
+  if (int r = check_hip(h, hipMemcpy(M.P, dev.data(), dev.size() * 4, hipMemcpyHostToDevice), "mlp upload")) return r;
+  if (int r = check_hip(h, hipMemset(M.Mo, 0, dev.size() * 4), "mlp adam")) return r;
+  if (int r = check_hip(h, hipMemset(M.Vo, 0, dev.size() * 4), "mlp adam")) return r;
+  if (sigma) {
+    if (int r = check_hip(h, hipMemcpy(M.sigma, sigma, 9 * sizeof(double), hipMemcpyHostToDevice), "sigma")) return r;
+    M.have_sigma = true;
+  }
+  M.sync_bf16(h->stream);
+  if (int r = check_hip(h, hipStreamSynchronize(h->stream), "sync")) return r;
+  h->mlp_step = 0;
+  h->sp.mlp_Pb = M.Pb;
+  h->sp.mlp_P = M.P;
+  h->sp.mlp_sigma = M.sigma;
+  M.have_params = true;
+  drop_graph(h);
+  return DG_OK;
+}
+
+int dg_mlp_get(dg_handle h, float* params) {
+  if (!h || !params) return DG_EINVAL;
+  if (!h->mlp.have_params) return fail(h, DG_EINVAL, "no network installed");
+  std::vector<float> dev(MLP_NPARAM_DEV);
+  if (int r = check_hip(h, hipStreamSynchronize(h->stream), "sync")) return r;
+  if (int r = check_hip(h, hipMemcpy(dev.data(), h->mlp.P, dev.size() * 4, hipMemcpyDeviceToHost), "download")) return r;
+  mlp_unpack(dev, params);
+  return DG_OK;
+}
+
+int dg_mlp_features(dg_handle h, const void* w, void* X) {
+  if (int r = valid_state(h, w)) return r;
+  if (!X) return fail(h, DG_EINVAL, "null X");
+  if (!h->mlp.have_params) return fail(h, DG_EINVAL, "dg_mlp_set first (feature scales)");
+  if (!h->L->mlp_features(w, (uint16_t*)X, h->mlp.sigma, h->g, h->stream)) return fail(h, DG_EUNSUPPORTED, "features");
+  return check_launch(h, "features");
+}
+
+int dg_mlp_labels(dg_handle h, const void* w, float* y) {
+  if (int r = valid_state(h, w)) return r;
+  if (!y) return fail(h, DG_EINVAL, "null y");
+  if (int r = dt_sequence(h, w)) return r;  // c_h of this state for the GLM block
+  if (!h->L->mlp_labels(w, y, h->g, h->sc, h->sp, h->stream)) return fail(h, DG_EUNSUPPORTED, "labels");
+  return check_launch(h, "labels");
+}
+
+int dg_mlp_record(dg_handle h, void* X, float* y, unsigned long long* counter, int64_t cap, double q_pos,
+                  double q_neg, uint64_t seed) {
+  if (!h) return DG_EINVAL;
+  if (X && (!y || !counter || cap <= 0)) return fail(h, DG_EINVAL, "record buffers");
+  if (X && !h->mlp.have_params) return fail(h, DG_EINVAL, "dg_mlp_set first (feature scales)");
+  h->rec_X = (uint16_t*)X;
+  h->rec_y = y;
+  h->rec_counter = counter;
+  h->rec_cap = cap;
+  h->rec_q = q_neg;
+  h->rec_qpos = q_pos;
+  h->rec_seed = seed;
+  drop_graph(h);
+  return DG_OK;
+}
+
+int dg_mlp_forward(dg_handle h, const void* X, int64_t nrows, float* prob) {
+  if (!h || !X || !prob || nrows < 0) return DG_EINVAL;
+  if (!h->mlp.have_params) return fail(h, DG_EINVAL, "no network installed");
+  std::string e;
+  MlpState& M = h->mlp;
+  if (!M.alloc(M.B > 0 ? M.B : 4096, e)) return fail(h, DG_ENOMEM, e);
+  for (int64_t r0 = 0; r0 < nrows; r0 += M.B) {
+    const int64_t nr = std::min<int64_t>(M.B, nrows - r0);
+    M.gather((const uint16_t*)X, nullptr, nullptr, r0, nrows, h->stream);
+    M.forward(h->stream);
+    mlp_head_probs(M, h->stream);
+    if (int r = check_hip(h, hipMemcpyAsync(prob + r0, M.pout, nr * 4, hipMemcpyDeviceToDevice, h->stream), "copy"))
+      return r;
+  }
+  return check_launch(h, "mlp forward");
+}
+
+int dg_mlp_grad(dg_handle h, const void* X, const float* y, int64_t nrows, float* grads, float* loss) {
+  if (!h || !X || !y || !grads || nrows <= 0) return DG_EINVAL;
+  if (!h->mlp.have_params) return fail(h, DG_EINVAL, "no network installed");
+  std::string e;
+  MlpState& M = h->mlp;
+  if (!M.alloc((int)nrows, e)) return fail(h, DG_ENOMEM, e);
+  mlp_zero_loss(M, 0, h->stream);
+  M.loss_slot = 0;
+  M.gather((const uint16_t*)X, y, nullptr, 0, nrows, h->stream);
+  M.backward(nrows, h->stream);
+  std::vector<float> dev(MLP_NPARAM_DEV);
+  float l = 0.f;
+  if (int r = check_hip(h, hipStreamSynchronize(h->stream), "sync")) return r;
+  if (int r = check_hip(h, hipMemcpy(dev.data(), M.G, dev.size() * 4, hipMemcpyDeviceToHost), "download")) return r;
+  if (int r = check_hip(h, hipMemcpy(&l, M.loss, 4, hipMemcpyDeviceToHost), "download")) return r;
+  mlp_unpack(dev, grads);
+  if (loss) *loss = l;
+  return DG_OK;
+}
+
+int dg_mlp_train(dg_handle h, const void* X, const float* y, int64_t nrows, int32_t batch, int32_t epochs, float lr,
+                 uint64_t seed, float* losses) {
+  if (!h || !X || !y || nrows <= 0 || batch < 16 || epochs < 1 || epochs > 4096 || !(lr > 0.f)) return DG_EINVAL;
+  if (!h->mlp.have_params) return fail(h, DG_EINVAL, "no network installed");
+  std::string e;
+  MlpState& M = h->mlp;
+  if (!M.alloc(batch, e)) return fail(h, DG_ENOMEM, e);
+  int32_t* idx = nullptr;
+  if (int r = check_hip(h, hipMalloc(&idx, (size_t)nrows * 4), "index")) return r;
+  std::vector<int32_t> perm((size_t)nrows);
+  std::mt19937_64 rng(seed);
+  int rc = DG_OK;
+  for (int ep = 0; ep < epochs && rc == DG_OK; ++ep) {
+    for (int64_t i = 0; i < nrows; ++i) perm[i] = (int32_t)i;
+    for (int64_t i = nrows - 1; i > 0; --i) std::swap(perm[i], perm[std::uniform_int_distribution<int64_t>(0, i)(rng)]);
+    rc = check_hip(h, hipMemcpyAsync(idx, perm.data(), (size_t)nrows * 4, hipMemcpyHostToDevice, h->stream), "idx");
+    if (rc) break;
+    mlp_zero_loss(M, ep, h->stream);
+    M.loss_slot = ep;
+    int64_t nb_ = 0;
+    for (int64_t r0 = 0; r0 + M.B <= nrows; r0 += M.B, ++nb_) {  // full batches only
+      M.gather((const uint16_t*)X, y, idx, r0, nrows, h->stream);
+      M.backward(M.B, h->stream);
+      M.adam(lr, ++h->mlp_step, h->stream);
+    }
+    rc = check_hip(h, hipStreamSynchronize(h->stream), "epoch");  // the host permutation buffer is reused
+    if (rc == DG_OK && losses) {
+      float l = 0.f;
+      rc = check_hip(h, hipMemcpy(&l, M.loss + ep, 4, hipMemcpyDeviceToHost), "loss");
+      losses[ep] = nb_ ? l / (float)nb_ : 0.f;
+    }
+  }
+  (void)hipFree(idx);
+  drop_graph(h);
+  if (rc) return rc;
+  return check_launch(h, "mlp train");
+}
+
 const char* dg_last_error(dg_handle h) { return h ? h->err.c_str() : g_err.c_str(); }
 
 void dg_destroy(dg_handle h) {
   if (!h) return;
   drop_graph(h);
+  h->mlp.release();
   if (h->L) { h->L->free_tables(); delete h->L; }
   if (h->ff) (void)hipFree(h->ff);
   if (h->jp) (void)hipFree(h->jp);

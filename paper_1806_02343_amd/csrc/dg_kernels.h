@@ -21,6 +21,7 @@ struct Scal {
   // limiter statistics (accumulated, reset by the host)
   unsigned long long n_tvb, n_pos, n_floor, n_mlp, n_fallback;
   double inj_mass, inj_energy;
+  unsigned long long n_record_stage;     // stages recorded for the learned indicator
 };
 
 struct Grid {
@@ -44,6 +45,11 @@ struct SchemeParams {
   double gamma, cfl, cfl_glm, glm_cr, glm_ch_fixed, powell_eta;
   double tvb_Mtilde, tvb_beta, tvb_eps, eps_rho, eps_p;
   int limiter;
+  // learned indicator (device pointers, null until installed)
+  double mlp_lo, mlp_hi;
+  const uint16_t* mlp_Pb;
+  const float* mlp_P;
+  const double* mlp_sigma;
 };
 
 // Per-configuration launcher; one instance per handle.
@@ -74,6 +80,14 @@ struct Launcher {
   // limiters in place
   virtual void limit(void* w, void* scratch, const Grid& g, Scal* sc, const SchemeParams& sp, hipStream_t s) = 0;
   virtual size_t limit_scratch_bytes(const Grid& g) const = 0;
+  // learned indicator helpers (GLM only; return false when not built)
+  virtual bool mlp_features(const void* w, uint16_t* X, const double* sigma, const Grid& g, hipStream_t s) = 0;
+  virtual bool mlp_labels(const void* w, float* y, const Grid& g, Scal* sc, const SchemeParams& sp,
+                          hipStream_t s) = 0;
+  virtual bool mlp_scale(const void* w, double* part, double* sigma, const Grid& g, hipStream_t s) = 0;
+  virtual bool mlp_record(const void* w, uint16_t* X, float* y, unsigned long long* counter, int64_t cap, double qpos,
+                          double qneg, unsigned long long seed, const Grid& g, Scal* sc, const SchemeParams& sp,
+                          hipStream_t s) = 0;
   virtual int nmodes() const = 0;
 };
 

@@ -818,6 +818,47 @@ struct LauncherImpl : Launcher {
     launch_limit<T, D, DEG, DIVB>(w, scratch, tb, g, sc, sp, s);
   }
   size_t limit_scratch_bytes(const Grid& g) const override { return limit_scratch<T, D, DEG, DIVB>(g); }
+  bool mlp_features(const void* w, uint16_t* X, const double* sigma, const Grid& g, hipStream_t s) override {
+    if constexpr (DIVB == GLM && DEG <= 3) {
+      if (g.level) return false;
+      k_mlp_features<T, D, DEG><<<(unsigned)((g.C * 256 + 255) / 256), 256, 0, s>>>((const T*)w, X, sigma, g);
+      return true;
+    }
+    return false;
+  }
+  bool mlp_scale(const void* w, double* part, double* sigma, const Grid& g, hipStream_t s) override {
+    if constexpr (DIVB == GLM) {
+      const int64_t nblk = (g.C + 255) / 256;
+      k_mean_sq<T, C::N><<<(unsigned)nblk, 256, 0, s>>>((const T*)w, part, g);
+      k_scale_final<<<1, 1, 0, s>>>(part, nblk, g.C, sigma);
+      return true;
+    }
+    return false;
+  }
+  bool mlp_labels(const void* w, float* y, const Grid& g, Scal* sc, const SchemeParams& sp, hipStream_t s) override {
+    if constexpr (DIVB == GLM) {
+      if (g.level) return false;
+      k_tvb_labels<T, D, DEG><<<(unsigned)((g.C + 127) / 128), 128, 0, s>>>((const T*)w, y, g, sc, sp.gamma,
+                                                                             sp.tvb_Mtilde * g.h, sp.tvb_beta,
+                                                                             sp.tvb_eps, (sp.limiter & 2) ? 1 : 0);
+      return true;
+    }
+    return false;
+  }
+  bool mlp_record(const void* w, uint16_t* X, float* y, unsigned long long* counter, int64_t cap, double qpos,
+                  double q, unsigned long long seed, const Grid& g, Scal* sc, const SchemeParams& sp,
+                  hipStream_t s) override {
+    if constexpr (DIVB == GLM) {
+      if (g.level || !sp.mlp_sigma) return false;
+      k_record<T, D, DEG><<<(unsigned)((g.C + 127) / 128), 128, 0, s>>>((const T*)w, X, y, counter, cap, qpos, q, seed, g,
+                                                                         sc, sp.mlp_sigma, sp.gamma,
+                                                                         sp.tvb_Mtilde * g.h, sp.tvb_beta,
+                                                                         sp.tvb_eps);
+      k_record_stage_bump<<<1, 1, 0, s>>>(sc);
+      return true;
+    }
+    return false;
+  }
   ~LauncherImpl() override { free_tables(); }
 };
 
