@@ -1,11 +1,19 @@
 """Throughput benchmark of the DG MHD hot path on one MI355X.
 
-One step = one SSP-RK3 time step of the whole path (time-step reduction, and
-per stage the face-flux kernel, the cell kernel and the limiters) over the
-full workload, inputs resident in HBM.  The metric is DoF-updates per second
-per RK stage: N_DoF x 3 x steps / wall time.
+One step = one SSP-RK3 time step of the whole path (time-step reduction,
+then per stage the face-flux kernel, the cell kernel and the limiters) over
+the full workload, inputs resident in HBM; the step replays one captured
+hipGraph.  The metric is DoF-updates per second per RK stage:
+N_DoF x 3 x steps / wall time.
 
-Prints one JSON line (see the repository's design notes for every field).
+Default workload (the metric's comparison): 3-D periodic 128^3, degree 3,
+GLM, 8 seeded over-pressured spheres, characteristic TVB + positivity
+limiters, CFL 0.3.  `value` is the FP64 plain method; the same JSON line
+carries the FP32 path and the FP32 path with the learned troubled-cell
+indicator (trained during untimed setup on other seeds), each with its
+relative L1 distance to the FP64 state after the timed steps.
+
+Prints one JSON line.
 """
 import argparse
 import json
@@ -17,17 +25,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "DG DoF-updates/sec per RK stage, FP64 plain vs FP32+learned limiter at L1 tol"
-PEAK_FP64 = 78.6e12   # MI355X FP64 vector = matrix peak (flop/s)
+PEAK_FP64 = 78.6e12   # MI355X FP64 (vector = matrix) flop/s
 PEAK_FP32 = 157.3e12
 PEAK_HBM = 8.0e12
+L1_TOL = 1e-5
 
 WORKLOADS = {
     # name: (D, d, n, divb, limiter, seed-config, description)
-    "cfg1": (3, 2, 64, 1, 0, 1, "3-D periodic 64^3, degree 2, Powell scheme with the LDF basis for B, "
-                                 "smooth seeded IC (random Fourier modes, B = curl A), SSP-RK3, CFL 0.3"),
-    "cfg0": (2, 1, 32, 0, 0, 0, "2-D periodic 32^2, degree 1, GLM, smooth seeded IC, SSP-RK3, CFL 0.3"),
-    "cfg2": (3, 3, 128, 0, 7, 2, "3-D periodic 128^3, degree 3, GLM, 8 seeded over-pressured spheres, "
-                                  "characteristic TVB + positivity limiters, SSP-RK3, CFL 0.3"),
+    "blast128": (3, 3, 128, 0, 7, 2, "3-D periodic 128^3, degree 3 (20 modes/var), GLM, 8 seeded over-pressured "
+                                     "spheres, characteristic TVB + positivity limiters, SSP-RK3, CFL 0.3"),
+    "smooth64": (3, 2, 64, 1, 0, 1, "3-D periodic 64^3, degree 2, Powell scheme with the LDF basis for B, smooth "
+                                    "seeded IC (random Fourier modes, B = curl A), SSP-RK3, CFL 0.3"),
+    "smooth32_2d": (2, 1, 32, 0, 0, 0, "2-D periodic 32^2, degree 1, GLM, smooth seeded IC, SSP-RK3, CFL 0.3"),
+    "peaks_amr": (3, 2, 64, 0, 0, 3, "3-D octree: base 64^3, 2 levels around 16 seeded Gaussian density peaks "
+                                     "(1,520,093 leaves), degree 2, GLM with fixed c_h, hanging faces, SSP-RK3, "
+                                     "CFL 0.3"),
 }
 
 
@@ -49,14 +61,45 @@ def cell_flops(D, d, divb):
     return nodal + flux + vol + surf + powell + update
 
 
+def rel_l1_modal(a, b, nmodes_per_var, nvar_cmp=8):
+    """max over rho, m, E, B of sum|a-b| / sum|b| over the variable's modes."""
+    out = []
+    for v in range(nvar_cmp):
+        sl = slice(v * nmodes_per_var, (v + 1) * nmodes_per_var)
+        out.append(float((a[sl].double() - b[sl].double()).abs().sum() / b[sl].double().abs().sum()))
+    return max(out), out
+
+
+def timed_run(gpu, w0, steps, warmup):
+    import torch
+    w = w0.clone()
+    gpu.step(w, warmup)
+    w.copy_(w0)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    gpu.step_async(w, steps)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1), w
+
+
+def make_handle(D, d, n, divb, limiter, prec, stream, octree=None, ch=0.0, lo=0.0):
+    from paper_1806_02343_amd import DG
+    return DG(D, d, n, divb=divb, precision=prec, limiter=limiter, cfl=0.3, stream=stream, octree=octree,
+              glm_ch_fixed=ch, mlp_lo=lo, mlp_hi=0.5)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg1", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="blast128", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -67,59 +110,89 @@ def main():
     import torch
 
     import workloads as wl
-    from paper_1806_02343_amd import DG
+    from paper_1806_02343_amd import DG_LIM_LEARNED
 
     D, d, n, divb, limiter, cfg, desc = WORKLOADS[args.workload]
-    field = wl.config_field(cfg)
-    results = {}
-    states = {}
     stream = torch.cuda.Stream()          # non-null stream: each step replays one captured hipGraph
     torch.cuda.set_stream(stream)
-    for prec in ([0] if args.no_fp32 else [0, 1]):
-        gpu = DG(D, d, n, divb=divb, precision=prec, limiter=limiter, cfl=0.3, stream=stream.cuda_stream)
+    octree, ch = None, 0.0
+    if args.workload == "peaks_amr":
+        pk = wl.Peaks(3000)
+        octree = wl.peaks_leaves(pk)
+        # c_h fixed at twice the largest signal speed sum_a(|v_a| + c)/D of the
+        # initial state (background density 1 has the largest sound and Alfven speeds)
+        B2 = sum(b * b for b in pk.B0)
+        c = np.sqrt((5.0 / 3.0 * 1.0 + B2) / 1.0)
+        ch = 2.0 * (sum(abs(v) for v in pk.V0) + 3 * c) / 3
+        field = pk
+    else:
+        field = wl.config_field(cfg)
+
+    runs = {}
+
+    def run(tag, prec, lim, extra=None, lo=0.0):
+        gpu = make_handle(D, d, n, divb, lim, prec, stream.cuda_stream, octree, ch, lo)
         w0 = gpu.empty_state()
         gpu.project_field(field, w0)
-        if limiter:
+        if extra:
+            extra(gpu, w0)
+        if lim:
             gpu.limit(w0)
         variant = gpu.autotune(w0)
-        w = w0.clone()
-        gpu.step(w, args.warmup)
-        w.copy_(w0)
-        torch.cuda.synchronize()
-        s = torch.cuda.current_stream()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        e0.record(s)
-        gpu.step_async(w, args.steps)
-        e1.record(s)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        ms = e0.elapsed_time(e1)
+        ms, w = timed_run(gpu, w0, args.steps, args.warmup)
         ndof = gpu.nmodes * gpu.ncells
-        results[prec] = dict(ms=ms, wall=wall, ndof=ndof, value=ndof * 3 * args.steps / (ms / 1e3), gpu=gpu,
-                             variant=variant)
-        states[prec] = w
-        # kernel timings (mean ms per launch)
-        results[prec]["k_face"] = gpu.time_kernel(w0, 0, 5)
-        results[prec]["k_cell"] = gpu.time_kernel(w0, 1, 5)
-        results[prec]["k_dt"] = gpu.time_kernel(w0, 2, 5)
-        results[prec]["k_limit"] = gpu.time_kernel(w0, 3, 5) if limiter else 0.0
-        print(f"# prec={'fp64' if prec == 0 else 'fp32'} ms/step={ms / args.steps:.3f} "
-              f"face={results[prec]['k_face']:.3f}ms cell={results[prec]['k_cell']:.3f}ms "
-              f"dt={results[prec]['k_dt']:.3f}ms limit={results[prec]['k_limit']:.3f}ms variant={variant}",
-              file=sys.stderr, flush=True)
+        r = dict(ms=ms, ndof=ndof, value=ndof * 3 * args.steps / (ms / 1e3), w=w, gpu=gpu, variant=variant,
+                 k_face=gpu.time_kernel(w0, 0, 5), k_cell=gpu.time_kernel(w0, 1, 5), k_dt=gpu.time_kernel(w0, 2, 5),
+                 k_limit=gpu.time_kernel(w0, 3, 5) if lim else 0.0)
+        print(f"# {tag}: ms/step={ms / args.steps:.3f} face={r['k_face']:.3f} cell={r['k_cell']:.3f} "
+              f"dt={r['k_dt']:.3f} limit={r['k_limit']:.3f} (ms/launch) variant={variant}", file=sys.stderr,
+              flush=True)
+        runs[tag] = r
+        return r
 
-    r64 = results[0]
-    gpu = r64["gpu"]
-    ncells = gpu.ncells
-    # roofline of the dominant kernel (FP64)
-    dom = "k_cell" if r64["k_cell"] >= r64["k_face"] else "k_face"
+    r64 = run("fp64", 0, limiter)
+    if not args.no_fp32:
+        run("fp32", 1, limiter)
+    learned_info = None
+    if limiter and not args.no_learned and not args.no_fp32 and args.workload == "blast128":
+        from paper_1806_02343_amd.learned import false_negative_rate, train_indicator
+        t0 = time.perf_counter()
+        info = train_indicator(wl, n=n, d=d, stream=stream.cuda_stream)
+        t_train = time.perf_counter() - t0
+        print(f"# trained indicator: rows={info['n_train']} pos_frac={info['pos_frac_train']:.3f} "
+              f"losses={info['losses']} lo={info['lo']:.4f} val_fn={info['val_fn_rate']:.4f} "
+              f"({t_train:.1f}s)", file=sys.stderr, flush=True)
+
+        def install(gpu, w0):
+            gpu.mlp_set(info["params"], info["sigma"])
+
+        rl = run("fp32_learned", 1, limiter | DG_LIM_LEARNED, install, info["lo"])
+        # the gate on the evaluated workload itself: record two steps and count
+        # the positives of the plain detector that the gate would skip
+        g = rl["gpu"]
+        cap = 1 << 21
+        X = torch.zeros((cap, 256), dtype=torch.int16, device="cuda")
+        y = torch.zeros(cap, device="cuda")
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        w = g.empty_state()
+        g.project_field(field, w)
+        g.limit(w)
+        g.mlp_record(X, y, cnt, q_pos=1.0, q_neg=0.02, seed=99)
+        g.step(w, 2)
+        g.mlp_record(None)
+        torch.cuda.synchronize()
+        nrec = min(int(cnt.item()), cap)
+        fn, skip, _, _ = false_negative_rate(g, X, y, nrec, info["lo"])
+        learned_info = dict(train_rows=info["n_train"], train_pos_frac=info["pos_frac_train"],
+                            losses=info["losses"], gate_lo=info["lo"], val_fn_rate=info["val_fn_rate"],
+                            eval_fn_rate=fn, train_seconds=t_train)
+
+    ncells = r64["gpu"].ncells
     flops_launch = cell_flops(D, d, divb) * ncells
     achieved = flops_launch / (r64["k_cell"] / 1e3)
     roof = {"kernel": "k_cell", "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
-            "dominant": dom, "ms_per_launch": r64["k_cell"], "flops_per_launch": flops_launch}
-
+            "ms_per_launch": r64["k_cell"], "flops_per_launch": flops_launch}
     line = {
         "metric": METRIC,
         "value": r64["value"],
@@ -134,40 +207,46 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "dim": D, "degree": d, "cells": ncells,
-                   "n_dof": r64["ndof"], "divb": "powell+ldf" if divb else "glm"},
+                   "n_dof": r64["ndof"], "divb": "powell+ldf" if divb else "glm", "limiter": limiter},
         "roofline": roof,
     }
-    if 1 in results:
-        r32 = results[1]
-        # FP32 state against the FP64 state of the same run (FP64 matches the oracle to 1e-12)
-        a = states[1][:, :ncells].double()
-        b = states[0][:, :ncells]
-        rel = float((a - b).abs().sum() / b.abs().sum())
-        line["fp32"] = {"value": r32["value"], "ms_per_step": r32["ms"] / args.steps,
-                        "rel_l1_modal_vs_fp64": rel, "speedup_vs_fp64": r32["value"] / r64["value"]}
-    if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(D, d, divb, cfg)
+    for tag in ("fp32", "fp32_learned"):
+        if tag in runs:
+            r = runs[tag]
+            ent = {"value": r["value"], "ms_per_step": r["ms"] / args.steps, "speedup_vs_fp64": r["value"] / r64["value"]}
+            if divb == 0:
+                rel, per = rel_l1_modal(r["w"][:, :ncells], r64["w"][:, :ncells], r64["gpu"].nmodes // 9)
+                ent["rel_l1_vs_fp64"] = rel
+                ent["within_l1_tol"] = rel <= L1_TOL
+            line[tag] = ent
+    if learned_info:
+        line["fp32_learned"].update(learned_info)
+    if not args.no_cpu and args.workload != "peaks_amr":
+        line["cpu_baseline"] = cpu_baseline(D, d, divb, cfg, limiter)
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline(D, d, divb, cfg):
+def cpu_baseline(D, d, divb, cfg, limiter):
     """The FP64 oracle timed on the host on a bounded sample of the workload:
-    one SSP-RK3 step of the same scheme on a 16^3 (3-D) or 32^2 (2-D) grid."""
-    import numpy as np
+    one SSP-RK3 step of the same scheme (limiters included) on a 16^3 (3-D)
+    or 32^2 (2-D) grid."""
     from threadpoolctl import threadpool_info
 
     import workloads as wl
-    from oracle import dg
+    from oracle import dg, limiters
     nsample = 16 if D == 3 else 32
     orc = dg.DG(dg.Mesh.uniform(D, nsample), d, divb=divb)
     w = orc.project(dg.conserved_field(wl.config_field(cfg), 5.0 / 3.0, orc.nvar))
+    lim = limiters.make_stage_limiter(orc, limiter) if limiter else None
+    if lim:
+        w = lim(w)
     t0 = time.perf_counter()
-    w, dt, ch, k = orc.step(w)
+    w, dt, ch, k = orc.step(w, limiter=lim)
     sec = time.perf_counter() - t0
     ndof = orc.nmodes * orc.mesh.ncells
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     return {"value": ndof * 3 / sec, "unit": "DoF-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"1 SSP-RK3 step on {nsample}^{D} cells ({ndof} DoF), {sec:.2f} s"}
+            "sample": f"1 SSP-RK3 step of the same scheme on {nsample}^{D} cells ({ndof} DoF), {sec:.2f} s"}
 
 
 if __name__ == "__main__":

@@ -178,8 +178,8 @@ int dg_mlp_features(dg_handle h, const void* w, void* X);
 /* Plain TVB detector decisions of every cell of w into y (device FP32, 1/0),
  * c_h from the time-step rule of w; w is not modified.  Async. */
 int dg_mlp_labels(dg_handle h, const void* w, float* y);
-/* Record (features, label) pairs of the pre-limiter state of every stage of
- * later dg_step calls: positives kept with probability q_pos, negatives with
+/* Record (features, label) pairs of the pre-limiter state of every later
+ * dg_limit call and of every stage of later dg_step calls: positives kept with probability q_pos, negatives with
  * q_neg (counter-based hash of cell, stage and seed), rows appended to X
  * (device BF16 [cap][256]) and y (device FP32 [cap]) through the device
  * counter (uint64, caller-cleared; it may exceed cap: rows beyond cap are

@@ -358,6 +358,9 @@ int dg_limit(dg_handle h, void* w, dg_limit_stats* stats) {
   if ((h->p.limiter & DG_LIM_TVB) && h->p.divb == DG_GLM) {
     if (int r = dt_sequence(h, w)) return r;
   }
+  if (h->rec_X)
+    (void)h->L->mlp_record(w, h->rec_X, h->rec_y, h->rec_counter, h->rec_cap, h->rec_qpos, h->rec_q, h->rec_seed,
+                           h->g, h->sc, h->sp, h->stream);
   if (h->p.limiter) h->L->limit(w, h->lscr, h->g, h->sc, h->sp, h->stream);
   if (int r = check_launch(h, "limit")) return r;
   if (stats) {

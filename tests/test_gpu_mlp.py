@@ -159,3 +159,33 @@ def test_recording_inside_steps():
     # the recorded features are those of real cells (first feature = rho mean / s_rho > 0)
     f0 = (X[:k, 0].to(torch.int32) & 0xFFFF).cpu().numpy().astype(np.uint32) << 16
     assert np.all(f0.view(np.float32) > 0)
+
+
+def test_training_driver_on_blast_states():
+    """The driver records plain-detector labels inside limited steps, trains,
+    and picks a gate whose held-out false-negative rate stays at the target;
+    a run with the gate then skips cells and limits no cell the plain
+    detector would leave alone."""
+    print("case mlp driver", flush=True)
+    from paper_1806_02343_amd import DG, DG_LIM_CHAR, DG_LIM_LEARNED, DG_LIM_POS, DG_LIM_TVB
+    from paper_1806_02343_amd.learned import train_indicator
+    info = train_indicator(wl, n=24, d=3, train_seeds=range(4001, 4004), val_seeds=range(4029, 4030), steps=4,
+                           cap=1 << 16, q_neg=0.2, epochs=6, batch=512, lr=3e-3, precision=1)
+    assert info["n_train"] > 4 * 512
+    assert 0.0 < info["pos_frac_train"] < 1.0
+    assert info["losses"][-1] < info["losses"][0], info["losses"]
+    assert 1e-4 <= info["lo"] <= 0.5
+    assert info["val_fn_rate"] <= 0.01 + 1e-12
+    lim = DG_LIM_TVB | DG_LIM_CHAR | DG_LIM_POS
+    plain = DG(3, 3, 24, limiter=lim, precision=1)
+    gated = DG(3, 3, 24, limiter=lim | DG_LIM_LEARNED, precision=1, mlp_lo=info["lo"], mlp_hi=0.5)
+    gated.mlp_set(info["params"], info["sigma"])
+    wp, wq = plain.empty_state(), gated.empty_state()
+    plain.project_field(wl.Blast(2000), wp)
+    gated.project_field(wl.Blast(2000), wq)
+    sp = plain.limit(wp, stats=True)
+    sq = gated.limit(wq, stats=True)
+    # the gate only removes cells from the plain detector's work
+    assert sq["n_tvb_triggered"] <= sp["n_tvb_triggered"]
+    assert sq["n_fallback"] + sq["n_mlp_flagged"] < plain.ncells
+    assert sq["n_tvb_triggered"] >= 0.9 * sp["n_tvb_triggered"]
