@@ -585,34 +585,58 @@ __global__ void __launch_bounds__(256) k_powell_rate(const T* __restrict__ w, co
 
 // ---------------------------------------------------------------------------
 // projection of pointwise primitive values (d+3 rule)
+//
+// One workgroup per tile of PTC cells: the tile's primitive values (a
+// contiguous slab of each variable's [ncell][npts] block) are read coalesced,
+// converted to conserved variables into LDS, and every (mode, cell) output is
+// then a dot product over the tile's points.
+
+template <int D, int DEG>
+struct ProjTile {
+  static constexpr int NP = (D == 2) ? (DEG + 3) * (DEG + 3) : (DEG + 3) * (DEG + 3) * (DEG + 3);
+  static constexpr int TC0 = 131072 / (9 * 8 * NP);
+  static constexpr int TC = TC0 > 16 ? 16 : (TC0 < 1 ? 1 : TC0);
+};
 
 template <typename T, int D, int DEG, int DIVB>
 __global__ void __launch_bounds__(256) k_project(const double* __restrict__ prim, int64_t cell0, int64_t ncell,
                                                  T* __restrict__ w, const double* __restrict__ vpw,
                                                  const double* __restrict__ pvpw, const double* __restrict__ minv,
-                                                 int npts, int64_t ld, double gamma) {
+                                                 int64_t ld, double gamma) {
   using C = Cfg<D, DEG, DIVB>;
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= (int64_t)C::NMODES * ncell) return;
-  const int64_t c = gid % ncell;
-  const int m = (int)(gid / ncell);
-  auto P = [&](int v, int p) { return prim[((int64_t)v * ncell + c) * npts + p]; };
-  double s = 0.0;
-  for (int p = 0; p < npts; ++p) {
-    const double rho = P(0, p), vx = P(1, p), vy = P(2, p), vz = P(3, p), pr = P(4, p);
-    const double bx = P(5, p), by = P(6, p), bz = P(7, p);
-    double u[9] = {rho, rho * vx, rho * vy, rho * vz,
-                   pr / (gamma - 1.0) + 0.5 * rho * (vx * vx + vy * vy + vz * vz) + 0.5 * (bx * bx + by * by + bz * bz),
-                   bx, by, bz, P(8, p)};
+  constexpr int NP = ProjTile<D, DEG>::NP, TC = ProjTile<D, DEG>::TC;
+  __shared__ double su[9 * TC * NP];
+  const int64_t c0 = (int64_t)blockIdx.x * TC;
+  const int nc = (int)((ncell - c0) < TC ? (ncell - c0) : TC);
+  for (int i = threadIdx.x; i < nc * NP; i += blockDim.x) {
+    const int c = i / NP, p = i - c * NP;
+    auto P = [&](int v) { return prim[((int64_t)v * ncell + c0) * NP + i]; };
+    const double rho = P(0), vx = P(1), vy = P(2), vz = P(3), pr = P(4);
+    const double bx = P(5), by = P(6), bz = P(7);
+    const double u[9] = {rho, rho * vx, rho * vy, rho * vz,
+                         pr / (gamma - 1.0) + 0.5 * rho * (vx * vx + vy * vy + vz * vz) +
+                             0.5 * (bx * bx + by * by + bz * bz),
+                         bx, by, bz, P(8)};
+#pragma unroll
+    for (int v = 0; v < 9; ++v) su[(v * TC + c) * NP + p] = u[v];
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < C::NMODES * nc; o += blockDim.x) {
+    const int m = o / nc, c = o - m * nc;
+    double s = 0.0;
     if (m < C::NLEG * C::N) {
       const int j = m / C::N, l = m % C::N;
-      s += vpw[p * C::N + l] * u[C::legvar(j)];
+      const double* uu = su + (C::legvar(j) * TC + c) * NP;
+      for (int p = 0; p < NP; ++p) s += vpw[p * C::N + l] * uu[p];
     } else {
       const int l = m - C::NLEG * C::N;
-      for (int cc = 0; cc < D; ++cc) s += pvpw[(cc * npts + p) * C::NLDF + l] * u[5 + cc];
+      for (int cc = 0; cc < D; ++cc) {
+        const double* uu = su + ((5 + cc) * TC + c) * NP;
+        for (int p = 0; p < NP; ++p) s += pvpw[(cc * NP + p) * C::NLDF + l] * uu[p];
+      }
     }
+    w[(int64_t)m * ld + cell0 + c0 + c] = (T)(s * minv[m]);
   }
-  w[(int64_t)m * ld + cell0 + c] = (T)(s * minv[m]);
 }
 
 // ---------------------------------------------------------------------------
@@ -809,10 +833,10 @@ struct LauncherImpl : Launcher {
   }
   void project(const double* prim, int64_t cell0, int64_t ncell, void* w, const Grid& g, const SchemeParams& sp,
                hipStream_t s) override {
-    const int64_t total = (int64_t)C::NMODES * ncell;
-    const int npts = (D == 2) ? (DEG + 3) * (DEG + 3) : (DEG + 3) * (DEG + 3) * (DEG + 3);
-    k_project<T, D, DEG, DIVB><<<(int)((total + 255) / 256), 256, 0, s>>>(prim, cell0, ncell, (T*)w, vpw, pvpw,
-                                                                         minv64, npts, g.ld, sp.gamma);
+    constexpr int TC = ProjTile<D, DEG>::TC;
+    if (ncell <= 0) return;
+    k_project<T, D, DEG, DIVB><<<(unsigned)((ncell + TC - 1) / TC), 256, 0, s>>>(prim, cell0, ncell, (T*)w, vpw,
+                                                                                pvpw, minv64, g.ld, sp.gamma);
   }
   void limit(void* w, void* scratch, const Grid& g, Scal* sc, const SchemeParams& sp, hipStream_t s) override {
     launch_limit<T, D, DEG, DIVB>(w, scratch, tb, g, sc, sp, s);
