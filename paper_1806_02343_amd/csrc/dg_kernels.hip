@@ -426,6 +426,191 @@ __global__ void __launch_bounds__(NT)
   }
 }
 
+// ---------------------------------------------------------------------------
+// Cell kernel on the matrix cores (GLM, uniform grids).
+//
+// One wave owns 16 cells; every contraction of the weak form is a chain of
+// 16x16x4 matrix products with the 16 cells as the column index:
+//   nodal values   U_v[q][c]  = sum_n V[q][n] w_v[n][c]              (K = modes)
+//   volume term    R_v[n][c] += sum_{a,q} GW_a[q][n] f_a,v(U(q,c))   (K = points)
+//   surface term   R_v[n][c] += sum_k LFs[n][k] Fhat_v[k][c]         (K = face points)
+// The accumulator layout of the nodal product (lane l, element r: point
+// 16 rt + row(l/16, r), cell l % 16) is the B-operand layout of the volume
+// product once its K index runs over the same points, so fluxes go from the
+// nodal accumulators straight into the next product without any exchange;
+// the table operands are stored in that lane order ("fragment order").
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // accumulator row held by element r of a lane in k-group k = lane / 16
+  static constexpr __host__ __device__ int row(int k, int r) { return k + 4 * r; }
+};
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static constexpr __host__ __device__ int row(int k, int r) { return 4 * k + r; }
+};
+
+template <int D, int DEG>
+struct MfmaShape {
+  using C = Cfg<D, DEG, GLM>;
+  static constexpr int NKS = (C::N + 3) / 4;            // k-steps of the nodal product
+  static constexpr int QT = (C::Q + 15) / 16;           // 16-point row tiles
+  static constexpr int NMT = (C::N + 15) / 16;          // 16-mode row tiles of the result
+  static constexpr int KS = (2 * D * C::FP + 3) / 4;    // k-steps of the surface product
+  static constexpr int SZ_V = QT * NKS * 64;
+  static constexpr int SZ_G = D * NMT * QT * 4 * 64;
+  static constexpr int SZ_L = NMT * KS * 64;
+};
+
+// Fragment-order tables from the plain tables V[q][n], GW[a][q][n] and
+// LF[a][side][r][n] (row-major, as uploaded for the other kernels).
+template <typename T, int D, int DEG>
+void mfma_tables(const Tables& t, std::vector<double>& fv, std::vector<double>& fg, std::vector<double>& fl) {
+  using C = Cfg<D, DEG, GLM>;
+  using S = MfmaShape<D, DEG>;
+  constexpr int N = C::N, Q = C::Q, FP = C::FP;
+  fv.assign(S::SZ_V, 0.0);
+  fg.assign(S::SZ_G, 0.0);
+  fl.assign(S::SZ_L, 0.0);
+  for (int rt = 0; rt < S::QT; ++rt)
+    for (int s = 0; s < S::NKS; ++s)
+      for (int l = 0; l < 64; ++l) {
+        const int q = 16 * rt + l % 16, n = 4 * s + l / 16;
+        if (q < Q && n < N) fv[(rt * S::NKS + s) * 64 + l] = t.V[q * N + n];
+      }
+  for (int a = 0; a < D; ++a)
+    for (int mt = 0; mt < S::NMT; ++mt)
+      for (int rt = 0; rt < S::QT; ++rt)
+        for (int j = 0; j < 4; ++j)
+          for (int l = 0; l < 64; ++l) {
+            const int q = 16 * rt + Mfma<T>::row(l / 16, j), n = 16 * mt + l % 16;
+            if (q < Q && n < N) fg[((((a * S::NMT + mt) * S::QT + rt) * 4 + j) * 64) + l] = t.GW[(a * Q + q) * N + n];
+          }
+  for (int mt = 0; mt < S::NMT; ++mt)
+    for (int s = 0; s < S::KS; ++s)
+      for (int l = 0; l < 64; ++l) {
+        const int k = 4 * s + l / 16, n = 16 * mt + l % 16;
+        if (k >= 2 * D * FP || n >= N) continue;
+        const int a = k / (2 * FP), side = (k / FP) % 2, r = k % FP;
+        const double v = t.LF[((a * 2 + side) * FP + r) * N + n];
+        fl[(mt * S::KS + s) * 64 + l] = side ? -v : v;
+      }
+}
+
+template <typename T, int D, int DEG, int NW>
+__global__ void __launch_bounds__(64 * NW)
+    k_cell_mfma(const T* w, const T* w0, T* out, const T* __restrict__ ff, const T* __restrict__ FV,
+                const T* __restrict__ FG, const T* __restrict__ FL, const T* __restrict__ Minv, Grid g,
+                const Scal* __restrict__ sc, double gamma, double a0, double b0, int mode) {
+  using C = Cfg<D, DEG, GLM>;
+  using S = MfmaShape<D, DEG>;
+  using M = Mfma<T>;
+  using v4 = typename M::v4;
+  constexpr int N = C::N, Q = C::Q, FP = C::FP, NV = 9;
+  const int lane = threadIdx.x & 63;
+  const int64_t c0 = ((int64_t)blockIdx.x * NW + (threadIdx.x >> 6)) * 16;
+  if (c0 >= g.C) return;  // whole wave; the kernel has no barrier
+  const int kq = lane >> 4, cl = lane & 15;
+  const int64_t K = c0 + cl;
+  const bool live = K < g.C;
+  const int64_t Kc = live ? K : c0;  // ragged tail: dead lanes read a live cell, write nothing
+  const int64_t ld = g.ld;
+  const T ch = (T)sc->ch;
+  const T ch2 = ch * ch;
+  v4 R[NV][S::NMT];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int mt = 0; mt < S::NMT; ++mt) R[v][mt] = v4{0, 0, 0, 0};
+
+  for (int rt = 0; rt < S::QT; ++rt) {
+    v4 U[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) U[v] = v4{0, 0, 0, 0};
+#pragma unroll 1
+    for (int s = 0; s < S::NKS; ++s) {
+      const T a = FV[(rt * S::NKS + s) * 64 + lane];
+      const int n = 4 * s + kq;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const T b = n < N ? w[(int64_t)(v * N + n) * ld + Kc] : T(0);
+        U[v] = M::mma(a, b, U[v]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bool qv = 16 * rt + M::row(kq, j) < Q;
+      T u[9];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) u[v] = U[v][j];
+      if (!qv) {  // padding point: a harmless state, its flux is zeroed below
+        u[0] = T(1);
+        u[4] = T(1);
+      }
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        T f[9];
+        mhd_flux<T, NV>(u, a, gamma, ch2, f);
+#pragma unroll
+        for (int mt = 0; mt < S::NMT; ++mt) {
+          const T ga = FG[((((a * S::NMT + mt) * S::QT + rt) * 4 + j) * 64) + lane];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) R[v][mt] = M::mma(ga, qv ? f[v] : T(0), R[v][mt]);
+        }
+      }
+    }
+  }
+#pragma unroll 1
+  for (int s = 0; s < S::KS; ++s) {
+    const int k = 4 * s + kq;
+    const bool kv = k < 2 * D * FP;
+    const int a = kv ? k / (2 * FP) : 0, side = (k / FP) % 2, r = k % FP;
+    const int64_t Kf = side ? Kc : nbr(Kc, a, -1, g);
+    T fv[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) fv[v] = kv ? ff[((int64_t)(a * NV + v) * FP + r) * ld + Kf] : T(0);
+#pragma unroll
+    for (int mt = 0; mt < S::NMT; ++mt) {
+      const T la = FL[(mt * S::KS + s) * 64 + lane];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) R[v][mt] = M::mma(la, fv[v], R[v][mt]);
+    }
+  }
+  if (!live) return;
+  const double dt = sc->dt;
+  const T kappa = (T)sc->kappa;
+  const T two_h = T(2.0 / g.h);
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int mt = 0; mt < S::NMT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int n = 16 * mt + M::row(kq, r);
+        if (n >= N) continue;
+        const int m = v * N + n;
+        T dw = R[v][mt][r] * two_h * Minv[m];
+        const T wm = w[(int64_t)m * ld + K];
+        if (v == 8) dw -= kappa * wm;
+        if (mode == 0) {
+          out[(int64_t)m * ld + K] = dw;
+        } else {
+          const T base = w0[(int64_t)m * ld + K];
+          out[(int64_t)m * ld + K] = (T)a0 * base + (T)b0 * (wm + (T)dt * dw);
+        }
+      }
+}
+
 // tile-shape variants of the cell kernel offered to the autotuner
 template <typename T, int D, int DEG, int DIVB>
 struct CellVariants {
@@ -715,6 +900,7 @@ struct LauncherImpl : Launcher {
   std::vector<void*> bufs;
   DevTab<T> tb{};
   double *vpw = nullptr, *pvpw = nullptr, *minv64 = nullptr;
+  const T *mfv = nullptr, *mfg = nullptr, *mfl = nullptr;  // fragment-order tables of the matrix-core cell kernel
 
   template <typename U>
   hipError_t up(const std::vector<double>& src, const U*& dst) {
@@ -743,6 +929,13 @@ struct LauncherImpl : Launcher {
     pvpw = (double*)d1;
     if ((e = up<double>(t.Minv, d1)) != hipSuccess) return e;
     minv64 = (double*)d1;
+    if constexpr (DIVB == GLM) {
+      std::vector<double> fv, fg, fl;
+      mfma_tables<T, D, DEG>(t, fv, fg, fl);
+      if ((e = up<T>(fv, mfv)) != hipSuccess) return e;
+      if ((e = up<T>(fg, mfg)) != hipSuccess) return e;
+      if ((e = up<T>(fl, mfl)) != hipSuccess) return e;
+    }
     return hipSuccess;
   }
   void free_tables() override {
@@ -772,6 +965,20 @@ struct LauncherImpl : Launcher {
   }
   int cell_variant = -1;  // -1: default
 
+  // variants 4, 5: the matrix-core cell kernel with 4 or 2 waves per workgroup
+  static constexpr int NVAR = 6;
+  template <int NW>
+  bool launch_cell_mfma(const void* w, const void* w0, void* out, const void* ff, const Grid& g, const Scal* sc,
+                        const SchemeParams& sp, double a0, double b0, int mode, hipStream_t s) {
+    if constexpr (DIVB == GLM) {
+      if (g.level) return false;
+      const int64_t tiles = (g.C + 15) / 16;
+      k_cell_mfma<T, D, DEG, NW><<<(unsigned)((tiles + NW - 1) / NW), 64 * NW, 0, s>>>(
+          (const T*)w, (const T*)w0, (T*)out, (const T*)ff, mfv, mfg, mfl, tb.Minv, g, sc, sp.gamma, a0, b0, mode);
+      return true;
+    }
+    return false;
+  }
   template <int V>
   bool launch_cell_v(const void* w, const void* w0, void* out, const void* ff, const void* jp, const Grid& g,
                      const Scal* sc, const SchemeParams& sp, double a0, double b0, int mode, hipStream_t s) {
@@ -799,16 +1006,24 @@ struct LauncherImpl : Launcher {
       case 1: return CellTile<T, D, DEG, DIVB, CellVariants<T, D, DEG, DIVB>::tc(1), CellVariants<T, D, DEG, DIVB>::nt(1)>::valid;
       case 2: return CellTile<T, D, DEG, DIVB, CellVariants<T, D, DEG, DIVB>::tc(2), CellVariants<T, D, DEG, DIVB>::nt(2)>::valid;
       case 3: return CellTile<T, D, DEG, DIVB, CellVariants<T, D, DEG, DIVB>::tc(3), CellVariants<T, D, DEG, DIVB>::nt(3)>::valid;
+      case 4:
+      case 5: return DIVB == GLM;
       default: return false;
     }
   }
-  int cell_variant_count() const override { return CellVariants<T, D, DEG, DIVB>::count; }
+  int cell_variant_count() const override { return NVAR; }
   void set_cell_variant(int v) override { cell_variant = v; }
   int get_cell_variant() const override { return cell_variant; }
   void cell(const void* w, const void* w0, void* out, const void* ff, const void* jp, const Grid& g, const Scal* sc,
             const SchemeParams& sp, double a0, double b0, int mode, hipStream_t s) override {
     int v = cell_variant;
     if (v < 0 || !cell_variant_valid(v)) {
+      v = 0;
+      while (v < 4 && !cell_variant_valid(v)) ++v;
+    }
+    if (v == 4 && launch_cell_mfma<4>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
+    if (v == 5 && launch_cell_mfma<2>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
+    if (v >= 4) {  // octree grids: the matrix-core kernel covers uniform grids only
       v = 0;
       while (v < 4 && !cell_variant_valid(v)) ++v;
     }

@@ -128,8 +128,11 @@ def test_step_is_deterministic():
     assert torch.equal(wg, w2)
 
 
-@pytest.mark.parametrize("case", [(3, 2, 6, dg.GLM), (3, 3, 5, dg.GLM), (3, 2, 6, dg.POWELL), (2, 2, 12, dg.GLM)],
-                         ids=ids)
+VARIANT_CASES = [(3, 2, 6, dg.GLM), (3, 3, 5, dg.GLM), (3, 1, 7, dg.GLM), (3, 2, 6, dg.POWELL), (2, 2, 12, dg.GLM),
+                 (2, 3, 9, dg.GLM), (2, 1, 11, dg.GLM)]
+
+
+@pytest.mark.parametrize("case", VARIANT_CASES, ids=ids)
 def test_every_cell_tile_variant_matches_oracle(case):
     """Each tile shape the autotuner may pick gives the same right-hand side."""
     D, d, n, divb = case
@@ -138,7 +141,7 @@ def test_every_cell_tile_variant_matches_oracle(case):
     dt, ch, kappa = orc.timestep(wo)
     r_o = orc.rhs(wo, ch, kappa)
     ran = 0
-    for v in range(4):
+    for v in range(6):
         try:
             gpu.autotune(wg, variant=v)
         except Exception:
@@ -151,4 +154,28 @@ def test_every_cell_tile_variant_matches_oracle(case):
         ran += 1
     assert ran >= 2
     chosen = gpu.autotune(wg)
-    assert 0 <= chosen < 4
+    assert 0 <= chosen < 6
+
+
+@pytest.mark.parametrize("case", [c for c in VARIANT_CASES if c[3] == dg.GLM], ids=ids)
+def test_every_cell_variant_fp32(case):
+    """FP32 right-hand sides of every cell-kernel variant (LDS-tiled and
+    matrix-core) against the oracle, block-relative error below 1e-4."""
+    D, d, n, divb = case
+    _announce("variants fp32", case)
+    gpu, wg, orc, wo = make_pair(D, d, n, divb, precision=1)
+    dt, ch, kappa = orc.timestep(wo)
+    r_o = orc.rhs(wo, ch, kappa)
+    ran = 0
+    for v in range(6):
+        try:
+            gpu.autotune(wg, variant=v)
+        except Exception:
+            continue
+        out = gpu.empty_state()
+        gpu.rhs(wg, out, ch, kappa)
+        torch.cuda.synchronize()
+        err = block_rel_max(to_cells(out, orc.mesh.ncells), r_o, orc)
+        assert np.all(err < 1e-4), (v, err)
+        ran += 1
+    assert ran >= 4
