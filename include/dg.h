@@ -206,14 +206,19 @@ int dg_mlp_train(dg_handle h, const void* X, const float* y, int64_t nrows, int3
  * only the handle's workspaces.  Synchronous. */
 int dg_time_kernel(dg_handle h, const void* w, int32_t which, int32_t reps, double* ms /*[host]*/);
 
-/* Tile-shape autotuner of the cell kernel (cells per block x threads per
- * block).  *variant >= 0 forces that variant (DG_EINVAL if it is not built
- * for this configuration); *variant < 0 times every built variant on the
- * state w (read only; the handle's workspaces are written) and keeps the
- * fastest.  cache_path (may be NULL): a JSON file of earlier choices keyed by
- * precision, dimension, degree, divergence scheme and cell count; an entry
- * found there is used without timing and new choices are appended.  On
- * return *variant holds the variant in use.  Synchronous. */
+/* Autotuner of the kernel schedule.  A schedule is cell variant + 16 x face
+ * variant.  Cell variants: 0-3 LDS-tiled kernels (cells per block x threads
+ * per block: 16x256, 32x256, 32x512, 64x512), 4-5 matrix-core kernel (4 or 2
+ * waves of 16 cells per block; GLM on uniform grids, elsewhere variant 0
+ * runs).  Face variants: 0 LDS-staged, 1 matrix-core (GLM).  *variant >= 0
+ * forces that schedule (DG_EINVAL if it is not built for this
+ * configuration); *variant < 0 times every built cell variant, then every
+ * face variant, on the state w (read only; the handle's workspaces are
+ * written) and keeps the fastest of each.  cache_path (may be NULL): a JSON
+ * file of earlier choices keyed by precision, dimension, degree, divergence
+ * scheme and cell count; an entry found there is used without timing and new
+ * choices are appended.  On return *variant holds the schedule in use.
+ * Synchronous. */
 int dg_autotune(dg_handle h, const void* w, const char* cache_path, int32_t* variant /*[host] in/out*/);
 
 const char* dg_last_error(dg_handle h);

@@ -496,7 +496,7 @@ int dg_time_kernel(dg_handle h, const void* w, int32_t which, int32_t reps, doub
 
 static std::string tune_key(dg_handle h) {
   std::ostringstream k;
-  k << "cell/p" << h->p.precision << "/D" << h->p.dim << "/d" << h->p.degree << "/b" << h->p.divb << "/C" << h->g.C;
+  k << "sched/p" << h->p.precision << "/D" << h->p.dim << "/d" << h->p.degree << "/b" << h->p.divb << "/C" << h->g.C;
   return k.str();
 }
 
@@ -540,27 +540,36 @@ static void tune_cache_store(const char* path, const std::string& key, int v, do
   (void)ms;
 }
 
+// A schedule is (cell variant) + 16 x (face variant).
+static bool schedule_valid(Launcher* L, int v) {
+  const int cv = v & 15, fv = v >> 4;
+  return v >= 0 && cv < L->cell_variant_count() && L->cell_variant_valid(cv) && fv < L->face_variant_count();
+}
+
+static void set_schedule(dg_handle h, int v) {
+  h->L->set_cell_variant(v & 15);
+  h->L->set_face_variant(v >> 4);
+  drop_graph(h);
+}
+
 int dg_autotune(dg_handle h, const void* w, const char* cache_path, int32_t* variant) {
   if (int r = valid_state(h, w)) return r;
   if (!variant) return fail(h, DG_EINVAL, "null variant");
   Launcher* L = h->L;
   if (*variant >= 0) {
-    if (*variant >= L->cell_variant_count() || !L->cell_variant_valid(*variant))
-      return fail(h, DG_EINVAL, "cell variant not built for this configuration");
-    L->set_cell_variant(*variant);
-    drop_graph(h);
+    if (!schedule_valid(L, *variant)) return fail(h, DG_EINVAL, "kernel variant not built for this configuration");
+    set_schedule(h, *variant);
     return DG_OK;
   }
   const std::string key = tune_key(h);
   int cached = -1;
-  if (cache_path && tune_cache_lookup(cache_path, key, cached) && cached >= 0 && cached < L->cell_variant_count() &&
-      L->cell_variant_valid(cached)) {
-    L->set_cell_variant(cached);
-    drop_graph(h);
+  if (cache_path && tune_cache_lookup(cache_path, key, cached) && schedule_valid(L, cached)) {
+    set_schedule(h, cached);
     *variant = cached;
     return DG_OK;
   }
-  int best = -1;
+  // cell and face kernels are independent: tune each on its own
+  int best_c = -1, best_f = 0;
   double best_ms = 1e300;
   for (int v = 0; v < L->cell_variant_count(); ++v) {
     if (!L->cell_variant_valid(v)) continue;
@@ -568,13 +577,22 @@ int dg_autotune(dg_handle h, const void* w, const char* cache_path, int32_t* var
     double ms = 0.0;
     if (int r = dg_time_kernel(h, w, 1, 1, &ms)) return r;  // warm-up
     if (int r = dg_time_kernel(h, w, 1, 3, &ms)) return r;
-    if (ms < best_ms) { best_ms = ms; best = v; }
+    if (ms < best_ms) { best_ms = ms; best_c = v; }
   }
-  if (best < 0) return fail(h, DG_EUNSUPPORTED, "no cell variant built");
-  L->set_cell_variant(best);
-  drop_graph(h);
+  if (best_c < 0) return fail(h, DG_EUNSUPPORTED, "no cell variant built");
+  L->set_cell_variant(best_c);
+  double best_fms = 1e300;
+  for (int v = 0; v < L->face_variant_count(); ++v) {
+    L->set_face_variant(v);
+    double ms = 0.0;
+    if (int r = dg_time_kernel(h, w, 0, 1, &ms)) return r;
+    if (int r = dg_time_kernel(h, w, 0, 3, &ms)) return r;
+    if (ms < best_fms) { best_fms = ms; best_f = v; }
+  }
+  const int best = best_c + 16 * best_f;
+  set_schedule(h, best);
   *variant = best;
-  if (cache_path) tune_cache_store(cache_path, key, best, best_ms);
+  if (cache_path) tune_cache_store(cache_path, key, best, best_ms + best_fms);
   return DG_OK;
 }
 

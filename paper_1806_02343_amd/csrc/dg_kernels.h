@@ -70,6 +70,9 @@ struct Launcher {
   virtual bool cell_variant_valid(int v) const = 0;
   virtual void set_cell_variant(int v) = 0;
   virtual int get_cell_variant() const = 0;
+  virtual int face_variant_count() const = 0;
+  virtual void set_face_variant(int v) = 0;
+  virtual int get_face_variant() const = 0;
   // per-cell signal speeds -> atomic maxima in sc
   virtual void maxsig(const void* w, const Grid& g, Scal* sc, const SchemeParams& sp, hipStream_t s) = 0;
   // Powell dt cap: per-face normal-field jumps then per-cell rate

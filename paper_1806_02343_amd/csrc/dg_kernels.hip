@@ -611,6 +611,88 @@ __global__ void __launch_bounds__(64 * NW)
       }
 }
 
+// Face kernel on the matrix cores (GLM, uniform grids): one wave owns 16
+// faces of one axis; the traces of both sides at the face points are 16x16x4
+// products of the trace tables with the two cells' modes (faces as columns),
+// and each lane then solves the Riemann problems of its four face points.
+template <int D, int DEG>
+struct MfmaFaceShape {
+  using C = Cfg<D, DEG, GLM>;
+  static constexpr int NKS = (C::N + 3) / 4;
+  static constexpr int SZ = D * 2 * NKS * 64;
+  static_assert(C::FP <= 16, "face points per face fit one 16-row tile");
+};
+
+template <typename T, int D, int DEG>
+void mfma_face_tables(const Tables& t, std::vector<double>& ft) {
+  using C = Cfg<D, DEG, GLM>;
+  using S = MfmaFaceShape<D, DEG>;
+  ft.assign(S::SZ, 0.0);
+  for (int a = 0; a < D; ++a)
+    for (int side = 0; side < 2; ++side)
+      for (int s = 0; s < S::NKS; ++s)
+        for (int l = 0; l < 64; ++l) {
+          const int r = l % 16, n = 4 * s + l / 16;
+          if (r < C::FP && n < C::N) ft[((a * 2 + side) * S::NKS + s) * 64 + l] = t.TF[((a * 2 + side) * C::FP + r) * C::N + n];
+        }
+}
+
+template <typename T, int D, int DEG, int NW>
+__global__ void __launch_bounds__(64 * NW) k_face_mfma(const T* __restrict__ w, T* __restrict__ ff,
+                                                       const T* __restrict__ FT, Grid g,
+                                                       const Scal* __restrict__ sc, double gamma) {
+  using C = Cfg<D, DEG, GLM>;
+  using S = MfmaFaceShape<D, DEG>;
+  using M = Mfma<T>;
+  using v4 = typename M::v4;
+  constexpr int N = C::N, FP = C::FP, NV = 9;
+  const int a = blockIdx.y;
+  const int lane = threadIdx.x & 63;
+  const int64_t f0 = ((int64_t)blockIdx.x * NW + (threadIdx.x >> 6)) * 16;
+  if (f0 >= g.C) return;  // whole wave; no barrier in this kernel
+  const int kq = lane >> 4, cl = lane & 15;
+  const int64_t F = f0 + cl;
+  const bool live = F < g.C;
+  const int64_t FL = live ? F : f0;           // face F lies between cells F (left) and its +a neighbour
+  const int64_t FR = nbr(FL, a, +1, g);
+  const int64_t ld = g.ld;
+  v4 UL[NV], UR[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    UL[v] = v4{0, 0, 0, 0};
+    UR[v] = v4{0, 0, 0, 0};
+  }
+#pragma unroll 1
+  for (int s = 0; s < S::NKS; ++s) {
+    const T tl = FT[((a * 2 + 1) * S::NKS + s) * 64 + lane];
+    const T tr = FT[((a * 2 + 0) * S::NKS + s) * 64 + lane];
+    const int n = 4 * s + kq;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const T bl = n < N ? w[(int64_t)(v * N + n) * ld + FL] : T(0);
+      const T br = n < N ? w[(int64_t)(v * N + n) * ld + FR] : T(0);
+      UL[v] = M::mma(tl, bl, UL[v]);
+      UR[v] = M::mma(tr, br, UR[v]);
+    }
+  }
+  if (!live) return;
+  const T ch = (T)sc->ch;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int r = M::row(kq, j);
+    if (r >= FP) continue;
+    T uL[9], uR[9], Fx[9];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      uL[v] = UL[v][j];
+      uR[v] = UR[v][j];
+    }
+    (void)face_flux<T, NV>(uL, uR, a, gamma, ch, Fx);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ff[((int64_t)(a * NV + v) * FP + r) * ld + F] = Fx[v];
+  }
+}
+
 // tile-shape variants of the cell kernel offered to the autotuner
 template <typename T, int D, int DEG, int DIVB>
 struct CellVariants {
@@ -901,6 +983,10 @@ struct LauncherImpl : Launcher {
   DevTab<T> tb{};
   double *vpw = nullptr, *pvpw = nullptr, *minv64 = nullptr;
   const T *mfv = nullptr, *mfg = nullptr, *mfl = nullptr;  // fragment-order tables of the matrix-core cell kernel
+  const T* mft = nullptr;                                   // and of the matrix-core face kernel
+  const double* mpos = nullptr;                             // and of the matrix-core positivity limiter
+  int pos_variant = 1;                                      // 1: matrix-core positivity limiter where built
+  int face_variant = -1;                                    // -1: default (0)
 
   template <typename U>
   hipError_t up(const std::vector<double>& src, const U*& dst) {
@@ -935,6 +1021,12 @@ struct LauncherImpl : Launcher {
       if ((e = up<T>(fv, mfv)) != hipSuccess) return e;
       if ((e = up<T>(fg, mfg)) != hipSuccess) return e;
       if ((e = up<T>(fl, mfl)) != hipSuccess) return e;
+      std::vector<double> ft;
+      mfma_face_tables<T, D, DEG>(t, ft);
+      if ((e = up<T>(ft, mft)) != hipSuccess) return e;
+      std::vector<double> pt;
+      pos_tables<D, DEG>(t, pt);
+      if ((e = up<double>(pt, mpos)) != hipSuccess) return e;
     }
     return hipSuccess;
   }
@@ -958,6 +1050,15 @@ struct LauncherImpl : Launcher {
         k_face_amr<T, D, DEG><<<(unsigned)((total + 255) / 256), 256, 0, s>>>((const T*)w, (T*)ff, tb, g, sc, sp.gamma);
       }
       return;
+    }
+    if constexpr (DIVB == GLM) {
+      if (face_variant == 1) {
+        constexpr int NW = 4;
+        const int64_t tiles = (g.C + 15) / 16;
+        dim3 grid((unsigned)((tiles + NW - 1) / NW), D);
+        k_face_mfma<T, D, DEG, NW><<<grid, 64 * NW, 0, s>>>((const T*)w, (T*)ff, mft, g, sc, sp.gamma);
+        return;
+      }
     }
     using FT = FaceTile<T, D, DEG, DIVB>;
     dim3 grid((unsigned)((g.C + FT::TF - 1) / FT::TF), D);
@@ -1012,6 +1113,10 @@ struct LauncherImpl : Launcher {
     }
   }
   int cell_variant_count() const override { return NVAR; }
+  // face variants: 0 LDS-staged, 1 matrix cores (GLM uniform grids)
+  int face_variant_count() const override { return DIVB == GLM ? 2 : 1; }
+  void set_face_variant(int v) override { face_variant = v; }
+  int get_face_variant() const override { return face_variant < 0 ? 0 : face_variant; }
   void set_cell_variant(int v) override { cell_variant = v; }
   int get_cell_variant() const override { return cell_variant; }
   void cell(const void* w, const void* w0, void* out, const void* ff, const void* jp, const Grid& g, const Scal* sc,
@@ -1054,7 +1159,7 @@ struct LauncherImpl : Launcher {
                                                                                 pvpw, minv64, g.ld, sp.gamma);
   }
   void limit(void* w, void* scratch, const Grid& g, Scal* sc, const SchemeParams& sp, hipStream_t s) override {
-    launch_limit<T, D, DEG, DIVB>(w, scratch, tb, g, sc, sp, s);
+    launch_limit<T, D, DEG, DIVB>(w, scratch, tb, pos_variant == 1 ? mpos : nullptr, g, sc, sp, s);
   }
   size_t limit_scratch_bytes(const Grid& g) const override { return limit_scratch<T, D, DEG, DIVB>(g); }
   bool mlp_features(const void* w, uint16_t* X, const double* sigma, const Grid& g, hipStream_t s) override {

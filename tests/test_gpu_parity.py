@@ -119,6 +119,21 @@ def test_config0_ten_steps_rel_l1():
     assert np.all(err < 1e-12), err
 
 
+@pytest.mark.parametrize("case", [(3, 3, 5, dg.GLM), (3, 2, 6, dg.GLM), (2, 2, 12, dg.GLM)], ids=ids)
+def test_matrix_core_schedule_steps_fp64(case):
+    """Three SSP-RK3 steps with the matrix-core cell and face kernels (schedule
+    4 + 16) against the oracle at 1e-12."""
+    D, d, n, divb = case
+    _announce("mfma steps", case)
+    gpu, wg, orc, wo = make_pair(D, d, n, divb)
+    gpu.autotune(wg, variant=4 + 16)
+    for _ in range(3):
+        wo, dt, ch, k = orc.step(wo)
+    gpu.step(wg, 3)
+    err = rel_l1(orc, to_cells(wg, orc.mesh.ncells), wo, ch=ch)
+    assert np.all(err < 1e-12), err
+
+
 def test_step_is_deterministic():
     _announce("determinism")
     gpu, wg, orc, wo = make_pair(3, 2, 6, dg.GLM)
@@ -141,7 +156,7 @@ def test_every_cell_tile_variant_matches_oracle(case):
     dt, ch, kappa = orc.timestep(wo)
     r_o = orc.rhs(wo, ch, kappa)
     ran = 0
-    for v in range(6):
+    for v in [c + 16 * f for f in (0, 1) for c in range(6)]:  # cell variant + 16 x face variant
         try:
             gpu.autotune(wg, variant=v)
         except Exception:
@@ -152,9 +167,9 @@ def test_every_cell_tile_variant_matches_oracle(case):
         err = block_rel_max(to_cells(out, orc.mesh.ncells), r_o, orc)
         assert np.all(err < 1e-12), (v, err)
         ran += 1
-    assert ran >= 2
+    assert ran >= (8 if divb == dg.GLM else 2)
     chosen = gpu.autotune(wg)
-    assert 0 <= chosen < 6
+    assert 0 <= (chosen & 15) < 6 and 0 <= (chosen >> 4) < 2
 
 
 @pytest.mark.parametrize("case", [c for c in VARIANT_CASES if c[3] == dg.GLM], ids=ids)
@@ -167,7 +182,7 @@ def test_every_cell_variant_fp32(case):
     dt, ch, kappa = orc.timestep(wo)
     r_o = orc.rhs(wo, ch, kappa)
     ran = 0
-    for v in range(6):
+    for v in [c + 16 * f for f in (0, 1) for c in range(6)]:
         try:
             gpu.autotune(wg, variant=v)
         except Exception:
@@ -178,4 +193,4 @@ def test_every_cell_variant_fp32(case):
         err = block_rel_max(to_cells(out, orc.mesh.ncells), r_o, orc)
         assert np.all(err < 1e-4), (v, err)
         ran += 1
-    assert ran >= 4
+    assert ran >= 8
