@@ -30,6 +30,10 @@ PEAK_FP32 = 157.3e12
 PEAK_HBM = 8.0e12
 L1_TOL = 1e-5
 
+# default step counts of each workload (the number of steps it is specified with)
+DEFAULT_STEPS = {"blast128": 50, "smooth64": 20, "smooth32_2d": 10, "peaks_amr": 30}
+VARS = ["rho", "mx", "my", "mz", "E", "Bx", "By", "Bz"]
+
 WORKLOADS = {
     # name: (D, d, n, divb, limiter, seed-config, description)
     "blast128": (3, 3, 128, 0, 7, 2, "3-D periodic 128^3, degree 3 (20 modes/var), GLM, 8 seeded over-pressured "
@@ -94,7 +98,7 @@ def make_handle(D, d, n, divb, limiter, prec, stream, octree=None, ch=0.0, lo=0.
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's own count)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="blast128", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -113,6 +117,8 @@ def main():
     from paper_1806_02343_amd import DG_LIM_LEARNED
 
     D, d, n, divb, limiter, cfg, desc = WORKLOADS[args.workload]
+    if args.steps is None:
+        args.steps = DEFAULT_STEPS[args.workload]
     stream = torch.cuda.Stream()          # non-null stream: each step replays one captured hipGraph
     torch.cuda.set_stream(stream)
     octree, ch = None, 0.0
@@ -190,7 +196,9 @@ def main():
     ncells = r64["gpu"].ncells
     flops_launch = cell_flops(D, d, divb) * ncells
     achieved = flops_launch / (r64["k_cell"] / 1e3)
-    roof = {"kernel": "k_cell", "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
+    mfma = (r64["variant"] & 15) >= 4
+    roof = {"kernel": "k_cell_mfma" if mfma else "k_cell", "bound": "mfma" if mfma else "alu",
+            "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
             "ms_per_launch": r64["k_cell"], "flops_per_launch": flops_launch}
     line = {
@@ -217,6 +225,7 @@ def main():
             if divb == 0:
                 rel, per = rel_l1_modal(r["w"][:, :ncells], r64["w"][:, :ncells], r64["gpu"].nmodes // 9)
                 ent["rel_l1_vs_fp64"] = rel
+                ent["rel_l1_per_var"] = dict(zip(VARS, per))
                 ent["within_l1_tol"] = rel <= L1_TOL
             line[tag] = ent
     if learned_info:

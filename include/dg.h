@@ -88,7 +88,8 @@ typedef struct {
 } dg_params;
 
 /* Mesh on the periodic box [0, box]^dim.  kind == DG_MESH_UNIFORM: n[0..dim)
- * cells per axis, cubic cells (box[a]/n[a] equal).  kind == DG_MESH_OCTREE:
+ * cells per axis, cubic cells (box[a]/n[a] equal), at most 2^31 - 1 cells
+ * (DG_EINVAL beyond).  kind == DG_MESH_OCTREE:
  * n[] is the level-0 grid, and leaf c has refinement level level[c] >= 0 and
  * integer coordinates ijk[3c..3c+2] on the grid of that level (host arrays,
  * copied by dg_init).  Leaves must tile the box and be 2:1 balanced across
@@ -208,9 +209,10 @@ int dg_time_kernel(dg_handle h, const void* w, int32_t which, int32_t reps, doub
 
 /* Autotuner of the kernel schedule.  A schedule is cell variant + 16 x face
  * variant.  Cell variants: 0-3 LDS-tiled kernels (cells per block x threads
- * per block: 16x256, 32x256, 32x512, 64x512), 4-5 matrix-core kernel (4 or 2
- * waves of 16 cells per block; GLM on uniform grids, elsewhere variant 0
- * runs).  Face variants: 0 LDS-staged, 1 matrix-core (GLM).  *variant >= 0
+ * per block: 16x256, 32x256, 32x512, 64x512), 4-7 matrix-core kernel (4 or 2
+ * waves of 16 cells per block, 6-7 with operand prefetch; GLM on uniform
+ * grids, elsewhere variant 0 runs).  Face variants: 0 LDS-staged, 1 matrix-core (GLM; also selects the
+ * matrix-core max-signal-speed reduction of the time step).  *variant >= 0
  * forces that schedule (DG_EINVAL if it is not built for this
  * configuration); *variant < 0 times every built cell variant, then every
  * face variant, on the state w (read only; the handle's workspaces are

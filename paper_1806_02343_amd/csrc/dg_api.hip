@@ -235,6 +235,11 @@ int dg_init(const dg_params* p, const dg_mesh* m, void* hip_stream, dg_handle* o
   for (int a = 1; a < p->dim; ++a)
     if (std::fabs(m->box[a] / m->n[a] - m->box[0] / m->n[0]) > 1e-12 * m->box[0] / m->n[0])
       return fail(nullptr, DG_EINVAL, "cells must be cubic");
+  {
+    int64_t nc = 1;
+    for (int a = 0; a < p->dim; ++a) nc *= m->n[a];
+    if (nc > INT32_MAX) return fail(nullptr, DG_EINVAL, "more than 2^31 - 1 cells on the base grid");
+  }
 
   dg_handle h = new (std::nothrow) dg_handle_s();
   if (!h) return fail(nullptr, DG_ENOMEM, "host allocation");

@@ -63,15 +63,20 @@ __device__ __forceinline__ double cell_h(const Grid& g, int64_t K) {
   return g.level ? g.hbase / (double)(1 << g.level[K]) : g.h;
 }
 
+// Periodic face neighbour of cell K along axis a (s = +1 or -1) on a uniform
+// grid; cell indices fit 32 bits (dg_init rejects larger grids), so the index
+// arithmetic is unsigned 32-bit.
 __device__ __forceinline__ int64_t nbr(int64_t K, int a, int s, const Grid& g) {
-  int64_t i = K % g.n0;
-  int64_t t = K / g.n0;
-  int64_t j = t % g.n1;
-  int64_t k = t / g.n1;
-  if (a == 0) i = (i + s + g.n0) % g.n0;
-  else if (a == 1) j = (j + s + g.n1) % g.n1;
-  else k = (k + s + g.n2) % g.n2;
-  return i + (int64_t)g.n0 * (j + (int64_t)g.n1 * k);
+  const uint32_t n0 = (uint32_t)g.n0, n1 = (uint32_t)g.n1, n2 = (uint32_t)g.n2;
+  const uint32_t k32 = (uint32_t)K;
+  uint32_t i = k32 % n0;
+  const uint32_t t = k32 / n0;
+  uint32_t j = t % n1;
+  uint32_t k = t / n1;
+  if (a == 0) i = s > 0 ? (i + 1 == n0 ? 0u : i + 1) : (i == 0 ? n0 - 1 : i - 1);
+  else if (a == 1) j = s > 0 ? (j + 1 == n1 ? 0u : j + 1) : (j == 0 ? n1 - 1 : j - 1);
+  else k = s > 0 ? (k + 1 == n2 ? 0u : k + 1) : (k == 0 ? n2 - 1 : k - 1);
+  return (int64_t)i + (int64_t)n0 * ((int64_t)j + (int64_t)n1 * k);
 }
 
 __device__ __forceinline__ void atomic_max_pos(unsigned long long* addr, double v) {
@@ -507,7 +512,7 @@ void mfma_tables(const Tables& t, std::vector<double>& fv, std::vector<double>& 
       }
 }
 
-template <typename T, int D, int DEG, int NW>
+template <typename T, int D, int DEG, int NW, bool PF>
 __global__ void __launch_bounds__(64 * NW)
     k_cell_mfma(const T* w, const T* w0, T* out, const T* __restrict__ ff, const T* __restrict__ FV,
                 const T* __restrict__ FG, const T* __restrict__ FL, const T* __restrict__ Minv, Grid g,
@@ -537,14 +542,33 @@ __global__ void __launch_bounds__(64 * NW)
     v4 U[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) U[v] = v4{0, 0, 0, 0};
+    // operands of the next k-step are loaded while the current products run
+    T bc[NV], bn[NV];
+    T ac = T(0), an = T(0);
+    if (PF) {
+      ac = FV[(rt * S::NKS) * 64 + lane];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) bc[v] = kq < N ? w[(int64_t)(v * N + kq) * ld + Kc] : T(0);
+    }
 #pragma unroll 1
     for (int s = 0; s < S::NKS; ++s) {
-      const T a = FV[(rt * S::NKS + s) * 64 + lane];
-      const int n = 4 * s + kq;
+      if (!PF) {  // no prefetch: load this step's operands now
+        const int n = 4 * s + kq;
+        ac = FV[(rt * S::NKS + s) * 64 + lane];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const T b = n < N ? w[(int64_t)(v * N + n) * ld + Kc] : T(0);
-        U[v] = M::mma(a, b, U[v]);
+        for (int v = 0; v < NV; ++v) bc[v] = n < N ? w[(int64_t)(v * N + n) * ld + Kc] : T(0);
+      } else if (s + 1 < S::NKS) {
+        const int n = 4 * (s + 1) + kq;
+        an = FV[(rt * S::NKS + s + 1) * 64 + lane];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) bn[v] = n < N ? w[(int64_t)(v * N + n) * ld + Kc] : T(0);
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) U[v] = M::mma(ac, bc[v], U[v]);
+      if (PF) {
+        ac = an;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) bc[v] = bn[v];
       }
     }
 #pragma unroll
@@ -570,20 +594,34 @@ __global__ void __launch_bounds__(64 * NW)
       }
     }
   }
-#pragma unroll 1
-  for (int s = 0; s < S::KS; ++s) {
+  // face values of k-step s (face point k = 4 s + kq: axis, side, point)
+  auto load_face = [&](int s, T* fv, T* la) {
     const int k = 4 * s + kq;
     const bool kv = k < 2 * D * FP;
     const int a = kv ? k / (2 * FP) : 0, side = (k / FP) % 2, r = k % FP;
     const int64_t Kf = side ? Kc : nbr(Kc, a, -1, g);
-    T fv[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) fv[v] = kv ? ff[((int64_t)(a * NV + v) * FP + r) * ld + Kf] : T(0);
 #pragma unroll
-    for (int mt = 0; mt < S::NMT; ++mt) {
-      const T la = FL[(mt * S::KS + s) * 64 + lane];
+    for (int mt = 0; mt < S::NMT; ++mt) la[mt] = FL[(mt * S::KS + s) * 64 + lane];
+  };
+  {
+    T fc[NV], fn[NV], lc[S::NMT], ln[S::NMT];
+    if (PF) load_face(0, fc, lc);
+#pragma unroll 1
+    for (int s = 0; s < S::KS; ++s) {
+      if (!PF) load_face(s, fc, lc);
+      else if (s + 1 < S::KS) load_face(s + 1, fn, ln);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) R[v][mt] = M::mma(la, fv[v], R[v][mt]);
+      for (int mt = 0; mt < S::NMT; ++mt)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) R[v][mt] = M::mma(lc[mt], fc[v], R[v][mt]);
+      if (PF) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) fc[v] = fn[v];
+#pragma unroll
+        for (int mt = 0; mt < S::NMT; ++mt) lc[mt] = ln[mt];
+      }
     }
   }
   if (!live) return;
@@ -690,6 +728,78 @@ __global__ void __launch_bounds__(64 * NW) k_face_mfma(const T* __restrict__ w, 
     (void)face_flux<T, NV>(uL, uR, a, gamma, ch, Fx);
 #pragma unroll
     for (int v = 0; v < NV; ++v) ff[((int64_t)(a * NV + v) * FP + r) * ld + F] = Fx[v];
+  }
+}
+
+// Max signal speed on the matrix cores (GLM, uniform grids): one wave
+// evaluates 16 cells at every volume point (row tiles of the nodal table)
+// and face point (row tiles of the trace tables) with 16x16x4 products in the
+// state's precision, the modes held in registers; wave and block maxima
+// (NaN-propagating) feed one atomic per block.
+template <typename T, int D, int DEG, int NW>
+__global__ void __launch_bounds__(64 * NW) k_maxsig_mfma(const T* __restrict__ w, const T* __restrict__ FV,
+                                                         const T* __restrict__ FT, Grid g, Scal* sc, double gamma) {
+  using C = Cfg<D, DEG, GLM>;
+  using S = MfmaShape<D, DEG>;
+  using M = Mfma<T>;
+  using v4 = typename M::v4;
+  constexpr int N = C::N;
+  __shared__ double red[NW];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t c0 = ((int64_t)blockIdx.x * NW + wid) * 16;
+  double smax = 0.0;
+  if (c0 < g.C) {
+    const int kq = lane >> 4, cl = lane & 15;
+    const int64_t K = c0 + cl;
+    const bool live = K < g.C;
+    const int64_t Kc = live ? K : c0;
+    T bw[8][S::NKS];
+#pragma unroll
+    for (int v = 0; v < 8; ++v)
+#pragma unroll
+      for (int s = 0; s < S::NKS; ++s) {
+        const int n = 4 * s + kq;
+        bw[v][s] = n < N ? w[(int64_t)(v * N + n) * g.ld + Kc] : T(0);
+      }
+#pragma unroll 1
+    for (int rt = 0; rt < S::QT + 2 * D; ++rt) {
+      v4 U[8];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) U[v] = v4{0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < S::NKS; ++s) {
+        const T a = rt < S::QT ? FV[(rt * S::NKS + s) * 64 + lane] : FT[((rt - S::QT) * S::NKS + s) * 64 + lane];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) U[v] = M::mma(a, bw[v][s], U[v]);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int i = M::row(kq, j);
+        const bool valid = live && (rt < S::QT ? (16 * rt + i < C::Q) : (i < C::FP));
+        if (!valid) continue;
+        T u[9];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) u[v] = U[v][j];
+        u[8] = T(0);
+        double sp = signal_sum<T, D>(u, gamma);
+        if (!(sp == sp)) sp = __longlong_as_double(0x7ff8000000000000ULL);
+        smax = (sp > smax || !(sp == sp)) ? sp : smax;
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double x = __shfl_xor(smax, o);
+    smax = (x > smax || !(x == x)) ? x : smax;
+  }
+  if (lane == 0) red[wid] = smax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = red[0];
+    for (int i = 1; i < NW; ++i) m = (red[i] > m || !(red[i] == red[i])) ? red[i] : m;
+    atomic_max_pos(&sc->maxsig_bits, m);
+    atomic_max_pos(&sc->maxrate_bits, m * (1.0 / g.h));
+    if (!(m == m)) atomicAdd(&sc->nonfinite, 1ULL);
   }
 }
 
@@ -1066,15 +1176,16 @@ struct LauncherImpl : Launcher {
   }
   int cell_variant = -1;  // -1: default
 
-  // variants 4, 5: the matrix-core cell kernel with 4 or 2 waves per workgroup
-  static constexpr int NVAR = 6;
-  template <int NW>
+  // variants 4, 5: the matrix-core cell kernel with 4 or 2 waves per
+  // workgroup; 6, 7: the same with operand prefetch (more registers)
+  static constexpr int NVAR = 8;
+  template <int NW, bool PF>
   bool launch_cell_mfma(const void* w, const void* w0, void* out, const void* ff, const Grid& g, const Scal* sc,
                         const SchemeParams& sp, double a0, double b0, int mode, hipStream_t s) {
     if constexpr (DIVB == GLM) {
       if (g.level) return false;
       const int64_t tiles = (g.C + 15) / 16;
-      k_cell_mfma<T, D, DEG, NW><<<(unsigned)((tiles + NW - 1) / NW), 64 * NW, 0, s>>>(
+      k_cell_mfma<T, D, DEG, NW, PF><<<(unsigned)((tiles + NW - 1) / NW), 64 * NW, 0, s>>>(
           (const T*)w, (const T*)w0, (T*)out, (const T*)ff, mfv, mfg, mfl, tb.Minv, g, sc, sp.gamma, a0, b0, mode);
       return true;
     }
@@ -1108,7 +1219,9 @@ struct LauncherImpl : Launcher {
       case 2: return CellTile<T, D, DEG, DIVB, CellVariants<T, D, DEG, DIVB>::tc(2), CellVariants<T, D, DEG, DIVB>::nt(2)>::valid;
       case 3: return CellTile<T, D, DEG, DIVB, CellVariants<T, D, DEG, DIVB>::tc(3), CellVariants<T, D, DEG, DIVB>::nt(3)>::valid;
       case 4:
-      case 5: return DIVB == GLM;
+      case 5:
+      case 6:
+      case 7: return DIVB == GLM;
       default: return false;
     }
   }
@@ -1126,8 +1239,10 @@ struct LauncherImpl : Launcher {
       v = 0;
       while (v < 4 && !cell_variant_valid(v)) ++v;
     }
-    if (v == 4 && launch_cell_mfma<4>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
-    if (v == 5 && launch_cell_mfma<2>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
+    if (v == 4 && launch_cell_mfma<4, false>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
+    if (v == 5 && launch_cell_mfma<2, false>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
+    if (v == 6 && launch_cell_mfma<4, true>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
+    if (v == 7 && launch_cell_mfma<2, true>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
     if (v >= 4) {  // octree grids: the matrix-core kernel covers uniform grids only
       v = 0;
       while (v < 4 && !cell_variant_valid(v)) ++v;
@@ -1140,6 +1255,15 @@ struct LauncherImpl : Launcher {
     }
   }
   void maxsig(const void* w, const Grid& g, Scal* sc, const SchemeParams& sp, hipStream_t s) override {
+    if constexpr (DIVB == GLM) {
+      if (!g.level && face_variant == 1) {
+        constexpr int NW = 4;
+        const int64_t tiles = (g.C + 15) / 16;
+        k_maxsig_mfma<T, D, DEG, NW><<<(unsigned)((tiles + NW - 1) / NW), 64 * NW, 0, s>>>((const T*)w, mfv, mft, g, sc,
+                                                                                          sp.gamma);
+        return;
+      }
+    }
     const int nb = (int)((g.C + TL::TC - 1) / TL::TC);
     k_maxsig<T, D, DEG, DIVB><<<nb, 256, 0, s>>>((const T*)w, tb, g, sc, sp.gamma);
   }

@@ -113,12 +113,21 @@ __global__ void k_gelu_back(const float* __restrict__ dA, const float* __restric
 }
 
 // Column sums (bias gradients), one thread per column, fixed order.
-__global__ void k_colsum(const float* __restrict__ X, int64_t rows, int N, int64_t ld, float* __restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= N) return;
+// out[c] = sum_r X[r][c]: one block of 256 threads per column, strided
+// partial sums and a fixed-order tree (deterministic).
+__global__ void __launch_bounds__(256) k_colsum(const float* __restrict__ X, int64_t rows, int N, int64_t ld,
+                                                float* __restrict__ out) {
+  __shared__ float red[256];
+  const int c = blockIdx.x;
   float s = 0.f;
-  for (int64_t r = 0; r < rows; ++r) s += X[r * ld + c];
-  out[c] = s;
+  for (int64_t r = threadIdx.x; r < rows; r += 256) s += X[r * ld + c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && c < N) out[c] = red[0];
 }
 
 __global__ void k_adam(float* __restrict__ P, const float* __restrict__ G, float* __restrict__ m,
@@ -277,7 +286,7 @@ void MlpState::backward(int64_t nvalid, hipStream_t s) {
     float* db = G + mlp_param_offset(l, true);
     // dW[fin][fout] = sum_b Ain[b][fin] dz[b][fout]
     gemm(Ain, 1, FIN[l], dzc, ldz, 1, dW, FOUT[l], FIN[l], FOUT[l], B, 0.f, s);
-    k_colsum<<<1, 64, 0, s>>>(dzf, B, l == 3 ? 1 : FOUT[l], l == 3 ? 1 : FOUT[l], db);
+    k_colsum<<<l == 3 ? 1 : FOUT[l], 256, 0, s>>>(dzf, B, l == 3 ? 1 : FOUT[l], l == 3 ? 1 : FOUT[l], db);
     if (l > 0) {
       // dA[b][fin] = sum_o dz[b][o] W[fin][o]
       const uint16_t* W = Pb + mlp_param_offset(l, false);

@@ -52,14 +52,18 @@ def false_negative_rate(gpu, X, y, n, lo):
     return fn, skip, p, lab
 
 
-def choose_lo(p, lab, target_fn=0.01):
-    """Largest gate threshold whose false-negative rate on (p, lab) stays
-    below target_fn."""
+def choose_lo(p, lab, target_fn=0.0, margin=0.5):
+    """Gate threshold: the target_fn quantile of the probabilities of the
+    plain detector's positives (target_fn = 0: the smallest), times a safety
+    margin, at most 0.5.  A skipped troubled cell is never limited
+    in that stage and its oscillation feeds the next stages, so the default
+    admits no false negative on the validation set."""
     pos = np.sort(p[lab])
     if pos.size == 0:
         return 0.5
     k = int(np.floor(target_fn * pos.size))
-    return float(max(min(pos[k] if k < pos.size else pos[-1], 0.5), 1e-4))
+    q = pos[k] if k < pos.size else pos[-1]
+    return float(min(margin * q, 0.5))
 
 
 def train_indicator(workloads, n=128, d=3, train_seeds=range(4001, 4005), val_seeds=range(4029, 4031), steps=6,

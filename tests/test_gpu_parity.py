@@ -127,6 +127,9 @@ def test_matrix_core_schedule_steps_fp64(case):
     _announce("mfma steps", case)
     gpu, wg, orc, wo = make_pair(D, d, n, divb)
     gpu.autotune(wg, variant=4 + 16)
+    dt_g, ch_g, _ = gpu.dt(wg)
+    dt_o, ch_o, _ = orc.timestep(wo)
+    assert abs(dt_g - dt_o) <= 1e-12 * dt_o and abs(ch_g - ch_o) <= 1e-12 * ch_o
     for _ in range(3):
         wo, dt, ch, k = orc.step(wo)
     gpu.step(wg, 3)
@@ -156,7 +159,7 @@ def test_every_cell_tile_variant_matches_oracle(case):
     dt, ch, kappa = orc.timestep(wo)
     r_o = orc.rhs(wo, ch, kappa)
     ran = 0
-    for v in [c + 16 * f for f in (0, 1) for c in range(6)]:  # cell variant + 16 x face variant
+    for v in [c + 16 * f for f in (0, 1) for c in range(8)]:  # cell variant + 16 x face variant
         try:
             gpu.autotune(wg, variant=v)
         except Exception:
@@ -169,7 +172,7 @@ def test_every_cell_tile_variant_matches_oracle(case):
         ran += 1
     assert ran >= (8 if divb == dg.GLM else 2)
     chosen = gpu.autotune(wg)
-    assert 0 <= (chosen & 15) < 6 and 0 <= (chosen >> 4) < 2
+    assert 0 <= (chosen & 15) < 8 and 0 <= (chosen >> 4) < 2
 
 
 @pytest.mark.parametrize("case", [c for c in VARIANT_CASES if c[3] == dg.GLM], ids=ids)
@@ -182,7 +185,7 @@ def test_every_cell_variant_fp32(case):
     dt, ch, kappa = orc.timestep(wo)
     r_o = orc.rhs(wo, ch, kappa)
     ran = 0
-    for v in [c + 16 * f for f in (0, 1) for c in range(6)]:
+    for v in [c + 16 * f for f in (0, 1) for c in range(8)]:
         try:
             gpu.autotune(wg, variant=v)
         except Exception:
