@@ -79,6 +79,17 @@ __device__ __forceinline__ int64_t nbr(int64_t K, int a, int s, const Grid& g) {
   return (int64_t)i + (int64_t)n0 * ((int64_t)j + (int64_t)n1 * k);
 }
 
+// XCD-aware block order.  Workgroups are dealt round-robin to the 8 XCDs
+// (each with its own L2); this maps launch block b to a logical tile so that
+// every XCD walks one contiguous 1/8 of the tiles in order, and a cell's
+// +y neighbour rows (and the fluxes written for them) are read on the XCD
+// whose L2 already holds them.  A bijection on [0, nb).
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
+  constexpr uint32_t NX = 8;
+  const uint32_t q = nb / NX, r = nb % NX, x = b % NX, i = b / NX;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 __device__ __forceinline__ void atomic_max_pos(unsigned long long* addr, double v) {
   // non-negative doubles order like their bit patterns; NaN is mapped above +inf
   unsigned long long b = __double_as_longlong(v);
@@ -523,7 +534,7 @@ __global__ void __launch_bounds__(64 * NW)
   using v4 = typename M::v4;
   constexpr int N = C::N, Q = C::Q, FP = C::FP, NV = 9;
   const int lane = threadIdx.x & 63;
-  const int64_t c0 = ((int64_t)blockIdx.x * NW + (threadIdx.x >> 6)) * 16;
+  const int64_t c0 = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * NW + (threadIdx.x >> 6)) * 16;
   if (c0 >= g.C) return;  // whole wave; the kernel has no barrier
   const int kq = lane >> 4, cl = lane & 15;
   const int64_t K = c0 + cl;
@@ -686,7 +697,7 @@ __global__ void __launch_bounds__(64 * NW) k_face_mfma(const T* __restrict__ w, 
   constexpr int N = C::N, FP = C::FP, NV = 9;
   const int a = blockIdx.y;
   const int lane = threadIdx.x & 63;
-  const int64_t f0 = ((int64_t)blockIdx.x * NW + (threadIdx.x >> 6)) * 16;
+  const int64_t f0 = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * NW + (threadIdx.x >> 6)) * 16;
   if (f0 >= g.C) return;  // whole wave; no barrier in this kernel
   const int kq = lane >> 4, cl = lane & 15;
   const int64_t F = f0 + cl;
@@ -746,7 +757,7 @@ __global__ void __launch_bounds__(64 * NW) k_maxsig_mfma(const T* __restrict__ w
   constexpr int N = C::N;
   __shared__ double red[NW];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int64_t c0 = ((int64_t)blockIdx.x * NW + wid) * 16;
+  const int64_t c0 = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * NW + wid) * 16;
   double smax = 0.0;
   if (c0 < g.C) {
     const int kq = lane >> 4, cl = lane & 15;
