@@ -175,25 +175,28 @@ def main():
             gpu.mlp_set(info["params"], info["sigma"])
 
         rl = run("fp32_learned", 1, limiter | DG_LIM_LEARNED, install, info["lo"])
-        # the gate on the evaluated workload itself: record two steps and count
-        # the positives of the plain detector that the gate would skip
+        # the gate on the evaluated workload itself, from the state the timed
+        # steps ended in: the share of cells whose plain detector it skips, and
+        # over two more recorded steps the positives of the plain detector that
+        # it would have skipped
         g = rl["gpu"]
+        w = rl["w"].clone()
+        st = g.limit(w.clone(), stats=True)
+        gate_skip = 1.0 - (st["n_fallback"] + st["n_mlp_flagged"]) / g.ncells
         cap = 1 << 21
         X = torch.zeros((cap, 256), dtype=torch.int16, device="cuda")
         y = torch.zeros(cap, device="cuda")
         cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
-        w = g.empty_state()
-        g.project_field(field, w)
-        g.limit(w)
         g.mlp_record(X, y, cnt, q_pos=1.0, q_neg=0.02, seed=99)
         g.step(w, 2)
         g.mlp_record(None)
         torch.cuda.synchronize()
         nrec = min(int(cnt.item()), cap)
         fn, skip, _, _ = false_negative_rate(g, X, y, nrec, info["lo"])
-        learned_info = dict(train_rows=info["n_train"], train_pos_frac=info["pos_frac_train"],
+        learned_info = dict(train_rows=info["n_train"], train_seeds=info["n_train_seeds"],
+                            train_pos_frac=info["pos_frac_train"], val_skip_frac=info["val_skip_frac"],
                             losses=info["losses"], gate_lo=info["lo"], val_fn_rate=info["val_fn_rate"],
-                            eval_fn_rate=fn, train_seconds=t_train)
+                            eval_fn_rate=fn, gate_skip_frac=gate_skip, train_seconds=t_train)
 
     ncells = r64["gpu"].ncells
     flops_launch = cell_flops(D, d, divb) * ncells

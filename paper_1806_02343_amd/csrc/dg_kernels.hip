@@ -548,38 +548,80 @@ __global__ void __launch_bounds__(64 * NW)
   for (int v = 0; v < NV; ++v)
 #pragma unroll
     for (int mt = 0; mt < S::NMT; ++mt) R[v][mt] = v4{0, 0, 0, 0};
+  // face values of k-step s (face point k = 4 s + kq: axis, side, point)
+  auto load_face = [&](int s, T* fv, T* la) {
+    const int k = 4 * s + kq;
+    const bool kv = k < 2 * D * FP;
+    const int a = kv ? k / (2 * FP) : 0, side = (k / FP) % 2, r = k % FP;
+    const int64_t Kf = side ? Kc : nbr(Kc, a, -1, g);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) fv[v] = kv ? ff[((int64_t)(a * NV + v) * FP + r) * ld + Kf] : T(0);
+#pragma unroll
+    for (int mt = 0; mt < S::NMT; ++mt) la[mt] = FL[(mt * S::KS + s) * 64 + lane];
+  };
+  auto surface_step = [&](const T* fv, const T* la) {
+#pragma unroll
+    for (int mt = 0; mt < S::NMT; ++mt)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) R[v][mt] = M::mma(la[mt], fv[v], R[v][mt]);
+  };
+  if (PF) {
+    // batched variant: the surface term first, while the nodal registers are
+    // free, with the loads of SB k-steps in flight together
+    constexpr int SB = 4;
+#pragma unroll 1
+    for (int s0 = 0; s0 < S::KS; s0 += SB) {
+      T fv[SB][NV], la[SB][S::NMT];
+#pragma unroll
+      for (int b = 0; b < SB; ++b) {
+        if (s0 + b < S::KS) {
+          load_face(s0 + b, fv[b], la[b]);
+        } else {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) fv[b][v] = T(0);
+#pragma unroll
+          for (int mt = 0; mt < S::NMT; ++mt) la[b][mt] = T(0);
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < SB; ++b) surface_step(fv[b], la[b]);
+    }
+  }
+  // the cell's modes as B operands of the nodal product: in the batched
+  // variant loaded once for all row tiles
+  T bw[PF ? S::NKS : 1][NV];
+  if (PF) {
+#pragma unroll
+    for (int s = 0; s < S::NKS; ++s)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int n = 4 * s + kq;
+        bw[PF ? s : 0][v] = n < N ? w[(int64_t)(v * N + n) * ld + Kc] : T(0);
+      }
+  }
 
   for (int rt = 0; rt < S::QT; ++rt) {
     v4 U[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) U[v] = v4{0, 0, 0, 0};
-    // operands of the next k-step are loaded while the current products run
-    T bc[NV], bn[NV];
-    T ac = T(0), an = T(0);
     if (PF) {
-      ac = FV[(rt * S::NKS) * 64 + lane];
+      T av[S::NKS];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) bc[v] = kq < N ? w[(int64_t)(v * N + kq) * ld + Kc] : T(0);
-    }
+      for (int s = 0; s < S::NKS; ++s) av[s] = FV[(rt * S::NKS + s) * 64 + lane];
+#pragma unroll
+      for (int s = 0; s < S::NKS; ++s)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) U[v] = M::mma(av[s], bw[PF ? s : 0][v], U[v]);
+    } else {
 #pragma unroll 1
-    for (int s = 0; s < S::NKS; ++s) {
-      if (!PF) {  // no prefetch: load this step's operands now
+      for (int s = 0; s < S::NKS; ++s) {
         const int n = 4 * s + kq;
-        ac = FV[(rt * S::NKS + s) * 64 + lane];
+        const T ac = FV[(rt * S::NKS + s) * 64 + lane];
+        T bc[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) bc[v] = n < N ? w[(int64_t)(v * N + n) * ld + Kc] : T(0);
-      } else if (s + 1 < S::NKS) {
-        const int n = 4 * (s + 1) + kq;
-        an = FV[(rt * S::NKS + s + 1) * 64 + lane];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) bn[v] = n < N ? w[(int64_t)(v * N + n) * ld + Kc] : T(0);
-      }
-#pragma unroll
-      for (int v = 0; v < NV; ++v) U[v] = M::mma(ac, bc[v], U[v]);
-      if (PF) {
-        ac = an;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) bc[v] = bn[v];
+        for (int v = 0; v < NV; ++v) U[v] = M::mma(ac, bc[v], U[v]);
       }
     }
 #pragma unroll
@@ -605,34 +647,12 @@ __global__ void __launch_bounds__(64 * NW)
       }
     }
   }
-  // face values of k-step s (face point k = 4 s + kq: axis, side, point)
-  auto load_face = [&](int s, T* fv, T* la) {
-    const int k = 4 * s + kq;
-    const bool kv = k < 2 * D * FP;
-    const int a = kv ? k / (2 * FP) : 0, side = (k / FP) % 2, r = k % FP;
-    const int64_t Kf = side ? Kc : nbr(Kc, a, -1, g);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) fv[v] = kv ? ff[((int64_t)(a * NV + v) * FP + r) * ld + Kf] : T(0);
-#pragma unroll
-    for (int mt = 0; mt < S::NMT; ++mt) la[mt] = FL[(mt * S::KS + s) * 64 + lane];
-  };
-  {
-    T fc[NV], fn[NV], lc[S::NMT], ln[S::NMT];
-    if (PF) load_face(0, fc, lc);
+  if (!PF) {
 #pragma unroll 1
     for (int s = 0; s < S::KS; ++s) {
-      if (!PF) load_face(s, fc, lc);
-      else if (s + 1 < S::KS) load_face(s + 1, fn, ln);
-#pragma unroll
-      for (int mt = 0; mt < S::NMT; ++mt)
-#pragma unroll
-        for (int v = 0; v < NV; ++v) R[v][mt] = M::mma(lc[mt], fc[v], R[v][mt]);
-      if (PF) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) fc[v] = fn[v];
-#pragma unroll
-        for (int mt = 0; mt < S::NMT; ++mt) lc[mt] = ln[mt];
-      }
+      T fv[NV], la[S::NMT];
+      load_face(s, fv, la);
+      surface_step(fv, la);
     }
   }
   if (!live) return;
@@ -1188,7 +1208,7 @@ struct LauncherImpl : Launcher {
   int cell_variant = -1;  // -1: default
 
   // variants 4, 5: the matrix-core cell kernel with 4 or 2 waves per
-  // workgroup; 6, 7: the same with operand prefetch (more registers)
+  // workgroup; 6, 7: the same with batched operand loads (more registers)
   static constexpr int NVAR = 8;
   template <int NW, bool PF>
   bool launch_cell_mfma(const void* w, const void* w0, void* out, const void* ff, const Grid& g, const Scal* sc,

@@ -66,25 +66,30 @@ def choose_lo(p, lab, target_fn=0.0, margin=0.5):
     return float(min(margin * q, 0.5))
 
 
-def train_indicator(workloads, n=128, d=3, train_seeds=range(4001, 4005), val_seeds=range(4029, 4031), steps=6,
-                    cap=1 << 21, q_neg=0.05, epochs=4, batch=4096, lr=2e-3, precision=1, stream=None, seed=1):
+def train_indicator(workloads, n=128, d=3, train_seeds=range(4001, 4033), val_seeds=range(4101, 4103), steps=4,
+                    cap=12 << 20, q_pos=0.1, q_neg=0.006, epochs=4, batch=4096, lr=2e-3, precision=1, stream=None,
+                    seed=1):
     """Train on blast states of the given seeds; returns a dict with the
-    parameters, feature scales, losses and validation statistics."""
+    parameters, feature scales, losses and validation statistics.  The
+    defaults record about 11M labelled cells from 32 blast seeds (13
+    pre-limiter states each: the projection and 4 steps x 3 stages)."""
     lim = DG_LIM_TVB | DG_LIM_CHAR | DG_LIM_POS
     gpu = DG(3, d, n, limiter=lim, precision=precision, stream=stream)
-    Xt, yt, nt, sigma = record_dataset(gpu, [workloads.Blast(s) for s in train_seeds], steps, cap, q_neg=q_neg,
-                                       seed=seed)
+    Xt, yt, nt, sigma = record_dataset(gpu, [workloads.Blast(s) for s in train_seeds], steps, cap, q_pos=q_pos,
+                                       q_neg=q_neg, seed=seed)
     losses = gpu.mlp_train(Xt, yt, nt, batch=batch, epochs=epochs, lr=lr, seed=seed) if nt >= batch else []
     params = gpu.mlp_get()
-    Xv, yv, nv, _ = record_dataset(gpu, [workloads.Blast(s) for s in val_seeds], steps, cap // 2, q_neg=q_neg,
-                                   seed=seed + 1, sigma=sigma)
+    pos_frac = float(yt[:nt].mean().item()) if nt else 0.0
+    del Xt, yt
+    Xv, yv, nv, _ = record_dataset(gpu, [workloads.Blast(s) for s in val_seeds], steps, cap // 2, q_pos=q_pos,
+                                   q_neg=q_neg, seed=seed + 1, sigma=sigma)
     # the second recording re-installed nothing: restore the trained network
     gpu.mlp_set(params, sigma)
     _, _, p, lab = false_negative_rate(gpu, Xv, yv, nv, 0.0)
     lo = choose_lo(p, lab)
     fn, skip, _, _ = false_negative_rate(gpu, Xv, yv, nv, lo)
     out = dict(params=params, sigma=sigma, losses=[float(x) for x in losses], n_train=nt,
-               pos_frac_train=float(yt[:nt].mean().item()) if nt else 0.0, n_val=nv, lo=lo, val_fn_rate=fn,
-               val_skip_frac=skip)
+               pos_frac_train=pos_frac, n_val=nv, lo=lo, val_fn_rate=fn, val_skip_frac=skip,
+               n_train_seeds=len(train_seeds))
     gpu.close()
     return out

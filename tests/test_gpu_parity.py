@@ -178,7 +178,12 @@ def test_every_cell_tile_variant_matches_oracle(case):
 @pytest.mark.parametrize("case", [c for c in VARIANT_CASES if c[3] == dg.GLM], ids=ids)
 def test_every_cell_variant_fp32(case):
     """FP32 right-hand sides of every cell-kernel variant (LDS-tiled and
-    matrix-core) against the oracle, block-relative error below 1e-4."""
+    matrix-core) against the oracle, block-relative error below 5e-4: FP32
+    rounding (2^-24) of about 3 x 10^2 accumulated terms per mode, times the
+    cancellation between the volume and surface terms of a smooth state
+    (up to ~10 for the psi block, whose right-hand side is the small
+    difference of c_h^2 B terms), gives up to ~1e-4 depending on the order
+    of accumulation, which differs between the variants."""
     D, d, n, divb = case
     _announce("variants fp32", case)
     gpu, wg, orc, wo = make_pair(D, d, n, divb, precision=1)
@@ -194,6 +199,6 @@ def test_every_cell_variant_fp32(case):
         gpu.rhs(wg, out, ch, kappa)
         torch.cuda.synchronize()
         err = block_rel_max(to_cells(out, orc.mesh.ncells), r_o, orc)
-        assert np.all(err < 1e-4), (v, err)
+        assert np.all(err < 5e-4), (v, err)
         ran += 1
     assert ran >= 8
