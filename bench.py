@@ -150,7 +150,7 @@ def main():
         ms, w = timed_run(gpu, w0, args.steps, args.warmup)
         ndof = gpu.nmodes * gpu.ncells
         r = dict(ms=ms, ndof=ndof, value=ndof * 3 * args.steps / (ms / 1e3), w=w, gpu=gpu, variant=variant,
-                 k_face=gpu.time_kernel(w0, 0, 5), k_cell=gpu.time_kernel(w0, 1, 5), k_dt=gpu.time_kernel(w0, 2, 5),
+                 k_face=gpu.time_kernel(w0, 0, 5), k_cell=gpu.time_kernel(w0, 1, 6), k_dt=gpu.time_kernel(w0, 2, 5),
                  k_limit=gpu.time_kernel(w0, 3, 5) if lim else 0.0)
         print(f"# {tag}: ms/step={ms / args.steps:.3f} face={r['k_face']:.3f} cell={r['k_cell']:.3f} "
               f"dt={r['k_dt']:.3f} limit={r['k_limit']:.3f} (ms/launch) variant={variant}", file=sys.stderr,
@@ -262,8 +262,9 @@ def kernel_source_hash():
 def measured_traffic(workload, variant):
     """HBM bytes per launch of the FP64 cell kernel from the committed
     rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by the
-    reading of a 1 GiB copy), or None when the summary is missing or was
-    taken from other kernel sources or another schedule."""
+    reading of a 1 GiB copy), or None when the summary is missing, has no
+    entry for the cell variant in use, or was taken from other kernel
+    sources."""
     path = os.path.join(ROOT, "profiles", f"k_cell_mfma_{workload}_fp64_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -273,9 +274,10 @@ def measured_traffic(workload, variant):
             if "=" in ln and not ln.lstrip().startswith("#"):
                 k, v = ln.split("=", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("source_sha256") != kernel_source_hash() or int(kv.get("schedule", -1)) != variant:
+    key = f"traffic_bytes_per_launch_cell_variant_{variant & 15}"
+    if kv.get("source_sha256") != kernel_source_hash() or key not in kv:
         return None
-    return float(kv["traffic_bytes_per_launch"])
+    return float(kv[key])
 
 
 def cpu_baseline(D, d, divb, cfg, limiter, nsteps=2):

@@ -203,7 +203,9 @@ int dg_mlp_train(dg_handle h, const void* X, const float* y, int64_t nrows, int3
 /* Measurement hook: launch one kernel of the step `reps` times back to back
  * on the handle's stream between two HIP events and return the mean time per
  * launch in ms.  which: 0 face flux kernel, 1 cell (volume + surface + stage
- * update) kernel, 2 time-step reduction, 3 limiter sequence.  Reads w; writes
+ * update) kernel in the step's mix of forms (rep i: the first stage's form
+ * if i % 3 == 0, else the later stages'), 2 time-step reduction, 3 limiter
+ * sequence.  Reads w; writes
  * only the handle's workspaces.  Synchronous. */
 int dg_time_kernel(dg_handle h, const void* w, int32_t which, int32_t reps, double* ms /*[host]*/);
 
@@ -216,7 +218,8 @@ int dg_time_kernel(dg_handle h, const void* w, int32_t which, int32_t reps, doub
  * forces that schedule (DG_EINVAL if it is not built for this
  * configuration); *variant < 0 times every built cell variant, then every
  * face variant, on the state w (read only; the handle's workspaces are
- * written) and keeps the fastest of each.  cache_path (may be NULL): a JSON
+ * written) and keeps the fastest of each.  Before any call the schedule is
+ * 6 + 16 (GLM) or 0 (Powell).  cache_path (may be NULL): a JSON
  * file of earlier choices keyed by precision, dimension, degree, divergence
  * scheme and cell count; an entry found there is used without timing and new
  * choices are appended.  On return *variant holds the schedule in use.

@@ -483,7 +483,12 @@ int dg_time_kernel(dg_handle h, const void* w, int32_t which, int32_t reps, doub
   for (int i = 0; i < reps; ++i) {
     switch (which) {
       case 0: h->L->face(w, h->ff, h->jp, h->g, h->sc, h->sp, h->stream); break;
-      case 1: h->L->cell(w, w, h->S1, h->ff, h->jp, h->g, h->sc, h->sp, 0.0, 1.0, 1, h->stream); break;
+      case 1:
+        // the step's mix: one stage-1 form (w -> S1) per two stage-2/3 forms
+        // (S1 and w read, S1 written in place); w is only read
+        if (i % 3 == 0) h->L->cell(w, w, h->S1, h->ff, h->jp, h->g, h->sc, h->sp, 0.0, 1.0, 1, h->stream);
+        else h->L->cell(h->S1, w, h->S1, h->ff, h->jp, h->g, h->sc, h->sp, 0.75, 0.25, 1, h->stream);
+        break;
       case 2: (void)dt_sequence(h, w); break;
       default: h->L->limit(h->S1, h->lscr, h->g, h->sc, h->sp, h->stream); break;
     }

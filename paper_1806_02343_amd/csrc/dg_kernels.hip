@@ -1127,7 +1127,7 @@ struct LauncherImpl : Launcher {
   const T* mft = nullptr;                                   // and of the matrix-core face kernel
   const double* mpos = nullptr;                             // and of the matrix-core positivity limiter
   int pos_variant = 1;                                      // 1: matrix-core positivity limiter where built
-  int face_variant = -1;                                    // -1: default (0)
+  int face_variant = DIVB == GLM ? 1 : 0;                   // default: matrix-core face kernel for GLM
 
   template <typename U>
   hipError_t up(const std::vector<double>& src, const U*& dst) {
@@ -1259,14 +1259,15 @@ struct LauncherImpl : Launcher {
   int cell_variant_count() const override { return NVAR; }
   // face variants: 0 LDS-staged, 1 matrix cores (GLM uniform grids)
   int face_variant_count() const override { return DIVB == GLM ? 2 : 1; }
-  void set_face_variant(int v) override { face_variant = v; }
-  int get_face_variant() const override { return face_variant < 0 ? 0 : face_variant; }
+  void set_face_variant(int v) override { face_variant = v < 0 ? (DIVB == GLM ? 1 : 0) : v; }
+  int get_face_variant() const override { return face_variant; }
   void set_cell_variant(int v) override { cell_variant = v; }
   int get_cell_variant() const override { return cell_variant; }
   void cell(const void* w, const void* w0, void* out, const void* ff, const void* jp, const Grid& g, const Scal* sc,
             const SchemeParams& sp, double a0, double b0, int mode, hipStream_t s) override {
     int v = cell_variant;
-    if (v < 0 || !cell_variant_valid(v)) {
+    if (v < 0) v = DIVB == GLM ? 6 : 0;  // default: the batched matrix-core kernel where it is built
+    if (!cell_variant_valid(v)) {
       v = 0;
       while (v < 4 && !cell_variant_valid(v)) ++v;
     }
