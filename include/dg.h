@@ -212,8 +212,9 @@ int dg_time_kernel(dg_handle h, const void* w, int32_t which, int32_t reps, doub
 /* Autotuner of the kernel schedule.  A schedule is cell variant + 16 x face
  * variant.  Cell variants: 0-3 LDS-tiled kernels (cells per block x threads
  * per block: 16x256, 32x256, 32x512, 64x512), 4-7 matrix-core kernel (4 or 2
- * waves of 16 cells per block, 6-7 with batched operand loads; GLM on uniform
- * grids, elsewhere variant 0 runs).  Face variants: 0 LDS-staged, 1 matrix-core (GLM; also selects the
+ * waves of 16 cells per block, 6-7 with batched operand loads, 8-9 batched and
+ * persistent with the tables in LDS; GLM on uniform grids, elsewhere variant
+ * 0 runs).  Face variants: 0 LDS-staged, 1 matrix-core (GLM; also selects the
  * matrix-core max-signal-speed reduction of the time step).  *variant >= 0
  * forces that schedule (DG_EINVAL if it is not built for this
  * configuration); *variant < 0 times every built cell variant, then every

@@ -523,19 +523,19 @@ void mfma_tables(const Tables& t, std::vector<double>& fv, std::vector<double>& 
       }
 }
 
-template <typename T, int D, int DEG, int NW, bool PF>
-__global__ void __launch_bounds__(64 * NW)
-    k_cell_mfma(const T* w, const T* w0, T* out, const T* __restrict__ ff, const T* __restrict__ FV,
-                const T* __restrict__ FG, const T* __restrict__ FL, const T* __restrict__ Minv, Grid g,
-                const Scal* __restrict__ sc, double gamma, double a0, double b0, int mode) {
+// The work of one wave on the 16 cells starting at c0 (tables FV, FG, FL in
+// global memory or LDS).
+template <typename T, int D, int DEG, bool PF>
+__device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w, const T* w0, T* out,
+                                               const T* __restrict__ ff, const T* FV, const T* FG, const T* FL,
+                                               const T* __restrict__ Minv, const Grid& g,
+                                               const Scal* __restrict__ sc, double gamma, double a0, double b0,
+                                               int mode) {
   using C = Cfg<D, DEG, GLM>;
   using S = MfmaShape<D, DEG>;
   using M = Mfma<T>;
   using v4 = typename M::v4;
   constexpr int N = C::N, Q = C::Q, FP = C::FP, NV = 9;
-  const int lane = threadIdx.x & 63;
-  const int64_t c0 = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * NW + (threadIdx.x >> 6)) * 16;
-  if (c0 >= g.C) return;  // whole wave; the kernel has no barrier
   const int kq = lane >> 4, cl = lane & 15;
   const int64_t K = c0 + cl;
   const bool live = K < g.C;
@@ -678,6 +678,39 @@ __global__ void __launch_bounds__(64 * NW)
           out[(int64_t)m * ld + K] = (T)a0 * base + (T)b0 * (wm + (T)dt * dw);
         }
       }
+}
+
+template <typename T, int D, int DEG, int NW, bool PF>
+__global__ void __launch_bounds__(64 * NW)
+    k_cell_mfma(const T* w, const T* w0, T* out, const T* __restrict__ ff, const T* __restrict__ FV,
+                const T* __restrict__ FG, const T* __restrict__ FL, const T* __restrict__ Minv, Grid g,
+                const Scal* __restrict__ sc, double gamma, double a0, double b0, int mode) {
+  const int64_t c0 = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * NW + (threadIdx.x >> 6)) * 16;
+  if (c0 >= g.C) return;  // whole wave; the kernel has no barrier
+  cell_tile_mfma<T, D, DEG, PF>(c0, threadIdx.x & 63, w, w0, out, ff, FV, FG, FL, Minv, g, sc, gamma, a0, b0, mode);
+}
+
+// Persistent form: one workgroup per resident slot copies the fragment
+// tables into LDS once, then its waves walk a contiguous range of 16-cell
+// tiles (ranges dealt XCD by XCD, as in xcd_block).
+template <typename T, int D, int DEG, int NW>
+__global__ void __launch_bounds__(64 * NW)
+    k_cell_mfma_p(const T* w, const T* w0, T* out, const T* __restrict__ ff, const T* __restrict__ FV,
+                  const T* __restrict__ FG, const T* __restrict__ FL, const T* __restrict__ Minv, Grid g,
+                  const Scal* __restrict__ sc, double gamma, double a0, double b0, int mode) {
+  using S = MfmaShape<D, DEG>;
+  __shared__ T sV[S::SZ_V], sG[S::SZ_G], sL[S::SZ_L];
+  for (int i = threadIdx.x; i < S::SZ_V; i += 64 * NW) sV[i] = FV[i];
+  for (int i = threadIdx.x; i < S::SZ_G; i += 64 * NW) sG[i] = FG[i];
+  for (int i = threadIdx.x; i < S::SZ_L; i += 64 * NW) sL[i] = FL[i];
+  __syncthreads();
+  const int64_t ntiles = (g.C + 15) / 16;
+  const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+  const int64_t t0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * per;
+  const int64_t t1 = t0 + per < ntiles ? t0 + per : ntiles;
+  for (int64_t t = t0 + (threadIdx.x >> 6); t < t1; t += NW)
+    cell_tile_mfma<T, D, DEG, true>(t * 16, threadIdx.x & 63, w, w0, out, ff, sV, sG, sL, Minv, g, sc, gamma, a0, b0,
+                                    mode);
 }
 
 // Face kernel on the matrix cores (GLM, uniform grids): one wave owns 16
@@ -1168,6 +1201,16 @@ struct LauncherImpl : Launcher {
       std::vector<double> pt;
       pos_tables<D, DEG>(t, pt);
       if ((e = up<double>(pt, mpos)) != hipSuccess) return e;
+      // resident workgroups of the persistent cell kernels on this device
+      int dev = 0, ncu = 0, b4 = 0, b2 = 0;
+      if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+      if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+      if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b4, k_cell_mfma_p<T, D, DEG, 4>, 256, 0)) != hipSuccess)
+        return e;
+      if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_cell_mfma_p<T, D, DEG, 2>, 128, 0)) != hipSuccess)
+        return e;
+      persist_blocks[0] = b4 * ncu;
+      persist_blocks[1] = b2 * ncu;
     }
     return hipSuccess;
   }
@@ -1208,8 +1251,24 @@ struct LauncherImpl : Launcher {
   int cell_variant = -1;  // -1: default
 
   // variants 4, 5: the matrix-core cell kernel with 4 or 2 waves per
-  // workgroup; 6, 7: the same with batched operand loads (more registers)
-  static constexpr int NVAR = 8;
+  // workgroup; 6, 7: the same with batched operand loads (more registers);
+  // 8, 9: batched and persistent, the tables in LDS
+  static constexpr int NVAR = 10;
+  int persist_blocks[2] = {0, 0};  // resident workgroups of the persistent kernels (4 and 2 waves)
+  template <int NW>
+  bool launch_cell_mfma_p(const void* w, const void* w0, void* out, const void* ff, const Grid& g, const Scal* sc,
+                          const SchemeParams& sp, double a0, double b0, int mode, hipStream_t s) {
+    if constexpr (DIVB == GLM) {
+      const int nb = persist_blocks[NW == 4 ? 0 : 1];
+      if (g.level || nb <= 0) return false;
+      const int64_t groups = ((g.C + 15) / 16 + NW - 1) / NW;
+      const unsigned grid = (unsigned)(groups < nb ? groups : nb);
+      k_cell_mfma_p<T, D, DEG, NW><<<grid, 64 * NW, 0, s>>>((const T*)w, (const T*)w0, (T*)out, (const T*)ff, mfv,
+                                                            mfg, mfl, tb.Minv, g, sc, sp.gamma, a0, b0, mode);
+      return true;
+    }
+    return false;
+  }
   template <int NW, bool PF>
   bool launch_cell_mfma(const void* w, const void* w0, void* out, const void* ff, const Grid& g, const Scal* sc,
                         const SchemeParams& sp, double a0, double b0, int mode, hipStream_t s) {
@@ -1252,7 +1311,9 @@ struct LauncherImpl : Launcher {
       case 4:
       case 5:
       case 6:
-      case 7: return DIVB == GLM;
+      case 7:
+      case 8:
+      case 9: return DIVB == GLM;
       default: return false;
     }
   }
@@ -1275,6 +1336,8 @@ struct LauncherImpl : Launcher {
     if (v == 5 && launch_cell_mfma<2, false>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
     if (v == 6 && launch_cell_mfma<4, true>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
     if (v == 7 && launch_cell_mfma<2, true>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
+    if (v == 8 && launch_cell_mfma_p<4>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
+    if (v == 9 && launch_cell_mfma_p<2>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
     if (v >= 4) {  // octree grids: the matrix-core kernel covers uniform grids only
       v = 0;
       while (v < 4 && !cell_variant_valid(v)) ++v;
