@@ -66,12 +66,16 @@ __device__ __forceinline__ double signal_sum(const T* u, double gamma) {
 // flux is zero and not returned).
 template <typename T>
 __device__ __forceinline__ void hlld_flux(const T* wl, const T* wr, T bx, double gamma, T* out) {
+  // divisions are products with reciprocals computed once (1/(gamma-1),
+  // 1/rho per side, 1/den, 1/(S - S_M) per side)
   const T g = (T)gamma;
+  const T igm1 = T(1) / (g - T(1));
   T UL[7], UR[7], FL[7], FR[7], EL, ER, ptL, ptR, cfL, cfR;
   auto cf = [&](const T* W, T* U, T* F, T& E, T& pt, T& c) {
     const T rho = W[0], u = W[1], v = W[2], w = W[3], p = W[4], by = W[5], bz = W[6];
+    const T irho = T(1) / rho;
     const T bb = bx * bx + by * by + bz * bz;
-    E = p / (g - T(1)) + T(0.5) * rho * (u * u + v * v + w * w) + T(0.5) * bb;
+    E = p * igm1 + T(0.5) * rho * (u * u + v * v + w * w) + T(0.5) * bb;
     pt = p + T(0.5) * bb;
     const T vb = u * bx + v * by + w * bz;
     U[0] = rho; U[1] = rho * u; U[2] = rho * v; U[3] = rho * w; U[4] = E; U[5] = by; U[6] = bz;
@@ -83,8 +87,8 @@ __device__ __forceinline__ void hlld_flux(const T* wl, const T* wr, T bx, double
     F[5] = by * u - v * bx;
     F[6] = bz * u - w * bx;
     const T gp = g * p;
-    const T s = (gp + bb) / rho;
-    T disc = s * s - T(4) * gp * bx * bx / (rho * rho);
+    const T s = (gp + bb) * irho;
+    T disc = s * s - T(4) * gp * bx * bx * (irho * irho);
     disc = disc > T(0) ? disc : T(0);
     c = sqrt(T(0.5) * (s + sqrt(disc)));
   };
@@ -97,9 +101,9 @@ __device__ __forceinline__ void hlld_flux(const T* wl, const T* wr, T bx, double
   if (SL > T(0)) { for (int k = 0; k < 7; ++k) out[k] = FL[k]; return; }
   if (SR <= T(0)) { for (int k = 0; k < 7; ++k) out[k] = FR[k]; return; }
   const T dL = (SL - uL) * rL, dR = (SR - uR) * rR;
-  const T den = dR - dL;
-  const T SM = (dR * uR - dL * uL - ptR + ptL) / den;
-  const T ptS = (dR * ptL - dL * ptR + rL * rR * (SR - uR) * (SL - uL) * (uR - uL)) / den;
+  const T iden = T(1) / (dR - dL);
+  const T SM = (dR * uR - dL * uL - ptR + ptL) * iden;
+  const T ptS = (dR * ptL - dL * ptR + rL * rR * (SR - uR) * (SL - uL) * (uR - uL)) * iden;
   // outer star states
   T Us[2][7], rs[2], vs[2], ws[2], bys[2], bzs[2], Es[2], vbs[2];
   for (int side = 0; side < 2; ++side) {
@@ -109,7 +113,8 @@ __device__ __forceinline__ void hlld_flux(const T* wl, const T* wr, T bx, double
     const T d = side ? dR : dL;
     const T E = side ? ER : EL, pt = side ? ptR : ptL;
     const T rho = W[0], u = W[1], v = W[2], w = W[3], by = W[5], bz = W[6];
-    const T r_s = d / (S - SM);
+    const T isd = T(1) / (S - SM);
+    const T r_s = d * isd;
     const T dd = d * (S - SM) - bx * bx;
     const T sc = rho * (S - u) * (S - u);
     const T thr = T(1e-12) * (sc > bx * bx ? sc : bx * bx);
@@ -126,7 +131,7 @@ __device__ __forceinline__ void hlld_flux(const T* wl, const T* wr, T bx, double
     }
     const T vb = u * bx + v * by + w * bz;
     const T vb_s = SM * bx + v_s * by_s + w_s * bz_s;
-    const T E_s = ((S - u) * E - pt * u + ptS * SM + bx * (vb - vb_s)) / (S - SM);
+    const T E_s = ((S - u) * E - pt * u + ptS * SM + bx * (vb - vb_s)) * isd;
     rs[side] = r_s; vs[side] = v_s; ws[side] = w_s; bys[side] = by_s; bzs[side] = bz_s;
     Es[side] = E_s; vbs[side] = vb_s;
     Us[side][0] = r_s; Us[side][1] = r_s * SM; Us[side][2] = r_s * v_s; Us[side][3] = r_s * w_s;
@@ -134,7 +139,7 @@ __device__ __forceinline__ void hlld_flux(const T* wl, const T* wr, T bx, double
     (void)U;
   }
   const T sqL = sqrt(rs[0]), sqR = sqrt(rs[1]);
-  const T SsL = SM - fabs(bx) / sqL, SsR = SM + fabs(bx) / sqR;
+  const T SsL = SM - fabs(bx) * (T(1) / sqL), SsR = SM + fabs(bx) * (T(1) / sqR);
   if (SsL > T(0)) {
     for (int k = 0; k < 7; ++k) out[k] = FL[k] + SL * (Us[0][k] - UL[k]);
     return;
