@@ -805,15 +805,26 @@ __global__ void __launch_bounds__(64 * NW) k_maxsig_mfma(const T* __restrict__ w
                                                          const T* __restrict__ FT, Grid g, Scal* sc, double gamma) {
   using C = Cfg<D, DEG, GLM>;
   using S = MfmaShape<D, DEG>;
+  using SF = MfmaFaceShape<D, DEG>;
   using M = Mfma<T>;
   using v4 = typename M::v4;
   constexpr int N = C::N;
+  static_assert(SF::NKS == S::NKS, "same k-steps for the volume and face evaluation tables");
+  // evaluation rows: the volume row tiles, then the trace rows of each face
+  __shared__ T sT[(S::QT + 2 * D) * S::NKS * 64];
   __shared__ double red[NW];
+  for (int i = threadIdx.x; i < S::SZ_V; i += 64 * NW) sT[i] = FV[i];
+  for (int i = threadIdx.x; i < 2 * D * S::NKS * 64; i += 64 * NW) sT[S::SZ_V + i] = FT[i];
+  __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int64_t c0 = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * NW + wid) * 16;
+  const int kq = lane >> 4, cl = lane & 15;
+  const int64_t ntiles = (g.C + 15) / 16;
+  const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+  const int64_t t0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * per;
+  const int64_t t1 = t0 + per < ntiles ? t0 + per : ntiles;
   double smax = 0.0;
-  if (c0 < g.C) {
-    const int kq = lane >> 4, cl = lane & 15;
+  for (int64_t t = t0 + wid; t < t1; t += NW) {
+    const int64_t c0 = t * 16;
     const int64_t K = c0 + cl;
     const bool live = K < g.C;
     const int64_t Kc = live ? K : c0;
@@ -832,7 +843,7 @@ __global__ void __launch_bounds__(64 * NW) k_maxsig_mfma(const T* __restrict__ w
       for (int v = 0; v < 8; ++v) U[v] = v4{0, 0, 0, 0};
 #pragma unroll
       for (int s = 0; s < S::NKS; ++s) {
-        const T a = rt < S::QT ? FV[(rt * S::NKS + s) * 64 + lane] : FT[((rt - S::QT) * S::NKS + s) * 64 + lane];
+        const T a = sT[(rt * S::NKS + s) * 64 + lane];
 #pragma unroll
         for (int v = 0; v < 8; ++v) U[v] = M::mma(a, bw[v][s], U[v]);
       }
@@ -1211,6 +1222,13 @@ struct LauncherImpl : Launcher {
         return e;
       persist_blocks[0] = b4 * ncu;
       persist_blocks[1] = b2 * ncu;
+      int bp = 0, bm = 0;
+      if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bp, k_pos_mfma<T, D, DEG, 4>, 256, 0)) != hipSuccess)
+        return e;
+      if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bm, k_maxsig_mfma<T, D, DEG, 4>, 256, 0)) != hipSuccess)
+        return e;
+      pos_blocks = bp * ncu;
+      maxsig_blocks = bm * ncu;
     }
     return hipSuccess;
   }
@@ -1255,6 +1273,7 @@ struct LauncherImpl : Launcher {
   // 8, 9: batched and persistent, the tables in LDS
   static constexpr int NVAR = 10;
   int persist_blocks[2] = {0, 0};  // resident workgroups of the persistent kernels (4 and 2 waves)
+  int pos_blocks = 0, maxsig_blocks = 0;
   template <int NW>
   bool launch_cell_mfma_p(const void* w, const void* w0, void* out, const void* ff, const Grid& g, const Scal* sc,
                           const SchemeParams& sp, double a0, double b0, int mode, hipStream_t s) {
@@ -1351,11 +1370,11 @@ struct LauncherImpl : Launcher {
   }
   void maxsig(const void* w, const Grid& g, Scal* sc, const SchemeParams& sp, hipStream_t s) override {
     if constexpr (DIVB == GLM) {
-      if (!g.level && face_variant == 1) {
+      if (!g.level && face_variant == 1 && maxsig_blocks > 0) {
         constexpr int NW = 4;
-        const int64_t tiles = (g.C + 15) / 16;
-        k_maxsig_mfma<T, D, DEG, NW><<<(unsigned)((tiles + NW - 1) / NW), 64 * NW, 0, s>>>((const T*)w, mfv, mft, g, sc,
-                                                                                          sp.gamma);
+        const int64_t groups = ((g.C + 15) / 16 + NW - 1) / NW;
+        const unsigned grid = (unsigned)(groups < maxsig_blocks ? groups : maxsig_blocks);
+        k_maxsig_mfma<T, D, DEG, NW><<<grid, 64 * NW, 0, s>>>((const T*)w, mfv, mft, g, sc, sp.gamma);
         return;
       }
     }
@@ -1378,7 +1397,7 @@ struct LauncherImpl : Launcher {
                                                                                 pvpw, minv64, g.ld, sp.gamma);
   }
   void limit(void* w, void* scratch, const Grid& g, Scal* sc, const SchemeParams& sp, hipStream_t s) override {
-    launch_limit<T, D, DEG, DIVB>(w, scratch, tb, pos_variant == 1 ? mpos : nullptr, g, sc, sp, s);
+    launch_limit<T, D, DEG, DIVB>(w, scratch, tb, pos_variant == 1 ? mpos : nullptr, pos_blocks, g, sc, sp, s);
   }
   size_t limit_scratch_bytes(const Grid& g) const override { return limit_scratch<T, D, DEG, DIVB>(g); }
   bool mlp_features(const void* w, uint16_t* X, const double* sigma, const Grid& g, hipStream_t s) override {
