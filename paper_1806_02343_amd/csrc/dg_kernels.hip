@@ -525,10 +525,13 @@ void mfma_tables(const Tables& t, std::vector<double>& fv, std::vector<double>& 
 
 // The work of one wave on the 16 cells starting at c0 (tables FV, FG, FL in
 // global memory or LDS).
-template <typename T, int D, int DEG, bool PF>
+// AMR: octree grid; the surface term is then an owner gather of the 1 or
+// 2^(D-1) (sub-)face fluxes of each side with the sub-face tables LFS,
+// accumulated on the vector ALU straight into the accumulator elements.
+template <typename T, int D, int DEG, bool PF, bool AMR>
 __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w, const T* w0, T* out,
                                                const T* __restrict__ ff, const T* FV, const T* FG, const T* FL,
-                                               const T* __restrict__ Minv, const Grid& g,
+                                               const T* __restrict__ LFS, const T* __restrict__ Minv, const Grid& g,
                                                const Scal* __restrict__ sc, double gamma, double a0, double b0,
                                                int mode) {
   using C = Cfg<D, DEG, GLM>;
@@ -565,7 +568,7 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
 #pragma unroll
       for (int v = 0; v < NV; ++v) R[v][mt] = M::mma(la[mt], fv[v], R[v][mt]);
   };
-  if (PF) {
+  if (PF && !AMR) {
     // batched variant: the surface term first, while the nodal registers are
     // free, with the loads of SB k-steps in flight together
     constexpr int SB = 4;
@@ -647,7 +650,7 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
       }
     }
   }
-  if (!PF) {
+  if (!PF && !AMR) {
 #pragma unroll 1
     for (int s = 0; s < S::KS; ++s) {
       T fv[NV], la[S::NMT];
@@ -655,10 +658,43 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
       surface_step(fv, la);
     }
   }
+  if (AMR && live) {
+    constexpr int NSUB = 1 + (1 << (D - 1)), NQ = 1 << (D - 1);
+    for (int a = 0; a < D; ++a)
+      for (int sd = 0; sd < 2; ++sd) {
+        const int32_t* sl = g.slots + (((int64_t)K * D + a) * 2 + sd) * 4;
+        for (int qf = 0; qf < NQ; ++qf) {
+          const int32_t f = sl[qf];
+          if (f < 0) break;
+          const int sub = 1 + (sd ? g.subL[f] : g.subR[f]);
+          const T sign = sd ? T(-1) : T(1);
+#pragma unroll 1
+          for (int r = 0; r < FP; ++r) {
+            const T* lf = LFS + (((a * 2 + sd) * NSUB + sub) * FP + r) * N;
+            T lv[S::NMT][4];
+#pragma unroll
+            for (int mt = 0; mt < S::NMT; ++mt)
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const int n = 16 * mt + M::row(kq, e);
+                lv[mt][e] = n < N ? lf[n] : T(0);
+              }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+              const T fv = sign * ff[((int64_t)v * FP + r) * g.ldf + f];
+#pragma unroll
+              for (int mt = 0; mt < S::NMT; ++mt)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) R[v][mt][e] += lv[mt][e] * fv;
+            }
+          }
+        }
+      }
+  }
   if (!live) return;
   const double dt = sc->dt;
   const T kappa = (T)sc->kappa;
-  const T two_h = T(2.0 / g.h);
+  const T two_h = T(2.0 / cell_h(g, K));
 #pragma unroll
   for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -680,24 +716,27 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
       }
 }
 
-template <typename T, int D, int DEG, int NW, bool PF>
+template <typename T, int D, int DEG, int NW, bool PF, bool AMR>
 __global__ void __launch_bounds__(64 * NW)
     k_cell_mfma(const T* w, const T* w0, T* out, const T* __restrict__ ff, const T* __restrict__ FV,
-                const T* __restrict__ FG, const T* __restrict__ FL, const T* __restrict__ Minv, Grid g,
-                const Scal* __restrict__ sc, double gamma, double a0, double b0, int mode) {
+                const T* __restrict__ FG, const T* __restrict__ FL, const T* __restrict__ LFS,
+                const T* __restrict__ Minv, Grid g, const Scal* __restrict__ sc, double gamma, double a0, double b0,
+                int mode) {
   const int64_t c0 = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * NW + (threadIdx.x >> 6)) * 16;
   if (c0 >= g.C) return;  // whole wave; the kernel has no barrier
-  cell_tile_mfma<T, D, DEG, PF>(c0, threadIdx.x & 63, w, w0, out, ff, FV, FG, FL, Minv, g, sc, gamma, a0, b0, mode);
+  cell_tile_mfma<T, D, DEG, PF, AMR>(c0, threadIdx.x & 63, w, w0, out, ff, FV, FG, FL, LFS, Minv, g, sc, gamma, a0,
+                                     b0, mode);
 }
 
 // Persistent form: one workgroup per resident slot copies the fragment
 // tables into LDS once, then its waves walk a contiguous range of 16-cell
 // tiles (ranges dealt XCD by XCD, as in xcd_block).
-template <typename T, int D, int DEG, int NW>
+template <typename T, int D, int DEG, int NW, bool AMR>
 __global__ void __launch_bounds__(64 * NW)
     k_cell_mfma_p(const T* w, const T* w0, T* out, const T* __restrict__ ff, const T* __restrict__ FV,
-                  const T* __restrict__ FG, const T* __restrict__ FL, const T* __restrict__ Minv, Grid g,
-                  const Scal* __restrict__ sc, double gamma, double a0, double b0, int mode) {
+                  const T* __restrict__ FG, const T* __restrict__ FL, const T* __restrict__ LFS,
+                  const T* __restrict__ Minv, Grid g, const Scal* __restrict__ sc, double gamma, double a0,
+                  double b0, int mode) {
   using S = MfmaShape<D, DEG>;
   __shared__ T sV[S::SZ_V], sG[S::SZ_G], sL[S::SZ_L];
   for (int i = threadIdx.x; i < S::SZ_V; i += 64 * NW) sV[i] = FV[i];
@@ -709,8 +748,8 @@ __global__ void __launch_bounds__(64 * NW)
   const int64_t t0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * per;
   const int64_t t1 = t0 + per < ntiles ? t0 + per : ntiles;
   for (int64_t t = t0 + (threadIdx.x >> 6); t < t1; t += NW)
-    cell_tile_mfma<T, D, DEG, true>(t * 16, threadIdx.x & 63, w, w0, out, ff, sV, sG, sL, Minv, g, sc, gamma, a0, b0,
-                                    mode);
+    cell_tile_mfma<T, D, DEG, true, AMR>(t * 16, threadIdx.x & 63, w, w0, out, ff, sV, sG, sL, LFS, Minv, g, sc,
+                                         gamma, a0, b0, mode);
 }
 
 // Face kernel on the matrix cores (GLM, uniform grids): one wave owns 16
@@ -1213,13 +1252,23 @@ struct LauncherImpl : Launcher {
       pos_tables<D, DEG>(t, pt);
       if ((e = up<double>(pt, mpos)) != hipSuccess) return e;
       // resident workgroups of the persistent cell kernels on this device
-      int dev = 0, ncu = 0, b4 = 0, b2 = 0;
+      int dev = 0, ncu = 0, b4 = 0, b2 = 0, ba4 = 0, ba2 = 0;
       if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
       if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-      if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b4, k_cell_mfma_p<T, D, DEG, 4>, 256, 0)) != hipSuccess)
+      if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b4, k_cell_mfma_p<T, D, DEG, 4, false>, 256, 0)) !=
+          hipSuccess)
         return e;
-      if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_cell_mfma_p<T, D, DEG, 2>, 128, 0)) != hipSuccess)
+      if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_cell_mfma_p<T, D, DEG, 2, false>, 128, 0)) !=
+          hipSuccess)
         return e;
+      if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&ba4, k_cell_mfma_p<T, D, DEG, 4, true>, 256, 0)) !=
+          hipSuccess)
+        return e;
+      if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&ba2, k_cell_mfma_p<T, D, DEG, 2, true>, 128, 0)) !=
+          hipSuccess)
+        return e;
+      persist_blocks_amr[0] = ba4 * ncu;
+      persist_blocks_amr[1] = ba2 * ncu;
       persist_blocks[0] = b4 * ncu;
       persist_blocks[1] = b2 * ncu;
       int bp = 0, bm = 0;
@@ -1272,18 +1321,25 @@ struct LauncherImpl : Launcher {
   // workgroup; 6, 7: the same with batched operand loads (more registers);
   // 8, 9: batched and persistent, the tables in LDS
   static constexpr int NVAR = 10;
-  int persist_blocks[2] = {0, 0};  // resident workgroups of the persistent kernels (4 and 2 waves)
+  int persist_blocks[2] = {0, 0};      // resident workgroups of the persistent kernels (4 and 2 waves)
+  int persist_blocks_amr[2] = {0, 0};  // the same on octree grids
   int pos_blocks = 0, maxsig_blocks = 0;
   template <int NW>
   bool launch_cell_mfma_p(const void* w, const void* w0, void* out, const void* ff, const Grid& g, const Scal* sc,
                           const SchemeParams& sp, double a0, double b0, int mode, hipStream_t s) {
     if constexpr (DIVB == GLM) {
-      const int nb = persist_blocks[NW == 4 ? 0 : 1];
-      if (g.level || nb <= 0) return false;
+      const int nb = g.level ? persist_blocks_amr[NW == 4 ? 0 : 1] : persist_blocks[NW == 4 ? 0 : 1];
+      if (nb <= 0) return false;
       const int64_t groups = ((g.C + 15) / 16 + NW - 1) / NW;
       const unsigned grid = (unsigned)(groups < nb ? groups : nb);
-      k_cell_mfma_p<T, D, DEG, NW><<<grid, 64 * NW, 0, s>>>((const T*)w, (const T*)w0, (T*)out, (const T*)ff, mfv,
-                                                            mfg, mfl, tb.Minv, g, sc, sp.gamma, a0, b0, mode);
+      if (g.level)
+        k_cell_mfma_p<T, D, DEG, NW, true><<<grid, 64 * NW, 0, s>>>((const T*)w, (const T*)w0, (T*)out,
+                                                                    (const T*)ff, mfv, mfg, mfl, tb.LFS, tb.Minv, g,
+                                                                    sc, sp.gamma, a0, b0, mode);
+      else
+        k_cell_mfma_p<T, D, DEG, NW, false><<<grid, 64 * NW, 0, s>>>((const T*)w, (const T*)w0, (T*)out,
+                                                                     (const T*)ff, mfv, mfg, mfl, tb.LFS, tb.Minv, g,
+                                                                     sc, sp.gamma, a0, b0, mode);
       return true;
     }
     return false;
@@ -1292,10 +1348,16 @@ struct LauncherImpl : Launcher {
   bool launch_cell_mfma(const void* w, const void* w0, void* out, const void* ff, const Grid& g, const Scal* sc,
                         const SchemeParams& sp, double a0, double b0, int mode, hipStream_t s) {
     if constexpr (DIVB == GLM) {
-      if (g.level) return false;
       const int64_t tiles = (g.C + 15) / 16;
-      k_cell_mfma<T, D, DEG, NW, PF><<<(unsigned)((tiles + NW - 1) / NW), 64 * NW, 0, s>>>(
-          (const T*)w, (const T*)w0, (T*)out, (const T*)ff, mfv, mfg, mfl, tb.Minv, g, sc, sp.gamma, a0, b0, mode);
+      const unsigned grid = (unsigned)((tiles + NW - 1) / NW);
+      if (g.level)
+        k_cell_mfma<T, D, DEG, NW, PF, true><<<grid, 64 * NW, 0, s>>>((const T*)w, (const T*)w0, (T*)out,
+                                                                      (const T*)ff, mfv, mfg, mfl, tb.LFS, tb.Minv, g,
+                                                                      sc, sp.gamma, a0, b0, mode);
+      else
+        k_cell_mfma<T, D, DEG, NW, PF, false><<<grid, 64 * NW, 0, s>>>((const T*)w, (const T*)w0, (T*)out,
+                                                                       (const T*)ff, mfv, mfg, mfl, tb.LFS, tb.Minv, g,
+                                                                       sc, sp.gamma, a0, b0, mode);
       return true;
     }
     return false;
@@ -1357,7 +1419,7 @@ struct LauncherImpl : Launcher {
     if (v == 7 && launch_cell_mfma<2, true>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
     if (v == 8 && launch_cell_mfma_p<4>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
     if (v == 9 && launch_cell_mfma_p<2>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
-    if (v >= 4) {  // octree grids: the matrix-core kernel covers uniform grids only
+    if (v >= 4) {  // not built for this configuration
       v = 0;
       while (v < 4 && !cell_variant_valid(v)) ++v;
     }
