@@ -695,8 +695,22 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
   const double dt = sc->dt;
   const T kappa = (T)sc->kappa;
   const T two_h = T(2.0 / cell_h(g, K));
+  // out may be w or w0 (stages 2 and 3 update in place), so the compiler
+  // keeps every load of an element before its store; loading a variable's
+  // elements together first keeps those loads in flight at once.  Each
+  // (mode, cell) element belongs to exactly one lane.
 #pragma unroll
-  for (int v = 0; v < NV; ++v)
+  for (int v = 0; v < NV; ++v) {
+    T wm[S::NMT][4], base[S::NMT][4];
+#pragma unroll
+    for (int mt = 0; mt < S::NMT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int n = 16 * mt + M::row(kq, r);
+        const int64_t at = (int64_t)(v * N + (n < N ? n : 0)) * ld + K;
+        wm[mt][r] = (v == 8 || mode != 0) ? w[at] : T(0);
+        base[mt][r] = mode != 0 ? w0[at] : T(0);
+      }
 #pragma unroll
     for (int mt = 0; mt < S::NMT; ++mt)
 #pragma unroll
@@ -705,15 +719,11 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
         if (n >= N) continue;
         const int m = v * N + n;
         T dw = R[v][mt][r] * two_h * Minv[m];
-        const T wm = w[(int64_t)m * ld + K];
-        if (v == 8) dw -= kappa * wm;
-        if (mode == 0) {
-          out[(int64_t)m * ld + K] = dw;
-        } else {
-          const T base = w0[(int64_t)m * ld + K];
-          out[(int64_t)m * ld + K] = (T)a0 * base + (T)b0 * (wm + (T)dt * dw);
-        }
+        if (v == 8) dw -= kappa * wm[mt][r];
+        if (mode == 0) out[(int64_t)m * ld + K] = dw;
+        else out[(int64_t)m * ld + K] = (T)a0 * base[mt][r] + (T)b0 * (wm[mt][r] + (T)dt * dw);
       }
+  }
 }
 
 template <typename T, int D, int DEG, int NW, bool PF, bool AMR>
