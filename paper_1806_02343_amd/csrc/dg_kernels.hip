@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <type_traits>
 #include <vector>
 
 #include "dg_kernels.h"
@@ -423,6 +424,14 @@ __global__ void __launch_bounds__(NT)
         }
       }
     }
+    // w0 may alias out (the last stage updates in place): load the item's
+    // w0 row together before the stores so the loads are in flight at once
+    T base[N];
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      const int m = blk < C::NLEG ? blk * N + l : C::NLEG * N + (blk - C::NLEG) * N + l;
+      base[l] = (mode != 0 && m < NM) ? w0[(int64_t)m * ld + K] : T(0);
+    }
 #pragma unroll
     for (int l = 0; l < N; ++l) {
       const int m = blk < C::NLEG ? blk * N + l : C::NLEG * N + (blk - C::NLEG) * N + l;
@@ -432,12 +441,8 @@ __global__ void __launch_bounds__(NT)
       if constexpr (DIVB == GLM) {
         if (m >= 8 * N) dw -= kappa * wm;
       }
-      if (mode == 0) {
-        out[(int64_t)m * ld + K] = dw;
-      } else {
-        const T base = w0[(int64_t)m * ld + K];
-        out[(int64_t)m * ld + K] = (T)a0 * base + (T)b0 * (wm + (T)dt * dw);
-      }
+      if (mode == 0) out[(int64_t)m * ld + K] = dw;
+      else out[(int64_t)m * ld + K] = (T)a0 * base[l] + (T)b0 * (wm + (T)dt * dw);
     }
   }
 }
@@ -828,20 +833,28 @@ __global__ void __launch_bounds__(64 * NW) k_face_mfma(const T* __restrict__ w, 
   }
   if (!live) return;
   const T ch = (T)sc->ch;
+  // the axis is uniform over the block: one branch per axis keeps every
+  // component index of the Riemann solver a compile-time constant
+  auto riemann = [&](auto axis) {
+    constexpr int A = decltype(axis)::value;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int r = M::row(kq, j);
-    if (r >= FP) continue;
-    T uL[9], uR[9], Fx[9];
+    for (int j = 0; j < 4; ++j) {
+      const int r = M::row(kq, j);
+      if (r >= FP) continue;
+      T uL[9], uR[9], Fx[9];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      uL[v] = UL[v][j];
-      uR[v] = UR[v][j];
+      for (int v = 0; v < NV; ++v) {
+        uL[v] = UL[v][j];
+        uR[v] = UR[v][j];
+      }
+      (void)face_flux_a<T, NV, A>(uL, uR, gamma, ch, Fx);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) ff[((int64_t)(A * NV + v) * FP + r) * ld + F] = Fx[v];
     }
-    (void)face_flux<T, NV>(uL, uR, a, gamma, ch, Fx);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) ff[((int64_t)(a * NV + v) * FP + r) * ld + F] = Fx[v];
-  }
+  };
+  if (a == 0) riemann(std::integral_constant<int, 0>{});
+  else if (a == 1) riemann(std::integral_constant<int, 1>{});
+  else if constexpr (D == 3) riemann(std::integral_constant<int, 2>{});
 }
 
 // Max signal speed on the matrix cores (GLM, uniform grids): one wave

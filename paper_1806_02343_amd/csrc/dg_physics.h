@@ -168,9 +168,9 @@ __device__ __forceinline__ void hlld_flux(const T* wl, const T* wr, T bx, double
 
 // Numerical flux through a face with normal +e_a between traces uL and uR
 // (global components).  Writes F (NV components) and returns B^n_F.
-template <typename T, int NV>
-__device__ __forceinline__ T face_flux(const T* uL, const T* uR, int a, double gamma, T ch, T* F) {
-  const int n = a, t1 = (a + 1) % 3, t2 = (a + 2) % 3;
+template <typename T, int NV, int A>
+__device__ __forceinline__ T face_flux_a(const T* uL, const T* uR, double gamma, T ch, T* F) {
+  constexpr int n = A, t1 = (A + 1) % 3, t2 = (A + 2) % 3;
   T wl[7], wr[7];
   {
     const T ir = T(1) / uL[0];
@@ -199,6 +199,15 @@ __device__ __forceinline__ T face_flux(const T* uL, const T* uR, int a, double g
     F[8] = ch * ch * bn_s;
   }
   return bnF;
+}
+
+// The same with a run-time axis (one branch per axis, so that every component
+// index inside is a compile-time constant).
+template <typename T, int NV>
+__device__ __forceinline__ T face_flux(const T* uL, const T* uR, int a, double gamma, T ch, T* F) {
+  if (a == 0) return face_flux_a<T, NV, 0>(uL, uR, gamma, ch, F);
+  if (a == 1) return face_flux_a<T, NV, 1>(uL, uR, gamma, ch, F);
+  return face_flux_a<T, NV, 2>(uL, uR, gamma, ch, F);
 }
 
 }  // namespace dgmhd
