@@ -213,14 +213,16 @@ int dg_time_kernel(dg_handle h, const void* w, int32_t which, int32_t reps, doub
  * variant.  Cell variants: 0-3 LDS-tiled kernels (cells per block x threads
  * per block: 16x256, 32x256, 32x512, 64x512), 4-7 matrix-core kernel (4 or 2
  * waves of 16 cells per block, 6-7 with batched operand loads, 8-9 batched and
- * persistent with the tables in LDS; GLM on uniform grids, elsewhere variant
- * 0 runs).  Face variants: 0 LDS-staged, 1 matrix-core (GLM; also selects the
+ * persistent with the tables in LDS; for the Powell scheme 8-9 are the
+ * matrix-core kernel with the LDF basis, 4 or 2 waves per block; on octree
+ * grids the GLM kernels gather sub-face fluxes; where a variant is not
+ * built, variant 0 runs).  Face variants: 0 LDS-staged, 1 matrix-core (GLM; also selects the
  * matrix-core max-signal-speed reduction of the time step).  *variant >= 0
  * forces that schedule (DG_EINVAL if it is not built for this
  * configuration); *variant < 0 times every built cell variant, then every
  * face variant, on the state w (read only; the handle's workspaces are
  * written) and keeps the fastest of each.  Before any call the schedule is
- * 6 + 16 (GLM) or 0 (Powell).  cache_path (may be NULL): a JSON
+ * 6 + 16 (GLM) or 8 (Powell).  cache_path (may be NULL): a JSON
  * file of earlier choices keyed by precision, dimension, degree, divergence
  * scheme and cell count; an entry found there is used without timing and new
  * choices are appended.  On return *variant holds the schedule in use.

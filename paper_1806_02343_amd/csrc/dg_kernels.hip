@@ -767,6 +767,260 @@ __global__ void __launch_bounds__(64 * NW)
                                          gamma, a0, b0, mode);
 }
 
+// ---------------------------------------------------------------------------
+// Cell kernel on the matrix cores for the Powell scheme (uniform grids).
+//
+// The Legendre variables (rho, m, E; B_z in 2-D) follow the GLM kernel.  The
+// magnetic field lives in the locally divergence-free basis: its nodal
+// values are products of the per-component tables PV_c with the LDF modes,
+// its volume term sums the products of PGW_{a,c} with the flux components
+// f_a[B_c], and its surface term the products of the signed PLF_c with the
+// face values.  The Powell face term of a face point (eq. powell-src-face
+// with q of the cell means) is added to the same B operand as the flux, so it
+// costs no extra product: side +a carries F + q (B^n_F - B^n_K), side -a
+// F - q (B^n_K' - B^n_F) under the signed tables.
+
+template <int D, int DEG>
+struct PowellShape {
+  using C = Cfg<D, DEG, POWELL>;
+  static constexpr int NKL = (C::NLDF + 3) / 4;      // k-steps over the LDF modes
+  static constexpr int NMTL = (C::NLDF + 15) / 16;   // 16-row tiles of the LDF result
+  static constexpr int QT = (C::Q + 15) / 16;
+  static constexpr int KS = (2 * D * C::FP + 3) / 4;
+  static constexpr int SZ_PV = D * QT * NKL * 64;
+  static constexpr int SZ_PG = D * D * NMTL * QT * 4 * 64;
+  static constexpr int SZ_PL = D * NMTL * KS * 64;
+};
+
+template <typename T, int D, int DEG>
+void powell_tables(const Tables& t, std::vector<double>& pv, std::vector<double>& pg, std::vector<double>& pl) {
+  using C = Cfg<D, DEG, POWELL>;
+  using S = PowellShape<D, DEG>;
+  constexpr int Q = C::Q, FP = C::FP, L = C::NLDF;
+  pv.assign(S::SZ_PV, 0.0);
+  pg.assign(S::SZ_PG, 0.0);
+  pl.assign(S::SZ_PL, 0.0);
+  for (int c = 0; c < D; ++c)
+    for (int rt = 0; rt < S::QT; ++rt)
+      for (int s = 0; s < S::NKL; ++s)
+        for (int l = 0; l < 64; ++l) {
+          const int q = 16 * rt + l % 16, i = 4 * s + l / 16;
+          if (q < Q && i < L) pv[((c * S::QT + rt) * S::NKL + s) * 64 + l] = t.PV[(c * Q + q) * L + i];
+        }
+  for (int a = 0; a < D; ++a)
+    for (int c = 0; c < D; ++c)
+      for (int mt = 0; mt < S::NMTL; ++mt)
+        for (int rt = 0; rt < S::QT; ++rt)
+          for (int j = 0; j < 4; ++j)
+            for (int l = 0; l < 64; ++l) {
+              const int q = 16 * rt + Mfma<T>::row(l / 16, j), i = 16 * mt + l % 16;
+              if (q < Q && i < L)
+                pg[(((((a * D + c) * S::NMTL + mt) * S::QT + rt) * 4 + j) * 64) + l] = t.PGW[((a * D + c) * Q + q) * L + i];
+            }
+  for (int c = 0; c < D; ++c)
+    for (int mt = 0; mt < S::NMTL; ++mt)
+      for (int s = 0; s < S::KS; ++s)
+        for (int l = 0; l < 64; ++l) {
+          const int k = 4 * s + l / 16, i = 16 * mt + l % 16;
+          if (k >= 2 * D * FP || i >= L) continue;
+          const int a = k / (2 * FP), side = (k / FP) % 2, r = k % FP;
+          const double v = t.PLF[(((a * 2 + side) * D + c) * FP + r) * L + i];
+          pl[((c * S::NMTL + mt) * S::KS + s) * 64 + l] = side ? -v : v;
+        }
+}
+
+template <typename T, int D, int DEG>
+__device__ __forceinline__ void cell_tile_mfma_powell(int64_t c0, int lane, const T* w, const T* w0, T* out,
+                                                      const T* __restrict__ ff, const T* __restrict__ jp,
+                                                      const T* FV, const T* FG, const T* FL, const T* PVt,
+                                                      const T* PGt, const T* PLt, const T* __restrict__ Pmean,
+                                                      const T* __restrict__ Minv, const Grid& g,
+                                                      const Scal* __restrict__ sc, double gamma, double a0, double b0,
+                                                      int mode) {
+  using C = Cfg<D, DEG, POWELL>;
+  using S = MfmaShape<D, DEG>;
+  using P = PowellShape<D, DEG>;
+  using M = Mfma<T>;
+  using v4 = typename M::v4;
+  constexpr int N = C::N, Q = C::Q, FP = C::FP, NV = 8, NL = C::NLEG, L = C::NLDF;
+  const int kq = lane >> 4, cl = lane & 15;
+  const int64_t K = c0 + cl;
+  const bool live = K < g.C;
+  const int64_t Kc = live ? K : c0;
+  const int64_t ld = g.ld;
+  v4 R[NL][S::NMT], RB[P::NMTL];
+#pragma unroll
+  for (int j = 0; j < NL; ++j)
+#pragma unroll
+    for (int mt = 0; mt < S::NMT; ++mt) R[j][mt] = v4{0, 0, 0, 0};
+#pragma unroll
+  for (int mt = 0; mt < P::NMTL; ++mt) RB[mt] = v4{0, 0, 0, 0};
+  // q(<u>_K) of the lane's cell from the cell means (eq. powellq-average)
+  T qv[8];
+  {
+    const T rho = w[Kc];
+    T bm[3];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      T b = 0;
+      for (int l = 0; l < L; ++l) b += Pmean[c * L + l] * w[(int64_t)(NL * N + l) * ld + Kc];
+      bm[c] = b;
+    }
+    if (D == 2) bm[2] = w[(int64_t)(5 * N) * ld + Kc];
+    const T v0 = w[(int64_t)(1 * N) * ld + Kc] / rho, v1 = w[(int64_t)(2 * N) * ld + Kc] / rho,
+            v2 = w[(int64_t)(3 * N) * ld + Kc] / rho;
+    qv[0] = 0; qv[1] = bm[0]; qv[2] = bm[1]; qv[3] = bm[2];
+    qv[4] = v0 * bm[0] + v1 * bm[1] + v2 * bm[2];
+    qv[5] = v0; qv[6] = v1; qv[7] = v2;
+  }
+  // surface first: flux + Powell term of face point k = 4 s + kq as one B operand per variable
+#pragma unroll 1
+  for (int s = 0; s < S::KS; ++s) {
+    const int k = 4 * s + kq;
+    const bool kv = k < 2 * D * FP;
+    const int a = kv ? k / (2 * FP) : 0, side = (k / FP) % 2, r = k % FP;
+    const int64_t Kf = side ? Kc : nbr(Kc, a, -1, g);
+    // side +a: jump B^n_F - B^n_K at face K; side -a: B^n_K - B^n_F at face K-a
+    const T jmp = kv ? jp[((int64_t)(a * 2 + (side ? 0 : 1)) * FP + r) * ld + Kf] : T(0);
+    T bv[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const T f = kv ? ff[((int64_t)(a * NV + v) * FP + r) * ld + Kf] : T(0);
+      bv[v] = side ? f + qv[v] * jmp : f - qv[v] * jmp;
+    }
+#pragma unroll
+    for (int mt = 0; mt < S::NMT; ++mt) {
+      const T la = FL[(mt * S::KS + s) * 64 + lane];
+#pragma unroll
+      for (int j = 0; j < NL; ++j) R[j][mt] = M::mma(la, bv[C::legvar(j)], R[j][mt]);
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+#pragma unroll
+      for (int mt = 0; mt < P::NMTL; ++mt)
+        RB[mt] = M::mma(PLt[((c * P::NMTL + mt) * S::KS + s) * 64 + lane], bv[5 + c], RB[mt]);
+  }
+  // the cell's modes as B operands, held for all row tiles
+  T bw[NL][S::NKS], bl[P::NKL];
+#pragma unroll
+  for (int j = 0; j < NL; ++j)
+#pragma unroll
+    for (int s = 0; s < S::NKS; ++s) {
+      const int n = 4 * s + kq;
+      bw[j][s] = n < N ? w[(int64_t)(j * N + n) * ld + Kc] : T(0);
+    }
+#pragma unroll
+  for (int s = 0; s < P::NKL; ++s) {
+    const int i = 4 * s + kq;
+    bl[s] = i < L ? w[(int64_t)(NL * N + i) * ld + Kc] : T(0);
+  }
+  const T ch2 = T(0);
+#pragma unroll 1
+  for (int rt = 0; rt < S::QT; ++rt) {
+    v4 U[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) U[v] = v4{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < S::NKS; ++s) {
+      const T av = FV[(rt * S::NKS + s) * 64 + lane];
+#pragma unroll
+      for (int j = 0; j < NL; ++j) U[C::legvar(j)] = M::mma(av, bw[j][s], U[C::legvar(j)]);
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+#pragma unroll
+      for (int s = 0; s < P::NKL; ++s)
+        U[5 + c] = M::mma(PVt[((c * S::QT + rt) * P::NKL + s) * 64 + lane], bl[s], U[5 + c]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bool qok = 16 * rt + M::row(kq, j) < Q;
+      T u[9];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) u[v] = U[v][j];
+      u[8] = T(0);
+      if (!qok) {
+        u[0] = T(1);
+        u[4] = T(1);
+      }
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        T f[9];
+        mhd_flux<T, NV>(u, a, gamma, ch2, f);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) f[v] = qok ? f[v] : T(0);
+#pragma unroll
+        for (int mt = 0; mt < S::NMT; ++mt) {
+          const T ga = FG[((((a * S::NMT + mt) * S::QT + rt) * 4 + j) * 64) + lane];
+#pragma unroll
+          for (int jj = 0; jj < NL; ++jj) R[jj][mt] = M::mma(ga, f[C::legvar(jj)], R[jj][mt]);
+        }
+#pragma unroll
+        for (int c = 0; c < D; ++c)
+#pragma unroll
+          for (int mt = 0; mt < P::NMTL; ++mt)
+            RB[mt] = M::mma(PGt[(((((a * D + c) * P::NMTL + mt) * S::QT + rt) * 4 + j) * 64) + lane], f[5 + c], RB[mt]);
+      }
+    }
+  }
+  if (!live) return;
+  const double dt = sc->dt;
+  const T two_h = T(2.0 / g.h);
+  auto finish = [&](int m, T racc) {
+    T dw = racc * two_h * Minv[m];
+    if (mode == 0) return dw;
+    return (T)a0 * w0[(int64_t)m * ld + K] + (T)b0 * (w[(int64_t)m * ld + K] + (T)dt * dw);
+  };
+  // out may alias w or w0: every element's loads precede its store, grouped per block
+#pragma unroll
+  for (int j = 0; j < NL; ++j) {
+    T o[S::NMT][4];
+#pragma unroll
+    for (int mt = 0; mt < S::NMT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int n = 16 * mt + M::row(kq, r);
+        o[mt][r] = n < N ? finish(j * N + n, R[j][mt][r]) : T(0);
+      }
+#pragma unroll
+    for (int mt = 0; mt < S::NMT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int n = 16 * mt + M::row(kq, r);
+        if (n < N) out[(int64_t)(j * N + n) * ld + K] = o[mt][r];
+      }
+  }
+  {
+    T o[P::NMTL][4];
+#pragma unroll
+    for (int mt = 0; mt < P::NMTL; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * mt + M::row(kq, r);
+        o[mt][r] = i < L ? finish(NL * N + i, RB[mt][r]) : T(0);
+      }
+#pragma unroll
+    for (int mt = 0; mt < P::NMTL; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * mt + M::row(kq, r);
+        if (i < L) out[(int64_t)(NL * N + i) * ld + K] = o[mt][r];
+      }
+  }
+}
+
+template <typename T, int D, int DEG, int NW>
+__global__ void __launch_bounds__(64 * NW)
+    k_cell_mfma_powell(const T* w, const T* w0, T* out, const T* __restrict__ ff, const T* __restrict__ jp,
+                       const T* __restrict__ FV, const T* __restrict__ FG, const T* __restrict__ FL,
+                       const T* __restrict__ PVt, const T* __restrict__ PGt, const T* __restrict__ PLt,
+                       const T* __restrict__ Pmean, const T* __restrict__ Minv, Grid g, const Scal* __restrict__ sc,
+                       double gamma, double a0, double b0, int mode) {
+  const int64_t c0 = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * NW + (threadIdx.x >> 6)) * 16;
+  if (c0 >= g.C) return;  // whole wave; no barrier in this kernel
+  cell_tile_mfma_powell<T, D, DEG>(c0, threadIdx.x & 63, w, w0, out, ff, jp, FV, FG, FL, PVt, PGt, PLt, Pmean, Minv, g,
+                                   sc, gamma, a0, b0, mode);
+}
+
 // Face kernel on the matrix cores (GLM, uniform grids): one wave owns 16
 // faces of one axis; the traces of both sides at the face points are 16x16x4
 // products of the trace tables with the two cells' modes (faces as columns),
@@ -1230,6 +1484,7 @@ struct LauncherImpl : Launcher {
   DevTab<T> tb{};
   double *vpw = nullptr, *pvpw = nullptr, *minv64 = nullptr;
   const T *mfv = nullptr, *mfg = nullptr, *mfl = nullptr;  // fragment-order tables of the matrix-core cell kernel
+  const T *mpv = nullptr, *mpg = nullptr, *mpl = nullptr;  // and its LDF (Powell) tables
   const T* mft = nullptr;                                   // and of the matrix-core face kernel
   const double* mpos = nullptr;                             // and of the matrix-core positivity limiter
   int pos_variant = 1;                                      // 1: matrix-core positivity limiter where built
@@ -1262,6 +1517,17 @@ struct LauncherImpl : Launcher {
     pvpw = (double*)d1;
     if ((e = up<double>(t.Minv, d1)) != hipSuccess) return e;
     minv64 = (double*)d1;
+    if constexpr (DIVB == POWELL) {
+      std::vector<double> fv, fg, fl, pv, pg, pl;
+      mfma_tables<T, D, DEG>(t, fv, fg, fl);
+      powell_tables<T, D, DEG>(t, pv, pg, pl);
+      if ((e = up<T>(fv, mfv)) != hipSuccess) return e;
+      if ((e = up<T>(fg, mfg)) != hipSuccess) return e;
+      if ((e = up<T>(fl, mfl)) != hipSuccess) return e;
+      if ((e = up<T>(pv, mpv)) != hipSuccess) return e;
+      if ((e = up<T>(pg, mpg)) != hipSuccess) return e;
+      if ((e = up<T>(pl, mpl)) != hipSuccess) return e;
+    }
     if constexpr (DIVB == GLM) {
       std::vector<double> fv, fg, fl;
       mfma_tables<T, D, DEG>(t, fv, fg, fl);
@@ -1385,6 +1651,24 @@ struct LauncherImpl : Launcher {
     }
     return false;
   }
+  bool launch_cell_powell(int nw, const void* w, const void* w0, void* out, const void* ff, const void* jp,
+                          const Grid& g, const Scal* sc, const SchemeParams& sp, double a0, double b0, int mode,
+                          hipStream_t s) {
+    if constexpr (DIVB == POWELL) {
+      if (g.level) return false;
+      const unsigned grid = (unsigned)(((g.C + 15) / 16 + nw - 1) / nw);
+      if (nw == 4)
+        k_cell_mfma_powell<T, D, DEG, 4><<<grid, 256, 0, s>>>((const T*)w, (const T*)w0, (T*)out, (const T*)ff,
+                                                              (const T*)jp, mfv, mfg, mfl, mpv, mpg, mpl, tb.Pmean,
+                                                              tb.Minv, g, sc, sp.gamma, a0, b0, mode);
+      else
+        k_cell_mfma_powell<T, D, DEG, 2><<<grid, 128, 0, s>>>((const T*)w, (const T*)w0, (T*)out, (const T*)ff,
+                                                              (const T*)jp, mfv, mfg, mfl, mpv, mpg, mpl, tb.Pmean,
+                                                              tb.Minv, g, sc, sp.gamma, a0, b0, mode);
+      return true;
+    }
+    return false;
+  }
   template <int V>
   bool launch_cell_v(const void* w, const void* w0, void* out, const void* ff, const void* jp, const Grid& g,
                      const Scal* sc, const SchemeParams& sp, double a0, double b0, int mode, hipStream_t s) {
@@ -1417,7 +1701,7 @@ struct LauncherImpl : Launcher {
       case 6:
       case 7:
       case 8:
-      case 9: return DIVB == GLM;
+      case 9: return true;
       default: return false;
     }
   }
@@ -1431,7 +1715,7 @@ struct LauncherImpl : Launcher {
   void cell(const void* w, const void* w0, void* out, const void* ff, const void* jp, const Grid& g, const Scal* sc,
             const SchemeParams& sp, double a0, double b0, int mode, hipStream_t s) override {
     int v = cell_variant;
-    if (v < 0) v = DIVB == GLM ? 6 : 0;  // default: the batched matrix-core kernel where it is built
+    if (v < 0) v = DIVB == GLM ? 6 : 8;  // default: a matrix-core kernel
     if (!cell_variant_valid(v)) {
       v = 0;
       while (v < 4 && !cell_variant_valid(v)) ++v;
@@ -1442,6 +1726,7 @@ struct LauncherImpl : Launcher {
     if (v == 7 && launch_cell_mfma<2, true>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
     if (v == 8 && launch_cell_mfma_p<4>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
     if (v == 9 && launch_cell_mfma_p<2>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
+    if ((v == 8 || v == 9) && launch_cell_powell(v == 8 ? 4 : 2, w, w0, out, ff, jp, g, sc, sp, a0, b0, mode, s)) return;
     if (v >= 4) {  // not built for this configuration
       v = 0;
       while (v < 4 && !cell_variant_valid(v)) ++v;
