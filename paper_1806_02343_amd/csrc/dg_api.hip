@@ -177,6 +177,25 @@ static std::string build_octree(dg_handle h, const dg_mesh* m) {
     const bool ok = (cnt[k] == 1 && full[k] == 1) || (cnt[k] == NQ && full[k] == 0);
     if (!ok) return "octree: a cell side is not covered by one full face or 2^(D-1) quarter faces";
   }
+  // face tiles for the matrix-core face kernel: per axis, the classes
+  // (full, full) then (full, quarter q) then (quarter q, full), each class's
+  // faces in list order, in tiles of 16 padded with -1
+  std::vector<int32_t> ftile, fperm;
+  {
+    const int NCL = 1 + 2 * NQ;
+    for (int a = 0; a < D; ++a)
+      for (int k = 0; k < NCL; ++k) {
+        const int wantL = k <= NQ ? -1 : k - 1 - NQ, wantR = (k >= 1 && k <= NQ) ? k - 1 : -1;
+        std::vector<int32_t> list;
+        for (int64_t f = face0[a]; f < face0[a + 1]; ++f)
+          if (sL[f] == wantL && sR[f] == wantR) list.push_back((int32_t)f);
+        for (size_t i = 0; i < list.size(); i += 16) {
+          ftile.push_back(a * NCL + k);
+          ftile.push_back((int32_t)fperm.size());
+          for (size_t j = 0; j < 16; ++j) fperm.push_back(i + j < list.size() ? list[i + j] : -1);
+        }
+      }
+  }
   // upload
   auto up = [&](const void* src, size_t bytes) -> void* {
     void* p = nullptr;
@@ -192,7 +211,11 @@ static std::string build_octree(dg_handle h, const dg_mesh* m) {
   g.subL = (const int8_t*)up(sL.data(), sL.size());
   g.subR = (const int8_t*)up(sR.data(), sR.size());
   g.slots = (const int32_t*)up(slots.data(), slots.size() * 4);
-  if (!g.level || !g.faceL || !g.faceR || !g.subL || !g.subR || !g.slots) return "octree: device allocation";
+  g.ftile = (const int32_t*)up(ftile.data(), ftile.size() * 4);
+  g.fperm = (const int32_t*)up(fperm.data(), fperm.size() * 4);
+  g.nftile = (int64_t)ftile.size() / 2;
+  if (!g.level || !g.faceL || !g.faceR || !g.subL || !g.subR || !g.slots || !g.ftile || !g.fperm)
+    return "octree: device allocation";
   g.NF = NF;
   g.ldf = (NF + 63) / 64 * 64;
   for (int a = 0; a <= 3; ++a) g.face0[a] = a <= D ? face0[a] : NF;

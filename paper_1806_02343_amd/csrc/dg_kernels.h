@@ -39,6 +39,12 @@ struct Grid {
   const int32_t* slots;    // [C][D][2][4] faces touching each cell side (side 1: +a), -1 = none
   int64_t NF, ldf;         // number of faces, leading dimension of face arrays
   int64_t face0[4];        // first face of each axis; face0[D] = NF
+  // faces grouped by class (axis, left sub-face, right sub-face) into tiles of
+  // 16 for the matrix-core face kernel: ftile[2t] = class, ftile[2t+1] =
+  // offset of the tile's 16 entries in fperm (face indices, -1 = padding)
+  const int32_t* ftile;
+  const int32_t* fperm;
+  int64_t nftile;
 };
 
 struct SchemeParams {

@@ -1021,6 +1021,99 @@ __global__ void __launch_bounds__(64 * NW)
                                    sc, gamma, a0, b0, mode);
 }
 
+// Face kernel on octree meshes on the matrix cores: one wave per tile of 16
+// faces of one class (axis, left sub-face, right sub-face), so that both
+// trace tables (the full face or the quarter of the coarse side, Sec. 4.4
+// prolongation) are shared by the tile's 16 faces; the traces are 16x16x4
+// products with the two cells' modes gathered by face, then each lane solves
+// the Riemann problems of its four face points.
+template <int D, int DEG>
+struct AmrFaceShape {
+  using C = Cfg<D, DEG, GLM>;
+  static constexpr int NSUB = 1 + (1 << (D - 1));
+  static constexpr int NQ = 1 << (D - 1);
+  static constexpr int NCL = 1 + 2 * NQ;
+  static constexpr int NKS = (C::N + 3) / 4;
+  static constexpr int SZ = D * 2 * NSUB * NKS * 64;
+};
+
+template <typename T, int D, int DEG>
+void amr_face_tables(const Tables& t, std::vector<double>& ft) {
+  using C = Cfg<D, DEG, GLM>;
+  using S = AmrFaceShape<D, DEG>;
+  ft.assign(S::SZ, 0.0);
+  for (int as = 0; as < D * 2 * S::NSUB; ++as)
+    for (int s = 0; s < S::NKS; ++s)
+      for (int l = 0; l < 64; ++l) {
+        const int r = l % 16, n = 4 * s + l / 16;
+        if (r < C::FP && n < C::N) ft[(as * S::NKS + s) * 64 + l] = t.TFS[(as * C::FP + r) * C::N + n];
+      }
+}
+
+template <typename T, int D, int DEG, int NW>
+__global__ void __launch_bounds__(64 * NW) k_face_amr_mfma(const T* __restrict__ w, T* __restrict__ ffa,
+                                                           const T* __restrict__ FT, Grid g,
+                                                           const Scal* __restrict__ sc, double gamma) {
+  using C = Cfg<D, DEG, GLM>;
+  using S = AmrFaceShape<D, DEG>;
+  using M = Mfma<T>;
+  using v4 = typename M::v4;
+  constexpr int N = C::N, FP = C::FP, NV = 9;
+  const int64_t tile = (int64_t)blockIdx.x * NW + (threadIdx.x >> 6);
+  if (tile >= g.nftile) return;  // whole wave; no barrier in this kernel
+  const int lane = threadIdx.x & 63, kq = lane >> 4, cl = lane & 15;
+  const int cls = g.ftile[2 * tile], off = g.ftile[2 * tile + 1];
+  const int a = cls / S::NCL, k = cls % S::NCL;
+  const int subL = k <= S::NQ ? -1 : k - 1 - S::NQ, subR = (k >= 1 && k <= S::NQ) ? k - 1 : -1;
+  const int32_t f = g.fperm[off + cl];
+  const bool live = f >= 0;
+  const int32_t fc = live ? f : g.fperm[off];  // the first entry of a tile is a face
+  const int64_t L = g.faceL[fc], R = g.faceR[fc];
+  const int64_t ld = g.ld;
+  const T* tl = FT + ((a * 2 + 1) * S::NSUB + subL + 1) * S::NKS * 64;
+  const T* tr = FT + ((a * 2 + 0) * S::NSUB + subR + 1) * S::NKS * 64;
+  v4 UL[NV], UR[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    UL[v] = v4{0, 0, 0, 0};
+    UR[v] = v4{0, 0, 0, 0};
+  }
+#pragma unroll 1
+  for (int s = 0; s < S::NKS; ++s) {
+    const T al = tl[s * 64 + lane], ar = tr[s * 64 + lane];
+    const int n = 4 * s + kq;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const T bl = n < N ? w[(int64_t)(v * N + n) * ld + L] : T(0);
+      const T br = n < N ? w[(int64_t)(v * N + n) * ld + R] : T(0);
+      UL[v] = M::mma(al, bl, UL[v]);
+      UR[v] = M::mma(ar, br, UR[v]);
+    }
+  }
+  if (!live) return;
+  const T ch = (T)sc->ch;
+  auto riemann = [&](auto axis) {
+    constexpr int A = decltype(axis)::value;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = M::row(kq, j);
+      if (r >= FP) continue;
+      T uL[9], uR[9], Fx[9];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        uL[v] = UL[v][j];
+        uR[v] = UR[v][j];
+      }
+      (void)face_flux_a<T, NV, A>(uL, uR, gamma, ch, Fx);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) ffa[((int64_t)v * FP + r) * g.ldf + f] = Fx[v];
+    }
+  };
+  if (a == 0) riemann(std::integral_constant<int, 0>{});
+  else if (a == 1) riemann(std::integral_constant<int, 1>{});
+  else if constexpr (D == 3) riemann(std::integral_constant<int, 2>{});
+}
+
 // Face kernel on the matrix cores (GLM, uniform grids): one wave owns 16
 // faces of one axis; the traces of both sides at the face points are 16x16x4
 // products of the trace tables with the two cells' modes (faces as columns),
@@ -1486,6 +1579,7 @@ struct LauncherImpl : Launcher {
   const T *mfv = nullptr, *mfg = nullptr, *mfl = nullptr;  // fragment-order tables of the matrix-core cell kernel
   const T *mpv = nullptr, *mpg = nullptr, *mpl = nullptr;  // and its LDF (Powell) tables
   const T* mft = nullptr;                                   // and of the matrix-core face kernel
+  const T* mfta = nullptr;                                  // and of its octree form (sub-face tables)
   const double* mpos = nullptr;                             // and of the matrix-core positivity limiter
   int pos_variant = 1;                                      // 1: matrix-core positivity limiter where built
   int face_variant = DIVB == GLM ? 1 : 0;                   // default: matrix-core face kernel for GLM
@@ -1534,9 +1628,11 @@ struct LauncherImpl : Launcher {
       if ((e = up<T>(fv, mfv)) != hipSuccess) return e;
       if ((e = up<T>(fg, mfg)) != hipSuccess) return e;
       if ((e = up<T>(fl, mfl)) != hipSuccess) return e;
-      std::vector<double> ft;
+      std::vector<double> ft, fta;
       mfma_face_tables<T, D, DEG>(t, ft);
       if ((e = up<T>(ft, mft)) != hipSuccess) return e;
+      amr_face_tables<T, D, DEG>(t, fta);
+      if ((e = up<T>(fta, mfta)) != hipSuccess) return e;
       std::vector<double> pt;
       pos_tables<D, DEG>(t, pt);
       if ((e = up<double>(pt, mpos)) != hipSuccess) return e;
@@ -1586,8 +1682,15 @@ struct LauncherImpl : Launcher {
             hipStream_t s) override {
     if (g.level) {
       if constexpr (DIVB == GLM) {
-        const int64_t total = (int64_t)C::FP * g.NF;
-        k_face_amr<T, D, DEG><<<(unsigned)((total + 255) / 256), 256, 0, s>>>((const T*)w, (T*)ff, tb, g, sc, sp.gamma);
+        if (face_variant == 1 && mfta && g.nftile > 0) {
+          constexpr int NW = 4;
+          k_face_amr_mfma<T, D, DEG, NW><<<(unsigned)((g.nftile + NW - 1) / NW), 64 * NW, 0, s>>>(
+              (const T*)w, (T*)ff, mfta, g, sc, sp.gamma);
+        } else {
+          const int64_t total = (int64_t)C::FP * g.NF;
+          k_face_amr<T, D, DEG><<<(unsigned)((total + 255) / 256), 256, 0, s>>>((const T*)w, (T*)ff, tb, g, sc,
+                                                                                sp.gamma);
+        }
       }
       return;
     }

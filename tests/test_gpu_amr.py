@@ -60,13 +60,15 @@ def test_amr_rhs_and_steps_match_oracle(d):
 @pytest.mark.parametrize("d", [1, 2, 3])
 def test_amr_every_cell_variant_matches_oracle(d):
     """Every cell-kernel variant on an octree (LDS-tiled, matrix-core with the
-    sub-face owner gather, persistent) gives the oracle's right-hand side."""
+    sub-face owner gather, persistent), with either face kernel (per face
+    point, or matrix-core over tiles of one face class), gives the oracle's
+    right-hand side."""
     print("case amr variants", d, flush=True)
     t = small_tree(3)
     gpu, wg, orc, wo = pair(t, d, wl.Smooth(79, 3))
     r_o = orc.rhs(wo, 3.0, 1.5)
     ran = 0
-    for v in range(10):
+    for v in [c + 16 * f for f in (0, 1) for c in range(10)]:
         try:
             gpu.autotune(wg, variant=v)
         except Exception:
@@ -77,7 +79,7 @@ def test_amr_every_cell_variant_matches_oracle(d):
         err = block_rel_max(to_cells(out, orc.mesh.ncells), r_o, orc)
         assert np.all(err < 1e-12), (v, err)
         ran += 1
-    assert ran >= 8
+    assert ran >= 16
 
 
 def test_amr_fp32_steps():
