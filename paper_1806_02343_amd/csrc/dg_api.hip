@@ -45,7 +45,7 @@ struct dg_handle_s {
   double rec_q = 0.0, rec_qpos = 1.0;
   unsigned long long rec_seed = 0;
   // one captured SSP-RK3 step per state pointer (non-null streams only)
-  hipGraphExec_t graph_exec = nullptr;
+  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};  // first step of a call, later steps
   const void* graph_w = nullptr;
   std::vector<int8_t> h_level;   // octree: host copy of the leaf levels
   std::vector<int32_t> h_ijk;    // octree: host copy of the leaf coordinates
@@ -412,11 +412,20 @@ int dg_limit(dg_handle h, void* w, dg_limit_stats* stats) {
 // The launch sequence of one SSP-RK3 step: device time-step reduction, then
 // per stage the face kernel, the cell kernel (stage combination fused) and
 // the limiters.  Kernels only: the sequence can be captured into a graph.
-static void step_sequence(dg_handle h, void* w) {
+// first: the first step of a dg_step call.  Where the positivity limiter can
+// fold the max signal speed of its output into the next step's slots
+// (fused_signal), later steps take their time-step reduction from there
+// instead of evaluating the state again.
+static void step_sequence(dg_handle h, void* w, bool first) {
   const bool lim = h->p.limiter != 0;
-  launch_reset_step(h->sc, h->stream);
-  h->L->maxsig(w, h->g, h->sc, h->sp, h->stream);
-  if (h->p.divb == DG_POWELL) h->L->powell_cap(w, h->jsum, h->g, h->sc, h->sp, h->stream);
+  const bool fused = lim && h->L->fused_signal(h->g, h->sp);
+  if (first || !fused) {
+    launch_reset_step(h->sc, h->stream);
+    h->L->maxsig(w, h->g, h->sc, h->sp, h->stream);
+    if (h->p.divb == DG_POWELL) h->L->powell_cap(w, h->jsum, h->g, h->sc, h->sp, h->stream);
+  } else {
+    launch_take_next(h->sc, h->stream);
+  }
   launch_finalize_dt(h->sc, h->sp, h->p.dim, h->p.degree, h->p.divb, h->hmin, h->stream);
   auto record = [&](void* u) {
     if (h->rec_X)
@@ -437,26 +446,37 @@ static void step_sequence(dg_handle h, void* w) {
   h->L->face(h->S1, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
   h->L->cell(h->S1, w, w, h->ff, h->jp, h->g, h->sc, h->sp, 1.0 / 3.0, 2.0 / 3.0, 1, h->stream);
   record(w);
-  if (lim) h->L->limit(w, h->lscr, h->g, h->sc, h->sp, h->stream);
+  if (fused) launch_reset_next(h->sc, h->stream);
+  if (lim) h->L->limit(w, h->lscr, h->g, h->sc, h->sp, h->stream, fused);
 }
 
 static void drop_graph(dg_handle h) {
-  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
-  h->graph_exec = nullptr;
+  for (int k = 0; k < 2; ++k) {
+    if (h->graph_exec[k]) (void)hipGraphExecDestroy(h->graph_exec[k]);
+    h->graph_exec[k] = nullptr;
+  }
   h->graph_w = nullptr;
 }
 
-// Capture one step for state w on the handle's (non-null) stream.
+// Capture the first and the later steps for state w on the handle's
+// (non-null) stream.
 static int capture_step(dg_handle h, void* w) {
   drop_graph(h);
-  hipGraph_t graph = nullptr;
-  if (int r = check_hip(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal), "begin capture")) return r;
-  step_sequence(h, w);
-  hipError_t e = hipStreamEndCapture(h->stream, &graph);
-  if (e != hipSuccess) return check_hip(h, e, "end capture");
-  e = hipGraphInstantiate(&h->graph_exec, graph, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(graph);
-  if (e != hipSuccess) { h->graph_exec = nullptr; return check_hip(h, e, "graph instantiate"); }
+  for (int k = 0; k < 2; ++k) {
+    hipGraph_t graph = nullptr;
+    if (int r = check_hip(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal), "begin capture"))
+      return r;
+    step_sequence(h, w, k == 0);
+    hipError_t e = hipStreamEndCapture(h->stream, &graph);
+    if (e != hipSuccess) return check_hip(h, e, "end capture");
+    e = hipGraphInstantiate(&h->graph_exec[k], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      h->graph_exec[k] = nullptr;
+      drop_graph(h);
+      return check_hip(h, e, "graph instantiate");
+    }
+  }
   h->graph_w = w;
   return DG_OK;
 }
@@ -467,14 +487,14 @@ int dg_step(dg_handle h, void* w, int32_t nsteps, double* t) {
   launch_set_time(h->sc, 0.0, h->stream);  // device clock of this call
   launch_reset_stats(h->sc, h->stream);
   const bool graph = h->stream != nullptr && nsteps > 0;
-  if (graph && (h->graph_w != w || !h->graph_exec)) {
+  if (graph && (h->graph_w != w || !h->graph_exec[0] || !h->graph_exec[1])) {
     if (int r = capture_step(h, w)) return r;
   }
   for (int32_t n = 0; n < nsteps; ++n) {
     if (graph) {
-      if (int r = check_hip(h, hipGraphLaunch(h->graph_exec, h->stream), "graph launch")) return r;
+      if (int r = check_hip(h, hipGraphLaunch(h->graph_exec[n == 0 ? 0 : 1], h->stream), "graph launch")) return r;
     } else {
-      step_sequence(h, w);
+      step_sequence(h, w, n == 0);
       if (int r = check_launch(h, "step")) return r;
     }
   }

@@ -22,6 +22,9 @@ struct Scal {
   unsigned long long n_tvb, n_pos, n_floor, n_mlp, n_fallback;
   double inj_mass, inj_energy;
   unsigned long long n_record_stage;     // stages recorded for the learned indicator
+  // the next step's max signal and rate, folded into the last stage's
+  // positivity limiter (bit patterns of non-negative doubles)
+  unsigned long long next_maxsig_bits, next_maxrate_bits;
 };
 
 struct Grid {
@@ -87,7 +90,11 @@ struct Launcher {
   virtual void project(const double* prim, int64_t cell0, int64_t ncell, void* w, const Grid& g,
                        const SchemeParams& sp, hipStream_t s) = 0;
   // limiters in place
-  virtual void limit(void* w, void* scratch, const Grid& g, Scal* sc, const SchemeParams& sp, hipStream_t s) = 0;
+  // next_sig: also reduce the max signal speed of the limited state into the
+  // next step's slots (only where fused_signal() is true)
+  virtual void limit(void* w, void* scratch, const Grid& g, Scal* sc, const SchemeParams& sp, hipStream_t s,
+                     bool next_sig = false) = 0;
+  virtual bool fused_signal(const Grid& g, const SchemeParams& sp) const = 0;
   virtual size_t limit_scratch_bytes(const Grid& g) const = 0;
   // learned indicator helpers (GLM only; return false when not built)
   virtual bool mlp_features(const void* w, uint16_t* X, const double* sigma, const Grid& g, hipStream_t s) = 0;
@@ -104,6 +111,8 @@ Launcher* make_launcher(int precision, int D, int d, int divb);
 
 // scalar kernels
 void launch_reset_step(Scal* sc, hipStream_t s);
+void launch_reset_next(Scal* sc, hipStream_t s);  // clears the next step's signal slots
+void launch_take_next(Scal* sc, hipStream_t s);   // moves them into this step's reduction
 void launch_finalize_dt(Scal* sc, const SchemeParams& sp, int D, int d, int divb, double hmin, hipStream_t s);
 void launch_set_scalars(Scal* sc, double ch, double kappa, double dt, hipStream_t s);
 void launch_set_time(Scal* sc, double t, hipStream_t s);

@@ -1503,6 +1503,17 @@ __global__ void __launch_bounds__(256) k_project(const double* __restrict__ prim
 // ---------------------------------------------------------------------------
 // scalar kernels
 
+__global__ void k_reset_next(Scal* sc) {
+  sc->next_maxsig_bits = 0ULL;
+  sc->next_maxrate_bits = 0ULL;
+}
+
+__global__ void k_take_next(Scal* sc) {
+  sc->maxsig_bits = sc->next_maxsig_bits;
+  sc->maxrate_bits = sc->next_maxrate_bits;
+  sc->powell_rate_bits = 0ULL;
+}
+
 __global__ void k_reset_step(Scal* sc) {
   sc->maxrate_bits = 0ULL;
   sc->maxsig_bits = 0ULL;
@@ -1553,6 +1564,8 @@ void launch_reset_stats(Scal* sc, hipStream_t s) { k_reset_stats<<<1, 1, 0, s>>>
 
 void launch_set_time(Scal* sc, double t, hipStream_t s) { k_set_time<<<1, 1, 0, s>>>(sc, t); }
 void launch_reset_step(Scal* sc, hipStream_t s) { k_reset_step<<<1, 1, 0, s>>>(sc); }
+void launch_reset_next(Scal* sc, hipStream_t s) { k_reset_next<<<1, 1, 0, s>>>(sc); }
+void launch_take_next(Scal* sc, hipStream_t s) { k_take_next<<<1, 1, 0, s>>>(sc); }
 void launch_finalize_dt(Scal* sc, const SchemeParams& sp, int D, int d, int divb, double hmin, hipStream_t s) {
   k_finalize_dt<<<1, 1, 0, s>>>(sc, sp, D, d, divb, hmin);
 }
@@ -1657,7 +1670,8 @@ struct LauncherImpl : Launcher {
       persist_blocks[0] = b4 * ncu;
       persist_blocks[1] = b2 * ncu;
       int bp = 0, bm = 0;
-      if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bp, k_pos_mfma<T, D, DEG, 4>, 256, 0)) != hipSuccess)
+      if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bp, k_pos_mfma<T, D, DEG, 4, true>, 256, 0)) !=
+          hipSuccess)
         return e;
       if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bm, k_maxsig_mfma<T, D, DEG, 4>, 256, 0)) != hipSuccess)
         return e;
@@ -1869,8 +1883,13 @@ struct LauncherImpl : Launcher {
     k_project<T, D, DEG, DIVB><<<(unsigned)((ncell + TC - 1) / TC), 256, 0, s>>>(prim, cell0, ncell, (T*)w, vpw,
                                                                                 pvpw, minv64, g.ld, sp.gamma);
   }
-  void limit(void* w, void* scratch, const Grid& g, Scal* sc, const SchemeParams& sp, hipStream_t s) override {
-    launch_limit<T, D, DEG, DIVB>(w, scratch, tb, pos_variant == 1 ? mpos : nullptr, pos_blocks, g, sc, sp, s);
+  void limit(void* w, void* scratch, const Grid& g, Scal* sc, const SchemeParams& sp, hipStream_t s,
+             bool next_sig) override {
+    launch_limit<T, D, DEG, DIVB>(w, scratch, tb, pos_variant == 1 ? mpos : nullptr, pos_blocks, g, sc, sp, s,
+                                  next_sig && fused_signal(g, sp));
+  }
+  bool fused_signal(const Grid& g, const SchemeParams& sp) const override {
+    return DIVB == GLM && !g.level && (sp.limiter & 4) && pos_variant == 1 && mpos && pos_blocks > 0;
   }
   size_t limit_scratch_bytes(const Grid& g) const override { return limit_scratch<T, D, DEG, DIVB>(g); }
   bool mlp_features(const void* w, uint16_t* X, const double* sigma, const Grid& g, hipStream_t s) override {
