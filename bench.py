@@ -202,7 +202,8 @@ def main():
     flops_launch = cell_flops(D, d, divb) * ncells
     achieved = flops_launch / (r64["k_cell"] / 1e3)
     mfma = (r64["variant"] & 15) >= 4 and octree is None  # octree grids run the LDS-tiled cell kernel
-    kname = ("k_cell_mfma_powell" if divb else "k_cell_mfma") if mfma else "k_cell"
+    cv = r64["variant"] & 15
+    kname = ("k_cell_mfma_powell" if divb else ("k_cell_mfma_p" if cv >= 8 else "k_cell_mfma")) if mfma else "k_cell"
     roof = {"kernel": kname, "bound": "mfma" if mfma else "alu",
             "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
