@@ -1078,17 +1078,31 @@ __global__ void __launch_bounds__(64 * NW) k_face_amr_mfma(const T* __restrict__
     UL[v] = v4{0, 0, 0, 0};
     UR[v] = v4{0, 0, 0, 0};
   }
-#pragma unroll 1
-  for (int s = 0; s < S::NKS; ++s) {
-    const T al = tl[s * 64 + lane], ar = tr[s * 64 + lane];
-    const int n = 4 * s + kq;
+  // one side's operands of every k-step are loaded together
+  {
+    T bk[S::NKS][NV], tk[S::NKS];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const T bl = n < N ? w[(int64_t)(v * N + n) * ld + L] : T(0);
-      const T br = n < N ? w[(int64_t)(v * N + n) * ld + R] : T(0);
-      UL[v] = M::mma(al, bl, UL[v]);
-      UR[v] = M::mma(ar, br, UR[v]);
+    for (int s = 0; s < S::NKS; ++s) {
+      const int n = 4 * s + kq;
+      tk[s] = tl[s * 64 + lane];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) bk[s][v] = n < N ? w[(int64_t)(v * N + n) * ld + L] : T(0);
     }
+#pragma unroll
+    for (int s = 0; s < S::NKS; ++s)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) UL[v] = M::mma(tk[s], bk[s][v], UL[v]);
+#pragma unroll
+    for (int s = 0; s < S::NKS; ++s) {
+      const int n = 4 * s + kq;
+      tk[s] = tr[s * 64 + lane];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) bk[s][v] = n < N ? w[(int64_t)(v * N + n) * ld + R] : T(0);
+    }
+#pragma unroll
+    for (int s = 0; s < S::NKS; ++s)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) UR[v] = M::mma(tk[s], bk[s][v], UR[v]);
   }
   if (!live) return;
   const T ch = (T)sc->ch;
@@ -1165,18 +1179,32 @@ __global__ void __launch_bounds__(64 * NW) k_face_mfma(const T* __restrict__ w, 
     UL[v] = v4{0, 0, 0, 0};
     UR[v] = v4{0, 0, 0, 0};
   }
-#pragma unroll 1
-  for (int s = 0; s < S::NKS; ++s) {
-    const T tl = FT[((a * 2 + 1) * S::NKS + s) * 64 + lane];
-    const T tr = FT[((a * 2 + 0) * S::NKS + s) * 64 + lane];
-    const int n = 4 * s + kq;
+  // the left cell's operands of every k-step are loaded together, then the
+  // right cell's are loaded while the left traces are multiplied
+  {
+    T bk[S::NKS][NV], tk[S::NKS];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const T bl = n < N ? w[(int64_t)(v * N + n) * ld + FL] : T(0);
-      const T br = n < N ? w[(int64_t)(v * N + n) * ld + FR] : T(0);
-      UL[v] = M::mma(tl, bl, UL[v]);
-      UR[v] = M::mma(tr, br, UR[v]);
+    for (int s = 0; s < S::NKS; ++s) {
+      const int n = 4 * s + kq;
+      tk[s] = FT[((a * 2 + 1) * S::NKS + s) * 64 + lane];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) bk[s][v] = n < N ? w[(int64_t)(v * N + n) * ld + FL] : T(0);
     }
+#pragma unroll
+    for (int s = 0; s < S::NKS; ++s)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) UL[v] = M::mma(tk[s], bk[s][v], UL[v]);
+#pragma unroll
+    for (int s = 0; s < S::NKS; ++s) {
+      const int n = 4 * s + kq;
+      tk[s] = FT[((a * 2 + 0) * S::NKS + s) * 64 + lane];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) bk[s][v] = n < N ? w[(int64_t)(v * N + n) * ld + FR] : T(0);
+    }
+#pragma unroll
+    for (int s = 0; s < S::NKS; ++s)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) UR[v] = M::mma(tk[s], bk[s][v], UR[v]);
   }
   if (!live) return;
   const T ch = (T)sc->ch;
