@@ -491,18 +491,44 @@ struct MfmaShape {
   static constexpr int SZ_V = QT * NKS * 64;
   static constexpr int SZ_G = D * NMT * QT * 4 * 64;
   static constexpr int SZ_L = NMT * KS * 64;
+  // modes 16..N-1 when there are at most 4 of them (degree 3: modes 16..19)
+  // are accumulated on the vector ALU instead of a 16-row tile that would be
+  // mostly padding: per lane 4 modes at its own points / face points
+  static constexpr bool XR = NMT == 2 && C::N - 16 <= 4;
+  static constexpr int SZ_GX = D * QT * 64;   // [a][rt][j][k][e]
+  static constexpr int SZ_LX = KS * 16;       // [s][k][e]
 };
 
 // Fragment-order tables from the plain tables V[q][n], GW[a][q][n] and
 // LF[a][side][r][n] (row-major, as uploaded for the other kernels).
 template <typename T, int D, int DEG>
-void mfma_tables(const Tables& t, std::vector<double>& fv, std::vector<double>& fg, std::vector<double>& fl) {
+void mfma_tables(const Tables& t, std::vector<double>& fv, std::vector<double>& fg, std::vector<double>& fl,
+                 std::vector<double>& gx, std::vector<double>& lx) {
   using C = Cfg<D, DEG, GLM>;
   using S = MfmaShape<D, DEG>;
   constexpr int N = C::N, Q = C::Q, FP = C::FP;
   fv.assign(S::SZ_V, 0.0);
   fg.assign(S::SZ_G, 0.0);
   fl.assign(S::SZ_L, 0.0);
+  gx.assign(S::SZ_GX, 0.0);
+  lx.assign(S::SZ_LX, 0.0);
+  for (int a = 0; a < D; ++a)
+    for (int rt = 0; rt < S::QT; ++rt)
+      for (int j = 0; j < 4; ++j)
+        for (int k = 0; k < 4; ++k)
+          for (int e = 0; e < 4; ++e) {
+            const int q = 16 * rt + Mfma<T>::row(k, j), n = 16 + e;
+            if (q < Q && n < N) gx[(((a * S::QT + rt) * 4 + j) * 4 + k) * 4 + e] = t.GW[(a * Q + q) * N + n];
+          }
+  for (int s = 0; s < S::KS; ++s)
+    for (int k = 0; k < 4; ++k)
+      for (int e = 0; e < 4; ++e) {
+        const int kk = 4 * s + k, n = 16 + e;
+        if (kk >= 2 * D * FP || n >= N) continue;
+        const int a = kk / (2 * FP), side = (kk / FP) % 2, r = kk % FP;
+        const double v = t.LF[((a * 2 + side) * FP + r) * N + n];
+        lx[(s * 4 + k) * 4 + e] = side ? -v : v;
+      }
   for (int rt = 0; rt < S::QT; ++rt)
     for (int s = 0; s < S::NKS; ++s)
       for (int l = 0; l < 64; ++l) {
@@ -536,7 +562,8 @@ void mfma_tables(const Tables& t, std::vector<double>& fv, std::vector<double>& 
 template <typename T, int D, int DEG, bool PF, bool AMR>
 __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w, const T* w0, T* out,
                                                const T* __restrict__ ff, const T* FV, const T* FG, const T* FL,
-                                               const T* __restrict__ LFS, const T* __restrict__ Minv, const Grid& g,
+                                               const T* GX, const T* LX, const T* __restrict__ LFS,
+                                               const T* __restrict__ Minv, const Grid& g,
                                                const Scal* __restrict__ sc, double gamma, double a0, double b0,
                                                int mode) {
   using C = Cfg<D, DEG, GLM>;
@@ -544,6 +571,8 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
   using M = Mfma<T>;
   using v4 = typename M::v4;
   constexpr int N = C::N, Q = C::Q, FP = C::FP, NV = 9;
+  constexpr bool XR = S::XR && !AMR;        // last modes on the vector ALU
+  constexpr int NMU = XR ? 1 : S::NMT;      // mode tiles on the matrix cores
   const int kq = lane >> 4, cl = lane & 15;
   const int64_t K = c0 + cl;
   const bool live = K < g.C;
@@ -556,7 +585,15 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
   for (int v = 0; v < NV; ++v)
 #pragma unroll
     for (int mt = 0; mt < S::NMT; ++mt) R[v][mt] = v4{0, 0, 0, 0};
-  // face values of k-step s (face point k = 4 s + kq: axis, side, point)
+  // XR: partial sums of modes 16..19 over the lane's own points (reduced
+  // over the cell's four lanes at the end)
+  T RX[NV][4];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) RX[v][e] = T(0);
+  // face values of k-step s (face point k = 4 s + kq: axis, side, point);
+  // la[NMU] matrix-core table fragments, la[NMU..NMU+3] the XR row values
   auto load_face = [&](int s, T* fv, T* la) {
     const int k = 4 * s + kq;
     const bool kv = k < 2 * D * FP;
@@ -565,21 +602,32 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
 #pragma unroll
     for (int v = 0; v < NV; ++v) fv[v] = kv ? ff[((int64_t)(a * NV + v) * FP + r) * ld + Kf] : T(0);
 #pragma unroll
-    for (int mt = 0; mt < S::NMT; ++mt) la[mt] = FL[(mt * S::KS + s) * 64 + lane];
+    for (int mt = 0; mt < NMU; ++mt) la[mt] = FL[(mt * S::KS + s) * 64 + lane];
+    if (XR) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) la[NMU + e] = LX[(s * 4 + kq) * 4 + e];
+    }
   };
   auto surface_step = [&](const T* fv, const T* la) {
 #pragma unroll
-    for (int mt = 0; mt < S::NMT; ++mt)
+    for (int mt = 0; mt < NMU; ++mt)
 #pragma unroll
       for (int v = 0; v < NV; ++v) R[v][mt] = M::mma(la[mt], fv[v], R[v][mt]);
+    if (XR) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) RX[v][e] += la[NMU + e] * fv[v];
+    }
   };
+  constexpr int NLA = NMU + (XR ? 4 : 0);
   if (PF && !AMR) {
     // batched variant: the surface term first, while the nodal registers are
     // free, with the loads of SB k-steps in flight together
     constexpr int SB = 4;
 #pragma unroll 1
     for (int s0 = 0; s0 < S::KS; s0 += SB) {
-      T fv[SB][NV], la[SB][S::NMT];
+      T fv[SB][NV], la[SB][NLA];
 #pragma unroll
       for (int b = 0; b < SB; ++b) {
         if (s0 + b < S::KS) {
@@ -588,7 +636,7 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
 #pragma unroll
           for (int v = 0; v < NV; ++v) fv[b][v] = T(0);
 #pragma unroll
-          for (int mt = 0; mt < S::NMT; ++mt) la[b][mt] = T(0);
+          for (int mt = 0; mt < NLA; ++mt) la[b][mt] = T(0);
         }
       }
 #pragma unroll
@@ -647,10 +695,21 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
         T f[9];
         mhd_flux<T, NV>(u, a, gamma, ch2, f);
 #pragma unroll
-        for (int mt = 0; mt < S::NMT; ++mt) {
+        for (int mt = 0; mt < NMU; ++mt) {
           const T ga = FG[((((a * S::NMT + mt) * S::QT + rt) * 4 + j) * 64) + lane];
 #pragma unroll
           for (int v = 0; v < NV; ++v) R[v][mt] = M::mma(ga, qv ? f[v] : T(0), R[v][mt]);
+        }
+        if (XR) {
+          T gx[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) gx[e] = GX[(((a * S::QT + rt) * 4 + j) * 4 + kq) * 4 + e];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const T fq = qv ? f[v] : T(0);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) RX[v][e] += gx[e] * fq;
+          }
         }
       }
     }
@@ -658,10 +717,19 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
   if (!PF && !AMR) {
 #pragma unroll 1
     for (int s = 0; s < S::KS; ++s) {
-      T fv[NV], la[S::NMT];
+      T fv[NV], la[NLA];
       load_face(s, fv, la);
       surface_step(fv, la);
     }
+  }
+  if (XR) {  // sum the partials over the cell's four lanes (every lane of the cell holds the total)
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        RX[v][e] += __shfl_xor(RX[v][e], 16);
+        RX[v][e] += __shfl_xor(RX[v][e], 32);
+      }
   }
   if (AMR && live) {
     constexpr int NSUB = 1 + (1 << (D - 1)), NQ = 1 << (D - 1);
@@ -723,7 +791,12 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
         const int n = 16 * mt + M::row(kq, r);
         if (n >= N) continue;
         const int m = v * N + n;
-        T dw = R[v][mt][r] * two_h * Minv[m];
+        T racc = R[v][mt][r];
+        if (XR && mt == 1) {
+          const int e = n - 16;
+          racc = e == 0 ? RX[v][0] : e == 1 ? RX[v][1] : e == 2 ? RX[v][2] : RX[v][3];
+        }
+        T dw = racc * two_h * Minv[m];
         if (v == 8) dw -= kappa * wm[mt][r];
         if (mode == 0) out[(int64_t)m * ld + K] = dw;
         else out[(int64_t)m * ld + K] = (T)a0 * base[mt][r] + (T)b0 * (wm[mt][r] + (T)dt * dw);
@@ -734,13 +807,13 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
 template <typename T, int D, int DEG, int NW, bool PF, bool AMR>
 __global__ void __launch_bounds__(64 * NW)
     k_cell_mfma(const T* w, const T* w0, T* out, const T* __restrict__ ff, const T* __restrict__ FV,
-                const T* __restrict__ FG, const T* __restrict__ FL, const T* __restrict__ LFS,
-                const T* __restrict__ Minv, Grid g, const Scal* __restrict__ sc, double gamma, double a0, double b0,
-                int mode) {
+                const T* __restrict__ FG, const T* __restrict__ FL, const T* __restrict__ GX,
+                const T* __restrict__ LX, const T* __restrict__ LFS, const T* __restrict__ Minv, Grid g,
+                const Scal* __restrict__ sc, double gamma, double a0, double b0, int mode) {
   const int64_t c0 = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * NW + (threadIdx.x >> 6)) * 16;
   if (c0 >= g.C) return;  // whole wave; the kernel has no barrier
-  cell_tile_mfma<T, D, DEG, PF, AMR>(c0, threadIdx.x & 63, w, w0, out, ff, FV, FG, FL, LFS, Minv, g, sc, gamma, a0,
-                                     b0, mode);
+  cell_tile_mfma<T, D, DEG, PF, AMR>(c0, threadIdx.x & 63, w, w0, out, ff, FV, FG, FL, GX, LX, LFS, Minv, g, sc,
+                                     gamma, a0, b0, mode);
 }
 
 // Persistent form: one workgroup per resident slot copies the fragment
@@ -749,22 +822,24 @@ __global__ void __launch_bounds__(64 * NW)
 template <typename T, int D, int DEG, int NW, bool AMR>
 __global__ void __launch_bounds__(64 * NW)
     k_cell_mfma_p(const T* w, const T* w0, T* out, const T* __restrict__ ff, const T* __restrict__ FV,
-                  const T* __restrict__ FG, const T* __restrict__ FL, const T* __restrict__ LFS,
-                  const T* __restrict__ Minv, Grid g, const Scal* __restrict__ sc, double gamma, double a0,
-                  double b0, int mode) {
+                  const T* __restrict__ FG, const T* __restrict__ FL, const T* __restrict__ GX,
+                  const T* __restrict__ LX, const T* __restrict__ LFS, const T* __restrict__ Minv, Grid g,
+                  const Scal* __restrict__ sc, double gamma, double a0, double b0, int mode) {
   using S = MfmaShape<D, DEG>;
-  __shared__ T sV[S::SZ_V], sG[S::SZ_G], sL[S::SZ_L];
+  __shared__ T sV[S::SZ_V], sG[S::SZ_G], sL[S::SZ_L], sGX[S::SZ_GX], sLX[S::SZ_LX];
   for (int i = threadIdx.x; i < S::SZ_V; i += 64 * NW) sV[i] = FV[i];
   for (int i = threadIdx.x; i < S::SZ_G; i += 64 * NW) sG[i] = FG[i];
   for (int i = threadIdx.x; i < S::SZ_L; i += 64 * NW) sL[i] = FL[i];
+  for (int i = threadIdx.x; i < S::SZ_GX; i += 64 * NW) sGX[i] = GX[i];
+  for (int i = threadIdx.x; i < S::SZ_LX; i += 64 * NW) sLX[i] = LX[i];
   __syncthreads();
   const int64_t ntiles = (g.C + 15) / 16;
   const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
   const int64_t t0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * per;
   const int64_t t1 = t0 + per < ntiles ? t0 + per : ntiles;
   for (int64_t t = t0 + (threadIdx.x >> 6); t < t1; t += NW)
-    cell_tile_mfma<T, D, DEG, true, AMR>(t * 16, threadIdx.x & 63, w, w0, out, ff, sV, sG, sL, LFS, Minv, g, sc,
-                                         gamma, a0, b0, mode);
+    cell_tile_mfma<T, D, DEG, true, AMR>(t * 16, threadIdx.x & 63, w, w0, out, ff, sV, sG, sL, sGX, sLX, LFS, Minv,
+                                         g, sc, gamma, a0, b0, mode);
 }
 
 // ---------------------------------------------------------------------------
@@ -1618,6 +1693,7 @@ struct LauncherImpl : Launcher {
   DevTab<T> tb{};
   double *vpw = nullptr, *pvpw = nullptr, *minv64 = nullptr;
   const T *mfv = nullptr, *mfg = nullptr, *mfl = nullptr;  // fragment-order tables of the matrix-core cell kernel
+  const T *mgx = nullptr, *mlx = nullptr;                   // and its vector-ALU rows (modes 16..19)
   const T *mpv = nullptr, *mpg = nullptr, *mpl = nullptr;  // and its LDF (Powell) tables
   const T* mft = nullptr;                                   // and of the matrix-core face kernel
   const T* mfta = nullptr;                                  // and of its octree form (sub-face tables)
@@ -1653,8 +1729,8 @@ struct LauncherImpl : Launcher {
     if ((e = up<double>(t.Minv, d1)) != hipSuccess) return e;
     minv64 = (double*)d1;
     if constexpr (DIVB == POWELL) {
-      std::vector<double> fv, fg, fl, pv, pg, pl;
-      mfma_tables<T, D, DEG>(t, fv, fg, fl);
+      std::vector<double> fv, fg, fl, pv, pg, pl, gx, lx;
+      mfma_tables<T, D, DEG>(t, fv, fg, fl, gx, lx);
       powell_tables<T, D, DEG>(t, pv, pg, pl);
       if ((e = up<T>(fv, mfv)) != hipSuccess) return e;
       if ((e = up<T>(fg, mfg)) != hipSuccess) return e;
@@ -1664,11 +1740,13 @@ struct LauncherImpl : Launcher {
       if ((e = up<T>(pl, mpl)) != hipSuccess) return e;
     }
     if constexpr (DIVB == GLM) {
-      std::vector<double> fv, fg, fl;
-      mfma_tables<T, D, DEG>(t, fv, fg, fl);
+      std::vector<double> fv, fg, fl, gx, lx;
+      mfma_tables<T, D, DEG>(t, fv, fg, fl, gx, lx);
       if ((e = up<T>(fv, mfv)) != hipSuccess) return e;
       if ((e = up<T>(fg, mfg)) != hipSuccess) return e;
       if ((e = up<T>(fl, mfl)) != hipSuccess) return e;
+      if ((e = up<T>(gx, mgx)) != hipSuccess) return e;
+      if ((e = up<T>(lx, mlx)) != hipSuccess) return e;
       std::vector<double> ft, fta;
       mfma_face_tables<T, D, DEG>(t, ft);
       if ((e = up<T>(ft, mft)) != hipSuccess) return e;
@@ -1768,11 +1846,11 @@ struct LauncherImpl : Launcher {
       const unsigned grid = (unsigned)(groups < nb ? groups : nb);
       if (g.level)
         k_cell_mfma_p<T, D, DEG, NW, true><<<grid, 64 * NW, 0, s>>>((const T*)w, (const T*)w0, (T*)out,
-                                                                    (const T*)ff, mfv, mfg, mfl, tb.LFS, tb.Minv, g,
+                                                                    (const T*)ff, mfv, mfg, mfl, mgx, mlx, tb.LFS, tb.Minv, g,
                                                                     sc, sp.gamma, a0, b0, mode);
       else
         k_cell_mfma_p<T, D, DEG, NW, false><<<grid, 64 * NW, 0, s>>>((const T*)w, (const T*)w0, (T*)out,
-                                                                     (const T*)ff, mfv, mfg, mfl, tb.LFS, tb.Minv, g,
+                                                                     (const T*)ff, mfv, mfg, mfl, mgx, mlx, tb.LFS, tb.Minv, g,
                                                                      sc, sp.gamma, a0, b0, mode);
       return true;
     }
@@ -1786,11 +1864,11 @@ struct LauncherImpl : Launcher {
       const unsigned grid = (unsigned)((tiles + NW - 1) / NW);
       if (g.level)
         k_cell_mfma<T, D, DEG, NW, PF, true><<<grid, 64 * NW, 0, s>>>((const T*)w, (const T*)w0, (T*)out,
-                                                                      (const T*)ff, mfv, mfg, mfl, tb.LFS, tb.Minv, g,
+                                                                      (const T*)ff, mfv, mfg, mfl, mgx, mlx, tb.LFS, tb.Minv, g,
                                                                       sc, sp.gamma, a0, b0, mode);
       else
         k_cell_mfma<T, D, DEG, NW, PF, false><<<grid, 64 * NW, 0, s>>>((const T*)w, (const T*)w0, (T*)out,
-                                                                       (const T*)ff, mfv, mfg, mfl, tb.LFS, tb.Minv, g,
+                                                                       (const T*)ff, mfv, mfg, mfl, mgx, mlx, tb.LFS, tb.Minv, g,
                                                                        sc, sp.gamma, a0, b0, mode);
       return true;
     }
