@@ -19,11 +19,27 @@ __device__ __forceinline__ double pressure64(const T* u, double gamma) {
   return (gamma - 1.0) * ((double)u[4] - 0.5 * m2 / r - 0.5 * b2);
 }
 
+// Reciprocal used by the flux and Riemann-solver arithmetic: the hardware
+// estimate refined by Newton steps (FP64: two steps, relative error at the
+// level of the last bit; FP32: one step).  Not correctly rounded, and 1/0
+// gives NaN rather than inf (both mark a broken state).
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return r;
+}
+__device__ __forceinline__ float recip(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  r = fmaf(fmaf(-x, r, 1.0f), r, r);
+  return r;
+}
+
 // Analytic flux along axis a of the NV-component state u (NV = 9: GLM).
 template <typename T, int NV>
 __device__ __forceinline__ void mhd_flux(const T* u, int a, double gamma, T ch2, T* f) {
   const T r = u[0];
-  const T ir = T(1) / r;
+  const T ir = recip(r);
   const T v0 = u[1] * ir, v1 = u[2] * ir, v2 = u[3] * ir;
   const T b0 = u[5], b1 = u[6], b2 = u[7];
   const T p = (T)pressure64(u, gamma);
@@ -69,11 +85,11 @@ __device__ __forceinline__ void hlld_flux(const T* wl, const T* wr, T bx, double
   // divisions are products with reciprocals computed once (1/(gamma-1),
   // 1/rho per side, 1/den, 1/(S - S_M) per side)
   const T g = (T)gamma;
-  const T igm1 = T(1) / (g - T(1));
+  const T igm1 = recip(g - T(1));
   T UL[7], UR[7], FL[7], FR[7], EL, ER, ptL, ptR, cfL, cfR;
   auto cf = [&](const T* W, T* U, T* F, T& E, T& pt, T& c) {
     const T rho = W[0], u = W[1], v = W[2], w = W[3], p = W[4], by = W[5], bz = W[6];
-    const T irho = T(1) / rho;
+    const T irho = recip(rho);
     const T bb = bx * bx + by * by + bz * bz;
     E = p * igm1 + T(0.5) * rho * (u * u + v * v + w * w) + T(0.5) * bb;
     pt = p + T(0.5) * bb;
@@ -101,7 +117,7 @@ __device__ __forceinline__ void hlld_flux(const T* wl, const T* wr, T bx, double
   if (SL > T(0)) { for (int k = 0; k < 7; ++k) out[k] = FL[k]; return; }
   if (SR <= T(0)) { for (int k = 0; k < 7; ++k) out[k] = FR[k]; return; }
   const T dL = (SL - uL) * rL, dR = (SR - uR) * rR;
-  const T iden = T(1) / (dR - dL);
+  const T iden = recip(dR - dL);
   const T SM = (dR * uR - dL * uL - ptR + ptL) * iden;
   const T ptS = (dR * ptL - dL * ptR + rL * rR * (SR - uR) * (SL - uL) * (uR - uL)) * iden;
   // outer star states
@@ -113,7 +129,7 @@ __device__ __forceinline__ void hlld_flux(const T* wl, const T* wr, T bx, double
     const T d = side ? dR : dL;
     const T E = side ? ER : EL, pt = side ? ptR : ptL;
     const T rho = W[0], u = W[1], v = W[2], w = W[3], by = W[5], bz = W[6];
-    const T isd = T(1) / (S - SM);
+    const T isd = recip(S - SM);
     const T r_s = d * isd;
     const T dd = d * (S - SM) - bx * bx;
     const T sc = rho * (S - u) * (S - u);
@@ -122,7 +138,7 @@ __device__ __forceinline__ void hlld_flux(const T* wl, const T* wr, T bx, double
     if (fabs(dd) <= thr) {
       v_s = v; w_s = w; by_s = by; bz_s = bz;
     } else {
-      const T idd = T(1) / dd;
+      const T idd = recip(dd);
       v_s = v - bx * by * (SM - u) * idd;
       w_s = w - bx * bz * (SM - u) * idd;
       const T fac = (d * (S - u) - bx * bx) * idd;
@@ -139,7 +155,7 @@ __device__ __forceinline__ void hlld_flux(const T* wl, const T* wr, T bx, double
     (void)U;
   }
   const T sqL = sqrt(rs[0]), sqR = sqrt(rs[1]);
-  const T SsL = SM - fabs(bx) * (T(1) / sqL), SsR = SM + fabs(bx) * (T(1) / sqR);
+  const T SsL = SM - fabs(bx) * recip(sqL), SsR = SM + fabs(bx) * recip(sqR);
   if (SsL > T(0)) {
     for (int k = 0; k < 7; ++k) out[k] = FL[k] + SL * (Us[0][k] - UL[k]);
     return;
@@ -149,7 +165,7 @@ __device__ __forceinline__ void hlld_flux(const T* wl, const T* wr, T bx, double
     return;
   }
   const T s = bx >= T(0) ? T(1) : T(-1);
-  const T isum = T(1) / (sqL + sqR);
+  const T isum = recip(sqL + sqR);
   const T vss = (sqL * vs[0] + sqR * vs[1] + (bys[1] - bys[0]) * s) * isum;
   const T wss = (sqL * ws[0] + sqR * ws[1] + (bzs[1] - bzs[0]) * s) * isum;
   const T byss = (sqL * bys[1] + sqR * bys[0] + sqL * sqR * (vs[1] - vs[0]) * s) * isum;
@@ -173,18 +189,18 @@ __device__ __forceinline__ T face_flux_a(const T* uL, const T* uR, double gamma,
   constexpr int n = A, t1 = (A + 1) % 3, t2 = (A + 2) % 3;
   T wl[7], wr[7];
   {
-    const T ir = T(1) / uL[0];
+    const T ir = recip(uL[0]);
     wl[0] = uL[0]; wl[1] = uL[1 + n] * ir; wl[2] = uL[1 + t1] * ir; wl[3] = uL[1 + t2] * ir;
     wl[4] = (T)pressure64(uL, gamma); wl[5] = uL[5 + t1]; wl[6] = uL[5 + t2];
   }
   {
-    const T ir = T(1) / uR[0];
+    const T ir = recip(uR[0]);
     wr[0] = uR[0]; wr[1] = uR[1 + n] * ir; wr[2] = uR[1 + t1] * ir; wr[3] = uR[1 + t2] * ir;
     wr[4] = (T)pressure64(uR, gamma); wr[5] = uR[5 + t1]; wr[6] = uR[5 + t2];
   }
   const T bnL = uL[5 + n], bnR = uR[5 + n];
-  const T iL = T(1) / sqrt(uL[0]), iR = T(1) / sqrt(uR[0]);
-  const T bnF = (bnL * iL + bnR * iR) / (iL + iR);
+  const T iL = recip(sqrt(uL[0])), iR = recip(sqrt(uR[0]));
+  const T bnF = (bnL * iL + bnR * iR) * recip(iL + iR);
   T fn[7];
   hlld_flux<T>(wl, wr, bnF, gamma, fn);
   F[0] = fn[0];
@@ -193,7 +209,7 @@ __device__ __forceinline__ T face_flux_a(const T* uL, const T* uR, double gamma,
   F[5 + n] = T(0); F[5 + t1] = fn[5]; F[5 + t2] = fn[6];
   if (NV == 9) {
     const T psL = uL[8], psR = uR[8];
-    const T bn_s = T(0.5) * (bnL + bnR) - (psR - psL) / (T(2) * ch);
+    const T bn_s = T(0.5) * (bnL + bnR) - (psR - psL) * recip(T(2) * ch);
     const T ps_s = T(0.5) * (psL + psR) - T(0.5) * ch * (bnR - bnL);
     F[5 + n] = ps_s;
     F[8] = ch * ch * bn_s;
