@@ -108,7 +108,7 @@ def main():
                     help="end with one device copy of 1 GiB (the calibration kernel of the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the design notes describe how the path would shard)", file=sys.stderr)
         sys.exit(2)
 
