@@ -66,3 +66,29 @@ def test_features_layout():
     assert F[c, 0] == pytest.approx(means[0, c] / (abs(means[0, c]) + sig[0]))
     up = s.mesh.neighbor(0, 1)[c]
     assert F[c, 180 + 9 + 4] == pytest.approx((means[4, up] - means[4, c]) / (abs(means[4, c]) + sig[4]))
+
+
+def test_features_invariants():
+    """Properties of the feature map that do not restate it: (1) degree-0
+    homogeneity: scaling the state and the scales sigma by the same factor
+    leaves every feature unchanged; (2) a state that is constant in space has
+    zero neighbour differences and zero higher-mode features; (3) shifting the
+    periodic state by one cell along an axis permutes the feature rows the
+    same way (neighbour features follow their neighbours)."""
+    s = dg.DG(dg.Mesh.uniform(3, 4), 3)
+    w = s.project(dg.conserved_field(wl.Blast(2000), 5 / 3, 9))
+    sig = mlp.feature_scale(s, w)
+    F = mlp.features(s, w, sig)
+    assert np.allclose(mlp.features(s, 3.7 * w, 3.7 * sig), F, rtol=1e-13, atol=1e-15)
+    const = np.zeros_like(w)
+    for v in range(9):
+        const[:, v * s.n] = 1.0 + v
+    Fc = mlp.features(s, const, sig)
+    assert np.all(Fc[:, 180:] == 0.0)
+    for v in range(9):
+        assert np.all(Fc[:, v * 20 + 1:v * 20 + 20] == 0.0)
+        assert np.allclose(Fc[:, v * 20], (1.0 + v) / (1.0 + v + sig[v]))
+    for a in range(3):
+        up = s.mesh.neighbor(a, 1)          # cell c+1 along a
+        shifted = w[up]                     # shifted[c] = w[c+1]
+        assert np.allclose(mlp.features(s, shifted, sig), F[up], rtol=0, atol=0)
