@@ -285,7 +285,17 @@ class DG:
 
     def project_field(self, field, w, chunk=1 << 16):
         """Evaluate a pointwise primitive field (callable x[P, D] -> dict, see
-        workloads) at the library's projection points and project it into w."""
+        workloads) at the library's projection points and project it into w.
+        The point values are computed on the handle's stream, so that the
+        library's kernels read them in order and their memory is not reused
+        while a projection still reads it."""
+        torch = self.torch
+        if torch.cuda.current_stream().cuda_stream == self.stream:
+            return self._project_field(field, w, chunk)
+        with torch.cuda.stream(torch.cuda.ExternalStream(self.stream)):
+            return self._project_field(field, w, chunk)
+
+    def _project_field(self, field, w, chunk):
         torch = self.torch
         xi = torch.as_tensor(self.proj_points(), dtype=torch.float64, device="cuda")
         npts = xi.shape[0]
