@@ -216,8 +216,11 @@ int dg_time_kernel(dg_handle h, const void* w, int32_t which, int32_t reps, doub
  * persistent with the tables in LDS; for the Powell scheme 8-9 are the
  * matrix-core kernel with the LDF basis, 4 or 2 waves per block; on octree
  * grids the GLM kernels gather sub-face fluxes; where a variant is not
- * built, variant 0 runs).  Face variants: 0 LDS-staged, 1 matrix-core (GLM; also selects the
- * matrix-core max-signal-speed reduction of the time step).  *variant >= 0
+ * built, variant 0 runs).  Face variants: 0 LDS-staged; 1-3 matrix-core (GLM;
+ * also select the matrix-core max-signal-speed reduction of the time step):
+ * 1 four waves per block, 2 one wave per block, 3 one wave per block with the
+ * right traces in LDS and one face point solved at a time (two waves per
+ * SIMD); on octree grids 1-3 run the matrix-core sub-face kernel.  *variant >= 0
  * forces that schedule (DG_EINVAL if it is not built for this
  * configuration); *variant < 0 times every built cell variant, then every
  * face variant, on the state w (read only; the handle's workspaces are

@@ -1307,6 +1307,82 @@ __global__ void __launch_bounds__(64 * NW) k_face_mfma(const T* __restrict__ w, 
   else if constexpr (D == 3) riemann(std::integral_constant<int, 2>{});
 }
 
+// Low-register form of the matrix-core face kernel: the operands are loaded
+// one k-step at a time, the right traces wait in LDS, and each lane solves its
+// four face points one after another, so that two waves fit on a SIMD and one
+// wave's loads run under the other's Riemann solves.
+template <typename T, int D, int DEG, int NW>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_face_mfma_lr(const T* __restrict__ w, T* __restrict__ ff, const T* __restrict__ FT, Grid g,
+               const Scal* __restrict__ sc, double gamma) {
+  using C = Cfg<D, DEG, GLM>;
+  using S = MfmaFaceShape<D, DEG>;
+  using M = Mfma<T>;
+  using v4 = typename M::v4;
+  constexpr int N = C::N, FP = C::FP, NV = 9;
+  const int a = blockIdx.y;
+  const int lane = threadIdx.x & 63;
+  const int64_t f0 = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * NW + (threadIdx.x >> 6)) * 16;
+  if (f0 >= g.C) return;  // whole wave; no barrier in this kernel
+  const int kq = lane >> 4, cl = lane & 15;
+  const int64_t F = f0 + cl;
+  const bool live = F < g.C;
+  const int64_t FL = live ? F : f0;
+  const int64_t FR = nbr(FL, a, +1, g);
+  const int64_t ld = g.ld;
+  __shared__ T sU[NW][NV * 4 * 64];
+  T* const su = sU[threadIdx.x >> 6];
+  v4 UL[NV], UR[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    UL[v] = v4{0, 0, 0, 0};
+    UR[v] = v4{0, 0, 0, 0};
+  }
+#pragma unroll
+  for (int s = 0; s < S::NKS; ++s) {
+    const int n = 4 * s + kq;
+    const T tl = FT[((a * 2 + 1) * S::NKS + s) * 64 + lane];
+    const T tr = FT[((a * 2 + 0) * S::NKS + s) * 64 + lane];
+    T bl[NV], br[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      bl[v] = n < N ? w[(int64_t)(v * N + n) * ld + FL] : T(0);
+      br[v] = n < N ? w[(int64_t)(v * N + n) * ld + FR] : T(0);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      UL[v] = M::mma(tl, bl[v], UL[v]);
+      UR[v] = M::mma(tr, br[v], UR[v]);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) su[(v * 4 + j) * 64 + lane] = UR[v][j];
+  if (!live) return;  // LDS rows are private to the wave: no barrier
+  const T ch = (T)sc->ch;
+  auto riemann = [&](auto axis) __attribute__((always_inline)) {
+    constexpr int A = decltype(axis)::value;
+#pragma unroll 1
+    for (int j = 0; j < 4; ++j) {
+      const int r = M::row(kq, j);
+      if (r >= FP) continue;
+      T uL[9], uR[9], Fx[9];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        uL[v] = j == 0 ? UL[v][0] : j == 1 ? UL[v][1] : j == 2 ? UL[v][2] : UL[v][3];
+        uR[v] = su[(v * 4 + j) * 64 + lane];
+      }
+      (void)face_flux_a<T, NV, A>(uL, uR, gamma, ch, Fx);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) ff[((int64_t)(A * NV + v) * FP + r) * ld + F] = Fx[v];
+    }
+  };
+  if (a == 0) riemann(std::integral_constant<int, 0>{});
+  else if (a == 1) riemann(std::integral_constant<int, 1>{});
+  else if constexpr (D == 3) riemann(std::integral_constant<int, 2>{});
+}
+
 // Max signal speed on the matrix cores (GLM, uniform grids): one wave
 // evaluates 16 cells at every volume point (row tiles of the nodal table)
 // and face point (row tiles of the trace tables) with 16x16x4 products in the
@@ -1783,6 +1859,7 @@ struct LauncherImpl : Launcher {
         return e;
       pos_blocks = bp * ncu;
       maxsig_blocks = bm * ncu;
+
     }
     return hipSuccess;
   }
@@ -1802,7 +1879,7 @@ struct LauncherImpl : Launcher {
             hipStream_t s) override {
     if (g.level) {
       if constexpr (DIVB == GLM) {
-        if (face_variant == 1 && mfta && g.nftile > 0) {
+        if (face_variant >= 1 && mfta && g.nftile > 0) {
           constexpr int NW = 4;
           k_face_amr_mfma<T, D, DEG, NW><<<(unsigned)((g.nftile + NW - 1) / NW), 64 * NW, 0, s>>>(
               (const T*)w, (T*)ff, mfta, g, sc, sp.gamma);
@@ -1815,11 +1892,22 @@ struct LauncherImpl : Launcher {
       return;
     }
     if constexpr (DIVB == GLM) {
+      const int64_t tiles = (g.C + 15) / 16;
       if (face_variant == 1) {
         constexpr int NW = 4;
-        const int64_t tiles = (g.C + 15) / 16;
         dim3 grid((unsigned)((tiles + NW - 1) / NW), D);
         k_face_mfma<T, D, DEG, NW><<<grid, 64 * NW, 0, s>>>((const T*)w, (T*)ff, mft, g, sc, sp.gamma);
+        return;
+      }
+      if (face_variant == 2) {
+        dim3 grid((unsigned)tiles, D);
+        k_face_mfma<T, D, DEG, 1><<<grid, 64, 0, s>>>((const T*)w, (T*)ff, mft, g, sc, sp.gamma);
+        return;
+      }
+      if (face_variant == 3) {
+        constexpr int NW = 1;
+        dim3 grid((unsigned)((tiles + NW - 1) / NW), D);
+        k_face_mfma_lr<T, D, DEG, NW><<<grid, 64 * NW, 0, s>>>((const T*)w, (T*)ff, mft, g, sc, sp.gamma);
         return;
       }
     }
@@ -1929,8 +2017,10 @@ struct LauncherImpl : Launcher {
     }
   }
   int cell_variant_count() const override { return NVAR; }
-  // face variants: 0 LDS-staged, 1 matrix cores (GLM uniform grids)
-  int face_variant_count() const override { return DIVB == GLM ? 2 : 1; }
+  // face variants: 0 LDS-staged; GLM uniform grids, matrix cores: 1 four
+  // waves per block, 2 one wave per block, 3 low-register form at two waves
+  // per SIMD (octree grids run the matrix-core sub-face kernel for 1-3)
+  int face_variant_count() const override { return DIVB == GLM ? 4 : 1; }
   void set_face_variant(int v) override { face_variant = v < 0 ? (DIVB == GLM ? 1 : 0) : v; }
   int get_face_variant() const override { return face_variant; }
   void set_cell_variant(int v) override { cell_variant = v; }
@@ -1963,7 +2053,7 @@ struct LauncherImpl : Launcher {
   }
   void maxsig(const void* w, const Grid& g, Scal* sc, const SchemeParams& sp, hipStream_t s) override {
     if constexpr (DIVB == GLM) {
-      if (!g.level && face_variant == 1 && maxsig_blocks > 0) {
+      if (!g.level && face_variant >= 1 && maxsig_blocks > 0) {
         constexpr int NW = 4;
         const int64_t groups = ((g.C + 15) / 16 + NW - 1) / NW;
         const unsigned grid = (unsigned)(groups < maxsig_blocks ? groups : maxsig_blocks);

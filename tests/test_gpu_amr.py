@@ -68,7 +68,7 @@ def test_amr_every_cell_variant_matches_oracle(d):
     gpu, wg, orc, wo = pair(t, d, wl.Smooth(79, 3))
     r_o = orc.rhs(wo, 3.0, 1.5)
     ran = 0
-    for v in [c + 16 * f for f in (0, 1) for c in range(10)]:
+    for v in [c + 16 * f for f in range(4) for c in range(10)]:
         try:
             gpu.autotune(wg, variant=v)
         except Exception:
