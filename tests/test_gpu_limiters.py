@@ -81,3 +81,45 @@ def test_limited_steps_fp32_error_stated():
     err = rel_l1(orc, to_cells(wg, orc.mesh.ncells), wo, ch=ch)
     print("fp32 limited rel-L1", err, flush=True)
     assert np.all(err < 1e-5), err
+
+
+@pytest.mark.parametrize("D,d,precision", [(3, 3, 0), (3, 2, 0), (3, 3, 1), (2, 3, 0)])
+def test_positivity_near_floors_matches_oracle(D, d, precision):
+    """Positivity limiter on states built around the floors, in tiles of 16
+    cells: small higher modes (every point far above the floors), a spread of
+    amplitudes (some cells with points below a floor, some just above), and
+    large ones (nearly every cell scaled), in density and in energy.  Decisions,
+    counts and states match the oracle, including on tiles the GPU path
+    screens out from the means and mode magnitudes without evaluating them.
+    FP64 within 1e-12 block-relative; FP32 within 1e-6 (the scaled modes are
+    rounded to FP32)."""
+    _announce("positivity near floors", D, d, precision)
+    n = 8 if D == 3 else 24
+    gpu, wg, orc, wo = make_pair(D, d, n, dg.GLM, limiter=4, precision=precision)
+    rng = np.random.default_rng(700 + 10 * D + d)
+    C, N = orc.mesh.ncells, orc.n
+    tile = np.arange(C) // 16
+    amp = np.where(tile % 3 == 0, 1e-3, np.where(tile % 3 == 1, rng.uniform(0.05, 0.6, C), rng.uniform(0.4, 1.0, C)))
+    w = np.zeros((C, orc.nmodes))
+    for v in range(9):
+        w[:, v * N + 1:(v + 1) * N] = rng.normal(size=(C, N - 1)) * (amp / np.sqrt(N - 1))[:, None]
+    w[:, 0] = 1.0
+    for v in (1, 2, 3, 5, 6, 7, 8):
+        w[:, v * N] = rng.uniform(-0.3, 0.3, C)
+    ke = 0.5 * sum(w[:, v * N] ** 2 for v in (1, 2, 3))
+    me = 0.5 * sum(w[:, v * N] ** 2 for v in (5, 6, 7))
+    w[:, 4 * N] = 0.3 / (G - 1.0) + ke + me
+    w[:, 4 * N + 1:5 * N] *= w[:, 4 * N][:, None]
+    if precision == 1:
+        w = w.astype(np.float32).astype(np.float64)
+    wg[:, :C] = torch.as_tensor(w.T.copy(), dtype=wg.dtype, device=wg.device)
+    torch.cuda.synchronize()
+    wo2, st_o = limiters.positivity(orc, w)
+    st_g = gpu.limit(wg, stats=True)
+    scaled = np.any(wo2 != w, axis=1)
+    assert not scaled[tile % 3 == 0].any() and scaled[tile % 3 == 2].mean() > 0.9
+    assert 0 < scaled[tile % 3 == 1].sum() < (tile % 3 == 1).sum()  # mixed tiles hold both kinds
+    assert st_g["n_pos_scaled"] == st_o["n_pos_scaled"]
+    assert st_g["n_floor"] == st_o["n_floor"]
+    err = block_rel_max(to_cells(wg, C), wo2, orc)
+    assert np.all(err < (1e-12 if precision == 0 else 1e-6)), err
