@@ -19,6 +19,14 @@ __device__ __forceinline__ double pressure64(const T* u, double gamma) {
   return (gamma - 1.0) * ((double)u[4] - 0.5 * m2 / r - 0.5 * b2);
 }
 
+// The same with 1/rho given in FP64 (a product instead of a division).
+template <typename T>
+__device__ __forceinline__ double pressure64_ir(const T* u, double gamma, double ir) {
+  double m2 = (double)u[1] * (double)u[1] + (double)u[2] * (double)u[2] + (double)u[3] * (double)u[3];
+  double b2 = (double)u[5] * (double)u[5] + (double)u[6] * (double)u[6] + (double)u[7] * (double)u[7];
+  return (gamma - 1.0) * ((double)u[4] - 0.5 * m2 * ir - 0.5 * b2);
+}
+
 // Reciprocal used by the flux and Riemann-solver arithmetic: the hardware
 // estimate refined by Newton steps (FP64: two steps, relative error at the
 // level of the last bit; FP32: one step).  Not correctly rounded, and 1/0
@@ -35,6 +43,29 @@ __device__ __forceinline__ float recip(float x) {
   return r;
 }
 
+// 1/sqrt(x) the same way: the hardware estimate and Newton steps
+// r <- r (3/2 - x r^2 / 2) (FP64: two, FP32: one).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  r = fma(r, fma(-h * r, r, 0.5), r);
+  r = fma(r, fma(-h * r, r, 0.5), r);
+  return r;
+}
+__device__ __forceinline__ float rsqrt_nr(float x) {
+  float r = __builtin_amdgcn_rsqf(x);
+  r = fmaf(r, fmaf(-0.5f * x * r, r, 0.5f), r);
+  return r;
+}
+
+// Thermal pressure in FP64 for a state whose 1/rho the caller holds in type T:
+// reused in FP64, recomputed by an FP64 division otherwise.
+template <typename T>
+__device__ __forceinline__ double pressure_of(const T* u, double gamma, T ir) {
+  if constexpr (sizeof(T) == sizeof(double)) return pressure64_ir(u, gamma, (double)ir);
+  else return pressure64(u, gamma);
+}
+
 // Analytic flux along axis a of the NV-component state u (NV = 9: GLM).
 template <typename T, int NV>
 __device__ __forceinline__ void mhd_flux(const T* u, int a, double gamma, T ch2, T* f) {
@@ -42,7 +73,7 @@ __device__ __forceinline__ void mhd_flux(const T* u, int a, double gamma, T ch2,
   const T ir = recip(r);
   const T v0 = u[1] * ir, v1 = u[2] * ir, v2 = u[3] * ir;
   const T b0 = u[5], b1 = u[6], b2 = u[7];
-  const T p = (T)pressure64(u, gamma);
+  const T p = (T)pressure_of(u, gamma, ir);
   const T pt = p + T(0.5) * (b0 * b0 + b1 * b1 + b2 * b2);
   const T vb = v0 * b0 + v1 * b1 + v2 * b2;
   const T va = a == 0 ? v0 : (a == 1 ? v1 : v2);
@@ -69,11 +100,12 @@ template <typename T, int D>
 __device__ __forceinline__ double signal_sum(const T* u, double gamma) {
   double r = (double)u[0];
   if (!(r > 0.0)) return (r == r) ? 0.0 : r;
-  double p = fmax(pressure64(u, gamma), 0.0);
+  const double ir = recip(r);
+  double p = fmax(pressure64_ir(u, gamma, ir), 0.0);
   double b2 = (double)u[5] * (double)u[5] + (double)u[6] * (double)u[6] + (double)u[7] * (double)u[7];
-  double c = sqrt((gamma * p + b2) / r);
+  double c = sqrt((gamma * p + b2) * ir);
   double s = 0.0;
-  for (int a = 0; a < D; ++a) s += fabs((double)u[1 + a] / r) + c;
+  for (int a = 0; a < D; ++a) s += fabs((double)u[1 + a]) * ir + c;
   return s;
 }
 
@@ -191,15 +223,15 @@ __device__ __forceinline__ T face_flux_a(const T* uL, const T* uR, double gamma,
   {
     const T ir = recip(uL[0]);
     wl[0] = uL[0]; wl[1] = uL[1 + n] * ir; wl[2] = uL[1 + t1] * ir; wl[3] = uL[1 + t2] * ir;
-    wl[4] = (T)pressure64(uL, gamma); wl[5] = uL[5 + t1]; wl[6] = uL[5 + t2];
+    wl[4] = (T)pressure_of(uL, gamma, ir); wl[5] = uL[5 + t1]; wl[6] = uL[5 + t2];
   }
   {
     const T ir = recip(uR[0]);
     wr[0] = uR[0]; wr[1] = uR[1 + n] * ir; wr[2] = uR[1 + t1] * ir; wr[3] = uR[1 + t2] * ir;
-    wr[4] = (T)pressure64(uR, gamma); wr[5] = uR[5 + t1]; wr[6] = uR[5 + t2];
+    wr[4] = (T)pressure_of(uR, gamma, ir); wr[5] = uR[5 + t1]; wr[6] = uR[5 + t2];
   }
   const T bnL = uL[5 + n], bnR = uR[5 + n];
-  const T iL = recip(sqrt(uL[0])), iR = recip(sqrt(uR[0]));
+  const T iL = rsqrt_nr(uL[0]), iR = rsqrt_nr(uR[0]);
   const T bnF = (bnL * iL + bnR * iR) * recip(iL + iR);
   T fn[7];
   hlld_flux<T>(wl, wr, bnF, gamma, fn);
