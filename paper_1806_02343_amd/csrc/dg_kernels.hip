@@ -1238,9 +1238,12 @@ __global__ void __launch_bounds__(64 * NW) k_face_mfma(const T* __restrict__ w, 
   using M = Mfma<T>;
   using v4 = typename M::v4;
   constexpr int N = C::N, FP = C::FP, NV = 9;
-  const int a = blockIdx.y;
+  // this wave's (tile, axis) pair: the D axes of a tile are consecutive, so
+  // one XCD reads a cell's modes for all its + faces while they are in its L2
+  const int64_t pw = (int64_t)xcd_block(blockIdx.x, gridDim.x) * NW + (threadIdx.x >> 6);
+  const int a = (int)(pw % D);
   const int lane = threadIdx.x & 63;
-  const int64_t f0 = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * NW + (threadIdx.x >> 6)) * 16;
+  const int64_t f0 = (pw / D) * 16;
   if (f0 >= g.C) return;  // whole wave; no barrier in this kernel
   const int kq = lane >> 4, cl = lane & 15;
   const int64_t F = f0 + cl;
@@ -1320,9 +1323,12 @@ k_face_mfma_lr(const T* __restrict__ w, T* __restrict__ ff, const T* __restrict_
   using M = Mfma<T>;
   using v4 = typename M::v4;
   constexpr int N = C::N, FP = C::FP, NV = 9;
-  const int a = blockIdx.y;
+  // this wave's (tile, axis) pair: the D axes of a tile are consecutive, so
+  // one XCD reads a cell's modes for all its + faces while they are in its L2
+  const int64_t pw = (int64_t)xcd_block(blockIdx.x, gridDim.x) * NW + (threadIdx.x >> 6);
+  const int a = (int)(pw % D);
   const int lane = threadIdx.x & 63;
-  const int64_t f0 = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * NW + (threadIdx.x >> 6)) * 16;
+  const int64_t f0 = (pw / D) * 16;
   if (f0 >= g.C) return;  // whole wave; no barrier in this kernel
   const int kq = lane >> 4, cl = lane & 15;
   const int64_t F = f0 + cl;
@@ -1893,20 +1899,21 @@ struct LauncherImpl : Launcher {
     }
     if constexpr (DIVB == GLM) {
       const int64_t tiles = (g.C + 15) / 16;
+      // one wave per (tile, axis) pair
       if (face_variant == 1) {
         constexpr int NW = 4;
-        dim3 grid((unsigned)((tiles + NW - 1) / NW), D);
+        const unsigned grid = (unsigned)((tiles * D + NW - 1) / NW);
         k_face_mfma<T, D, DEG, NW><<<grid, 64 * NW, 0, s>>>((const T*)w, (T*)ff, mft, g, sc, sp.gamma);
         return;
       }
       if (face_variant == 2) {
-        dim3 grid((unsigned)tiles, D);
+        const unsigned grid = (unsigned)(tiles * D);
         k_face_mfma<T, D, DEG, 1><<<grid, 64, 0, s>>>((const T*)w, (T*)ff, mft, g, sc, sp.gamma);
         return;
       }
       if (face_variant == 3) {
         constexpr int NW = 1;
-        dim3 grid((unsigned)((tiles + NW - 1) / NW), D);
+        const unsigned grid = (unsigned)((tiles * D + NW - 1) / NW);
         k_face_mfma_lr<T, D, DEG, NW><<<grid, 64 * NW, 0, s>>>((const T*)w, (T*)ff, mft, g, sc, sp.gamma);
         return;
       }
