@@ -593,10 +593,12 @@ static void tune_cache_store(const char* path, const std::string& key, int v, do
   (void)ms;
 }
 
-// A schedule is (cell variant) + 16 x (face variant).
-static bool schedule_valid(Launcher* L, int v) {
+// A schedule is (cell variant) + 16 x (face variant); the two kernels must
+// agree on the face-flux layout (points or moments) of the grid.
+static bool schedule_valid(Launcher* L, const Grid& g, int v) {
   const int cv = v & 15, fv = v >> 4;
-  return v >= 0 && cv < L->cell_variant_count() && L->cell_variant_valid(cv) && fv < L->face_variant_count();
+  return v >= 0 && cv < L->cell_variant_count() && L->cell_variant_valid(cv) && fv < L->face_variant_count() &&
+         L->layout_compatible(cv, fv, g);
 }
 
 static void set_schedule(dg_handle h, int v) {
@@ -610,42 +612,48 @@ int dg_autotune(dg_handle h, const void* w, const char* cache_path, int32_t* var
   if (!variant) return fail(h, DG_EINVAL, "null variant");
   Launcher* L = h->L;
   if (*variant >= 0) {
-    if (!schedule_valid(L, *variant)) return fail(h, DG_EINVAL, "kernel variant not built for this configuration");
+    if (!schedule_valid(L, h->g, *variant))
+      return fail(h, DG_EINVAL, "kernel variant not built for this configuration, or cell and face kernels that exchange different face-flux layouts");
     set_schedule(h, *variant);
     return DG_OK;
   }
   const std::string key = tune_key(h);
   int cached = -1;
-  if (cache_path && tune_cache_lookup(cache_path, key, cached) && schedule_valid(L, cached)) {
+  if (cache_path && tune_cache_lookup(cache_path, key, cached) && schedule_valid(L, h->g, cached)) {
     set_schedule(h, cached);
     *variant = cached;
     return DG_OK;
   }
-  // cell and face kernels are independent: tune each on its own
-  int best_c = -1, best_f = 0;
-  double best_ms = 1e300;
+  // the cell and face kernels are timed on their own (each reads only its
+  // inputs), then the fastest compatible pair is kept
+  std::vector<double> cms(L->cell_variant_count(), 1e300), fms(L->face_variant_count(), 1e300);
   for (int v = 0; v < L->cell_variant_count(); ++v) {
     if (!L->cell_variant_valid(v)) continue;
     L->set_cell_variant(v);
     double ms = 0.0;
     if (int r = dg_time_kernel(h, w, 1, 1, &ms)) return r;  // warm-up
     if (int r = dg_time_kernel(h, w, 1, 3, &ms)) return r;
-    if (ms < best_ms) { best_ms = ms; best_c = v; }
+    cms[v] = ms;
   }
-  if (best_c < 0) return fail(h, DG_EUNSUPPORTED, "no cell variant built");
-  L->set_cell_variant(best_c);
-  double best_fms = 1e300;
   for (int v = 0; v < L->face_variant_count(); ++v) {
     L->set_face_variant(v);
     double ms = 0.0;
     if (int r = dg_time_kernel(h, w, 0, 1, &ms)) return r;
     if (int r = dg_time_kernel(h, w, 0, 3, &ms)) return r;
-    if (ms < best_fms) { best_fms = ms; best_f = v; }
+    fms[v] = ms;
   }
-  const int best = best_c + 16 * best_f;
+  int best = -1;
+  double best_ms = 1e300;
+  for (int c = 0; c < L->cell_variant_count(); ++c)
+    for (int f = 0; f < L->face_variant_count(); ++f)
+      if (schedule_valid(L, h->g, c + 16 * f) && cms[c] + fms[f] < best_ms) {
+        best_ms = cms[c] + fms[f];
+        best = c + 16 * f;
+      }
+  if (best < 0) return fail(h, DG_EUNSUPPORTED, "no cell variant built");
   set_schedule(h, best);
   *variant = best;
-  if (cache_path) tune_cache_store(cache_path, key, best, best_ms + best_fms);
+  if (cache_path) tune_cache_store(cache_path, key, best, best_ms);
   return DG_OK;
 }
 

@@ -79,6 +79,8 @@ struct Launcher {
   virtual bool cell_variant_valid(int v) const = 0;
   virtual void set_cell_variant(int v) = 0;
   virtual int get_cell_variant() const = 0;
+  // cell variant cv and face variant fv exchange the same face-flux layout on g
+  virtual bool layout_compatible(int cv, int fv, const Grid& g) const = 0;
   virtual int face_variant_count() const = 0;
   virtual void set_face_variant(int v) = 0;
   virtual int get_face_variant() const = 0;

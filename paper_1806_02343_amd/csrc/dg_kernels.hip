@@ -37,6 +37,8 @@ struct Cfg {
   static constexpr int NM1 = D == 2 ? DEG * (DEG + 1) / 2 : DEG * (DEG + 1) * (DEG + 2) / 6;
   static constexpr int Q = D == 2 ? P * P : P * P * P;
   static constexpr int FP = D == 2 ? P : P * P;
+  // face moments: polynomials of degree <= DEG in the face coordinates
+  static constexpr int FM = D == 2 ? P : P * (P + 1) / 2;
   static constexpr int NV = DIVB == GLM ? 9 : 8;
   static constexpr int NLEG = DIVB == GLM ? 9 : (D == 3 ? 5 : 6);
   static constexpr int NLDF = DIVB == GLM ? 0 : D * N - NM1;
@@ -454,7 +456,7 @@ __global__ void __launch_bounds__(NT)
 // 16x16x4 matrix products with the 16 cells as the column index:
 //   nodal values   U_v[q][c]  = sum_n V[q][n] w_v[n][c]              (K = modes)
 //   volume term    R_v[n][c] += sum_{a,q} GW_a[q][n] f_a,v(U(q,c))   (K = points)
-//   surface term   R_v[n][c] += sum_k LFs[n][k] Fhat_v[k][c]         (K = face points)
+//   surface term   R_v[n][c] += sum_k LFs[n][k] Fhat_v[k][c]         (K = face moments)
 // The accumulator layout of the nodal product (lane l, element r: point
 // 16 rt + row(l/16, r), cell l % 16) is the B-operand layout of the volume
 // product once its K index runs over the same points, so fluxes go from the
@@ -497,7 +499,99 @@ struct MfmaShape {
   static constexpr bool XR = NMT == 2 && C::N - 16 <= 4;
   static constexpr int SZ_GX = D * QT * 64;   // [a][rt][j][k][e]
   static constexpr int SZ_LX = KS * 16;       // [s][k][e]
+  // surface product over face moments (GLM uniform grids): K = 2 D FM
+  static constexpr int KSM = (2 * D * C::FM + 3) / 4;
+  static constexpr int SZ_LM = NMT * KSM * 64;
+  static constexpr int SZ_LXM = KSM * 16;
 };
+
+// Face moments.  A face flux enters the weak form only through its products
+// with the lift rows w_r phi_n(x_r) of the two adjacent cells, which span a
+// space of dimension FM (the traces of the basis are polynomials of degree
+// <= DEG in the face coordinates, and the two sides differ by signs only).
+// With an orthonormal basis Q of that space (FP x FM per axis), the FM
+// coordinates M = Q^T F of the point fluxes F carry the whole surface term:
+// sum_r LF[n][r] F_r = sum_m (LF Q)[n][m] M_m, exactly up to rounding.
+// Q by Gram-Schmidt (two passes) on the lift rows; false if the rank is not
+// FM or a row is not reproduced.  qb[a][r][m].
+template <int D, int DEG>
+bool face_moment_basis(const Tables& t, std::vector<double>& qb) {
+  using C = Cfg<D, DEG, GLM>;
+  constexpr int N = C::N, FP = C::FP, FM = C::FM;
+  qb.assign((size_t)D * FP * FM, 0.0);
+  for (int a = 0; a < D; ++a) {
+    auto row = [&](int side, int n, int r) { return t.LF[((a * 2 + side) * FP + r) * N + n]; };
+    double scale = 0.0;
+    for (int side = 0; side < 2; ++side)
+      for (int n = 0; n < N; ++n)
+        for (int r = 0; r < FP; ++r) scale = std::max(scale, std::fabs(row(side, n, r)));
+    std::vector<std::vector<double>> bs;
+    for (int side = 0; side < 2; ++side)
+      for (int n = 0; n < N; ++n) {
+        std::vector<double> x(FP);
+        for (int r = 0; r < FP; ++r) x[r] = row(side, n, r);
+        for (int pass = 0; pass < 2; ++pass)
+          for (const auto& b : bs) {
+            double d = 0.0;
+            for (int r = 0; r < FP; ++r) d += b[r] * x[r];
+            for (int r = 0; r < FP; ++r) x[r] -= d * b[r];
+          }
+        double nx = 0.0;
+        for (int r = 0; r < FP; ++r) nx += x[r] * x[r];
+        nx = std::sqrt(nx);
+        if (nx > 1e-8 * scale) {
+          for (int r = 0; r < FP; ++r) x[r] /= nx;
+          bs.push_back(x);
+        }
+      }
+    if ((int)bs.size() != FM) return false;
+    for (int r = 0; r < FP; ++r)
+      for (int m = 0; m < FM; ++m) qb[((size_t)a * FP + r) * FM + m] = bs[m][r];
+    for (int side = 0; side < 2; ++side)
+      for (int n = 0; n < N; ++n)
+        for (int r = 0; r < FP; ++r) {
+          double pr = 0.0;
+          for (int m = 0; m < FM; ++m) {
+            double d = 0.0;
+            for (int rr = 0; rr < FP; ++rr) d += bs[m][rr] * row(side, n, rr);
+            pr += d * bs[m][r];
+          }
+          if (std::fabs(pr - row(side, n, r)) > 1e-13 * scale) return false;
+        }
+  }
+  return true;
+}
+
+// Fragment-order lift tables of the GLM cell kernel over face moments:
+// entries (LF Q)[a][side][n][m] at K index k = (a * 2 + side) * FM + m
+// (negated on the -a side, as the point tables).
+template <typename T, int D, int DEG>
+void mfma_moment_lift(const Tables& t, const std::vector<double>& qb, std::vector<double>& fl,
+                      std::vector<double>& lx) {
+  using C = Cfg<D, DEG, GLM>;
+  using S = MfmaShape<D, DEG>;
+  constexpr int N = C::N, FP = C::FP, FM = C::FM;
+  auto lift = [&](int k, int n) {
+    const int a = k / (2 * FM), side = (k / FM) % 2, m = k % FM;
+    double v = 0.0;
+    for (int r = 0; r < FP; ++r) v += t.LF[((a * 2 + side) * FP + r) * N + n] * qb[((size_t)a * FP + r) * FM + m];
+    return side ? -v : v;
+  };
+  fl.assign(S::SZ_LM, 0.0);
+  lx.assign(S::SZ_LXM, 0.0);
+  for (int mt = 0; mt < S::NMT; ++mt)
+    for (int s = 0; s < S::KSM; ++s)
+      for (int l = 0; l < 64; ++l) {
+        const int k = 4 * s + l / 16, n = 16 * mt + l % 16;
+        if (k < 2 * D * FM && n < N) fl[(mt * S::KSM + s) * 64 + l] = lift(k, n);
+      }
+  for (int s = 0; s < S::KSM; ++s)
+    for (int k = 0; k < 4; ++k)
+      for (int e = 0; e < 4; ++e) {
+        const int kk = 4 * s + k, n = 16 + e;
+        if (kk < 2 * D * FM && n < N) lx[(s * 4 + k) * 4 + e] = lift(kk, n);
+      }
+}
 
 // Fragment-order tables from the plain tables V[q][n], GW[a][q][n] and
 // LF[a][side][r][n] (row-major, as uploaded for the other kernels).
@@ -592,17 +686,18 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
   for (int v = 0; v < NV; ++v)
 #pragma unroll
     for (int e = 0; e < 4; ++e) RX[v][e] = T(0);
-  // face values of k-step s (face point k = 4 s + kq: axis, side, point);
+  // face moments of k-step s (k = 4 s + kq: axis, side, moment);
   // la[NMU] matrix-core table fragments, la[NMU..NMU+3] the XR row values
+  constexpr int FM = C::FM;
   auto load_face = [&](int s, T* fv, T* la) {
     const int k = 4 * s + kq;
-    const bool kv = k < 2 * D * FP;
-    const int a = kv ? k / (2 * FP) : 0, side = (k / FP) % 2, r = k % FP;
+    const bool kv = k < 2 * D * FM;
+    const int a = kv ? k / (2 * FM) : 0, side = (k / FM) % 2, r = k % FM;
     const int64_t Kf = side ? Kc : nbr(Kc, a, -1, g);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) fv[v] = kv ? ff[((int64_t)(a * NV + v) * FP + r) * ld + Kf] : T(0);
+    for (int v = 0; v < NV; ++v) fv[v] = kv ? ff[((int64_t)(a * NV + v) * FM + r) * ld + Kf] : T(0);
 #pragma unroll
-    for (int mt = 0; mt < NMU; ++mt) la[mt] = FL[(mt * S::KS + s) * 64 + lane];
+    for (int mt = 0; mt < NMU; ++mt) la[mt] = FL[(mt * S::KSM + s) * 64 + lane];
     if (XR) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) la[NMU + e] = LX[(s * 4 + kq) * 4 + e];
@@ -626,11 +721,11 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
     // free, with the loads of SB k-steps in flight together
     constexpr int SB = 4;
 #pragma unroll 1
-    for (int s0 = 0; s0 < S::KS; s0 += SB) {
+    for (int s0 = 0; s0 < S::KSM; s0 += SB) {
       T fv[SB][NV], la[SB][NLA];
 #pragma unroll
       for (int b = 0; b < SB; ++b) {
-        if (s0 + b < S::KS) {
+        if (s0 + b < S::KSM) {
           load_face(s0 + b, fv[b], la[b]);
         } else {
 #pragma unroll
@@ -716,7 +811,7 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
   }
   if (!PF && !AMR) {
 #pragma unroll 1
-    for (int s = 0; s < S::KS; ++s) {
+    for (int s = 0; s < S::KSM; ++s) {
       T fv[NV], la[NLA];
       load_face(s, fv, la);
       surface_step(fv, la);
@@ -826,12 +921,12 @@ __global__ void __launch_bounds__(64 * NW)
                   const T* __restrict__ LX, const T* __restrict__ LFS, const T* __restrict__ Minv, Grid g,
                   const Scal* __restrict__ sc, double gamma, double a0, double b0, int mode) {
   using S = MfmaShape<D, DEG>;
-  __shared__ T sV[S::SZ_V], sG[S::SZ_G], sL[S::SZ_L], sGX[S::SZ_GX], sLX[S::SZ_LX];
+  __shared__ T sV[S::SZ_V], sG[S::SZ_G], sL[S::SZ_LM], sGX[S::SZ_GX], sLX[S::SZ_LXM];
   for (int i = threadIdx.x; i < S::SZ_V; i += 64 * NW) sV[i] = FV[i];
   for (int i = threadIdx.x; i < S::SZ_G; i += 64 * NW) sG[i] = FG[i];
-  for (int i = threadIdx.x; i < S::SZ_L; i += 64 * NW) sL[i] = FL[i];
+  for (int i = threadIdx.x; i < S::SZ_LM; i += 64 * NW) sL[i] = FL[i];
   for (int i = threadIdx.x; i < S::SZ_GX; i += 64 * NW) sGX[i] = GX[i];
-  for (int i = threadIdx.x; i < S::SZ_LX; i += 64 * NW) sLX[i] = LX[i];
+  for (int i = threadIdx.x; i < S::SZ_LXM; i += 64 * NW) sLX[i] = LX[i];
   __syncthreads();
   const int64_t ntiles = (g.C + 15) / 16;
   const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
@@ -1212,14 +1307,18 @@ struct MfmaFaceShape {
   using C = Cfg<D, DEG, GLM>;
   static constexpr int NKS = (C::N + 3) / 4;
   static constexpr int SZ = D * 2 * NKS * 64;
+  static constexpr int SZM = SZ + D * 4 * 64;  // and the moment tables, one per axis
   static_assert(C::FP <= 16, "face points per face fit one 16-row tile");
 };
 
+// Trace tables (A operands: face points x modes), then per axis the moment
+// table Q^T (A operand: moments x points) with its K index in the order of
+// the flux accumulator rows, so the point fluxes are its B operands as they lie.
 template <typename T, int D, int DEG>
-void mfma_face_tables(const Tables& t, std::vector<double>& ft) {
+void mfma_face_tables(const Tables& t, const std::vector<double>& qb, std::vector<double>& ft) {
   using C = Cfg<D, DEG, GLM>;
   using S = MfmaFaceShape<D, DEG>;
-  ft.assign(S::SZ, 0.0);
+  ft.assign(S::SZM, 0.0);
   for (int a = 0; a < D; ++a)
     for (int side = 0; side < 2; ++side)
       for (int s = 0; s < S::NKS; ++s)
@@ -1227,6 +1326,44 @@ void mfma_face_tables(const Tables& t, std::vector<double>& ft) {
           const int r = l % 16, n = 4 * s + l / 16;
           if (r < C::FP && n < C::N) ft[((a * 2 + side) * S::NKS + s) * 64 + l] = t.TF[((a * 2 + side) * C::FP + r) * C::N + n];
         }
+  for (int a = 0; a < D; ++a)
+    for (int s = 0; s < 4; ++s)
+      for (int l = 0; l < 64; ++l) {
+        const int m = l % 16, r = Mfma<T>::row(l / 16, s);
+        if (m < C::FM && r < C::FP) ft[S::SZ + (a * 4 + s) * 64 + l] = qb[((size_t)a * C::FP + r) * C::FM + m];
+      }
+}
+
+// Face moments of one wave's 16 faces along axis A from the point fluxes FX
+// (accumulator layout: element j of lane l is point row(l/16, j) of face
+// l % 16): 16x16x4 products with the moment table; rows < FM stored.
+// fx(v, j): the flux of variable v at the lane's point j (ROLL: one variable
+// at a time, for fluxes held in LDS).
+template <typename T, int D, int DEG, int A, bool ROLL = false, typename FX>
+__device__ __forceinline__ void store_face_moments(FX&& fx, const T* __restrict__ FT, T* __restrict__ ff,
+                                                   int lane, int64_t F, bool live, int64_t ld) {
+  using C = Cfg<D, DEG, GLM>;
+  using S = MfmaFaceShape<D, DEG>;
+  using M = Mfma<T>;
+  using V4 = typename M::v4;
+  constexpr int NV = 9, FM = C::FM;
+  T mt[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) mt[s] = FT[S::SZ + (A * 4 + s) * 64 + lane];
+  const int kq = lane >> 4;
+#pragma unroll(ROLL ? 1 : NV)
+  for (int v = 0; v < NV; ++v) {
+    V4 acc = V4{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc = M::mma(mt[s], fx(v, s), acc);
+    if (live) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int m = M::row(kq, e);
+        if (m < FM) ff[((int64_t)(A * NV + v) * FM + m) * ld + F] = acc[e];
+      }
+    }
+  }
 }
 
 template <typename T, int D, int DEG, int NW>
@@ -1284,26 +1421,34 @@ __global__ void __launch_bounds__(64 * NW) k_face_mfma(const T* __restrict__ w, 
 #pragma unroll
       for (int v = 0; v < NV; ++v) UR[v] = M::mma(tk[s], bk[s][v], UR[v]);
   }
-  if (!live) return;
   const T ch = (T)sc->ch;
-  // the axis is uniform over the block: one branch per axis keeps every
-  // component index of the Riemann solver a compile-time constant
+  // the axis is uniform over the wave: one branch per axis keeps every
+  // component index of the Riemann solver a compile-time constant.  Every
+  // lane stays for the moment products (dead lanes and padding rows carry
+  // zero fluxes).
   auto riemann = [&](auto axis) {
     constexpr int A = decltype(axis)::value;
+    v4 FX[NV];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int r = M::row(kq, j);
-      if (r >= FP) continue;
-      T uL[9], uR[9], Fx[9];
+      T Fx[9];
+      if (live && r < FP) {
+        T uL[9], uR[9];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        uL[v] = UL[v][j];
-        uR[v] = UR[v][j];
+        for (int v = 0; v < NV; ++v) {
+          uL[v] = UL[v][j];
+          uR[v] = UR[v][j];
+        }
+        (void)face_flux_a<T, NV, A>(uL, uR, gamma, ch, Fx);
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Fx[v] = T(0);
       }
-      (void)face_flux_a<T, NV, A>(uL, uR, gamma, ch, Fx);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) ff[((int64_t)(A * NV + v) * FP + r) * ld + F] = Fx[v];
+      for (int v = 0; v < NV; ++v) FX[v][j] = Fx[v];
     }
+    store_face_moments<T, D, DEG, A>([&](int v, int j) { return FX[v][j]; }, FT, ff, lane, F, live, ld);
   };
   if (a == 0) riemann(std::integral_constant<int, 0>{});
   else if (a == 1) riemann(std::integral_constant<int, 1>{});
@@ -1365,24 +1510,32 @@ k_face_mfma_lr(const T* __restrict__ w, T* __restrict__ ff, const T* __restrict_
   for (int v = 0; v < NV; ++v)
 #pragma unroll
     for (int j = 0; j < 4; ++j) su[(v * 4 + j) * 64 + lane] = UR[v][j];
-  if (!live) return;  // LDS rows are private to the wave: no barrier
+  // each lane reads and writes only its own LDS slots: no barrier
   const T ch = (T)sc->ch;
   auto riemann = [&](auto axis) __attribute__((always_inline)) {
     constexpr int A = decltype(axis)::value;
+    // the point fluxes replace the right traces in LDS, slot by slot
 #pragma unroll 1
     for (int j = 0; j < 4; ++j) {
       const int r = M::row(kq, j);
-      if (r >= FP) continue;
-      T uL[9], uR[9], Fx[9];
+      T Fx[9];
+      if (live && r < FP) {
+        T uL[9], uR[9];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        uL[v] = j == 0 ? UL[v][0] : j == 1 ? UL[v][1] : j == 2 ? UL[v][2] : UL[v][3];
-        uR[v] = su[(v * 4 + j) * 64 + lane];
+        for (int v = 0; v < NV; ++v) {
+          uL[v] = j == 0 ? UL[v][0] : j == 1 ? UL[v][1] : j == 2 ? UL[v][2] : UL[v][3];
+          uR[v] = su[(v * 4 + j) * 64 + lane];
+        }
+        (void)face_flux_a<T, NV, A>(uL, uR, gamma, ch, Fx);
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Fx[v] = T(0);
       }
-      (void)face_flux_a<T, NV, A>(uL, uR, gamma, ch, Fx);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) ff[((int64_t)(A * NV + v) * FP + r) * ld + F] = Fx[v];
+      for (int v = 0; v < NV; ++v) su[(v * 4 + j) * 64 + lane] = Fx[v];
     }
+    store_face_moments<T, D, DEG, A, true>([&](int v, int j) { return su[(v * 4 + j) * 64 + lane]; }, FT, ff, lane,
+                                           F, live, ld);
   };
   if (a == 0) riemann(std::integral_constant<int, 0>{});
   else if (a == 1) riemann(std::integral_constant<int, 1>{});
@@ -1776,6 +1929,7 @@ struct LauncherImpl : Launcher {
   double *vpw = nullptr, *pvpw = nullptr, *minv64 = nullptr;
   const T *mfv = nullptr, *mfg = nullptr, *mfl = nullptr;  // fragment-order tables of the matrix-core cell kernel
   const T *mgx = nullptr, *mlx = nullptr;                   // and its vector-ALU rows (modes 16..19)
+  // (GLM: mfl and mlx lift face moments; Powell: face points)
   const T *mpv = nullptr, *mpg = nullptr, *mpl = nullptr;  // and its LDF (Powell) tables
   const T* mft = nullptr;                                   // and of the matrix-core face kernel
   const T* mfta = nullptr;                                  // and of its octree form (sub-face tables)
@@ -1822,15 +1976,19 @@ struct LauncherImpl : Launcher {
       if ((e = up<T>(pl, mpl)) != hipSuccess) return e;
     }
     if constexpr (DIVB == GLM) {
-      std::vector<double> fv, fg, fl, gx, lx;
+      // uniform grids: the matrix-core face kernels store face moments and
+      // the matrix-core cell kernel lifts them (tables over moments)
+      std::vector<double> qb, fv, fg, fl, gx, lx, flm, lxm;
+      if (!face_moment_basis<D, DEG>(t, qb)) return hipErrorInvalidValue;
       mfma_tables<T, D, DEG>(t, fv, fg, fl, gx, lx);
+      mfma_moment_lift<T, D, DEG>(t, qb, flm, lxm);
       if ((e = up<T>(fv, mfv)) != hipSuccess) return e;
       if ((e = up<T>(fg, mfg)) != hipSuccess) return e;
-      if ((e = up<T>(fl, mfl)) != hipSuccess) return e;
+      if ((e = up<T>(flm, mfl)) != hipSuccess) return e;
       if ((e = up<T>(gx, mgx)) != hipSuccess) return e;
-      if ((e = up<T>(lx, mlx)) != hipSuccess) return e;
+      if ((e = up<T>(lxm, mlx)) != hipSuccess) return e;
       std::vector<double> ft, fta;
-      mfma_face_tables<T, D, DEG>(t, ft);
+      mfma_face_tables<T, D, DEG>(t, qb, ft);
       if ((e = up<T>(ft, mft)) != hipSuccess) return e;
       amr_face_tables<T, D, DEG>(t, fta);
       if ((e = up<T>(fta, mfta)) != hipSuccess) return e;
@@ -2028,6 +2186,12 @@ struct LauncherImpl : Launcher {
   // waves per block, 2 one wave per block, 3 low-register form at two waves
   // per SIMD (octree grids run the matrix-core sub-face kernel for 1-3)
   int face_variant_count() const override { return DIVB == GLM ? 4 : 1; }
+  // GLM uniform grids: the LDS kernels (cell 0-3, face 0) exchange point
+  // fluxes, the matrix-core ones (cell 4-9, face 1-3) face moments
+  bool layout_compatible(int cv, int fv, const Grid& g) const override {
+    if (DIVB != GLM || g.level) return true;
+    return (fv >= 1) == (cv >= 4);
+  }
   void set_face_variant(int v) override { face_variant = v < 0 ? (DIVB == GLM ? 1 : 0) : v; }
   int get_face_variant() const override { return face_variant; }
   void set_cell_variant(int v) override { cell_variant = v; }
@@ -2047,6 +2211,9 @@ struct LauncherImpl : Launcher {
     if (v == 8 && launch_cell_mfma_p<4>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
     if (v == 9 && launch_cell_mfma_p<2>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
     if ((v == 8 || v == 9) && launch_cell_powell(v == 8 ? 4 : 2, w, w0, out, ff, jp, g, sc, sp, a0, b0, mode, s)) return;
+    // GLM: a persistent form that cannot be resident runs the batched one
+    // (same face-flux layout)
+    if (v >= 8 && launch_cell_mfma<4, true>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
     if (v >= 4) {  // not built for this configuration
       v = 0;
       while (v < 4 && !cell_variant_valid(v)) ++v;
