@@ -220,11 +220,16 @@ int dg_time_kernel(dg_handle h, const void* w, int32_t which, int32_t reps, doub
  * also select the matrix-core max-signal-speed reduction of the time step):
  * 1 four waves per block, 2 one wave per block, 3 one wave per block with the
  * right traces in LDS and one face point solved at a time (two waves per
- * SIMD); on octree grids 1-3 run the matrix-core sub-face kernel.  *variant >= 0
- * forces that schedule (DG_EINVAL if it is not built for this
- * configuration); *variant < 0 times every built cell variant, then every
- * face variant, on the state w (read only; the handle's workspaces are
- * written) and keeps the fastest of each.  Before any call the schedule is
+ * SIMD); on octree grids 1-3 run the matrix-core sub-face kernel.  On
+ * uniform GLM grids the matrix-core face kernels hand the cell kernel face
+ * moments (the projections of the face fluxes on the polynomials of degree
+ * <= d in the face coordinates, the only part of a face flux the weak form
+ * uses) and the LDS kernels face-point values, so a schedule pairs cell 0-3
+ * with face 0 or cell 4-9 with face 1-3.  *variant >= 0 forces that schedule
+ * (DG_EINVAL if it is not built for this configuration or pairs the two
+ * layouts); *variant < 0 times every built cell variant and every face
+ * variant on the state w (read only; the handle's workspaces are written)
+ * and keeps the fastest valid pair.  Before any call the schedule is
  * 6 + 16 (GLM) or 8 (Powell).  cache_path (may be NULL): a JSON
  * file of earlier choices keyed by precision, dimension, degree, divergence
  * scheme and cell count; an entry found there is used without timing and new
