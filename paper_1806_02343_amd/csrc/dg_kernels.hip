@@ -719,7 +719,7 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
   if (PF && !AMR) {
     // batched variant: the surface term first, while the nodal registers are
     // free, with the loads of SB k-steps in flight together
-    constexpr int SB = 4;
+    constexpr int SB = 5;
 #pragma unroll 1
     for (int s0 = 0; s0 < S::KSM; s0 += SB) {
       T fv[SB][NV], la[SB][NLA];
@@ -867,9 +867,17 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
   // keeps every load of an element before its store; loading a variable's
   // elements together first keeps those loads in flight at once.  Each
   // (mode, cell) element belongs to exactly one lane.
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    T wm[S::NMT][4], base[S::NMT][4];
+  // Each (mode, cell) element belongs to exactly one lane and each variable
+  // owns its rows, so the operands of variable v+1 (its state, stage base
+  // and inverse-mass entries) may be loaded before the stores of v, even
+  // when out aliases w or w0: two variables' loads are in flight while one
+  // is combined and stored (FP64; FP32 loads each variable's operands just
+  // before it, keeping its registers for two waves per SIMD).  The inverse-
+  // mass entries are loaded with the other operands: out is not known not
+  // to alias Minv, so a load of Minv after a store would wait for that store.
+  constexpr bool AHEAD = sizeof(T) == 8;
+  T ew[2][S::NMT][4], eb[2][S::NMT][4], em[2][S::NMT][4];
+  auto eload = [&](int v, T (&wm)[S::NMT][4], T (&base)[S::NMT][4], T (&mi)[S::NMT][4]) {
 #pragma unroll
     for (int mt = 0; mt < S::NMT; ++mt)
 #pragma unroll
@@ -878,7 +886,17 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
         const int64_t at = (int64_t)(v * N + (n < N ? n : 0)) * ld + K;
         wm[mt][r] = (v == 8 || mode != 0) ? w[at] : T(0);
         base[mt][r] = mode != 0 ? w0[at] : T(0);
+        mi[mt][r] = n < N ? Minv[v * N + n] : T(0);
       }
+  };
+  eload(0, ew[0], eb[0], em[0]);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    if (AHEAD && v + 1 < NV) eload(v + 1, ew[(v + 1) & 1], eb[(v + 1) & 1], em[(v + 1) & 1]);
+    if (!AHEAD && v > 0) eload(v, ew[v & 1], eb[v & 1], em[v & 1]);
+    const auto& wm = ew[v & 1];
+    const auto& base = eb[v & 1];
+    const auto& mi = em[v & 1];
 #pragma unroll
     for (int mt = 0; mt < S::NMT; ++mt)
 #pragma unroll
@@ -891,7 +909,7 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
           const int e = n - 16;
           racc = e == 0 ? RX[v][0] : e == 1 ? RX[v][1] : e == 2 ? RX[v][2] : RX[v][3];
         }
-        T dw = racc * two_h * Minv[m];
+        T dw = racc * two_h * mi[mt][r];
         if (v == 8) dw -= kappa * wm[mt][r];
         if (mode == 0) out[(int64_t)m * ld + K] = dw;
         else out[(int64_t)m * ld + K] = (T)a0 * base[mt][r] + (T)b0 * (wm[mt][r] + (T)dt * dw);
