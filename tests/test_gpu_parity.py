@@ -202,3 +202,35 @@ def test_every_cell_variant_fp32(case):
         assert np.all(err < 5e-4), (v, err)
         ran += 1
     assert ran >= 8
+
+
+def test_schedule_pairs_face_flux_layouts():
+    """On uniform GLM grids the LDS kernels (cell 0-3, face 0) exchange face-point
+    fluxes and the matrix-core kernels (cell 4-9, face 1-3) face moments: a
+    schedule that pairs the two is refused, every compatible pair matches the
+    oracle, and the autotuner keeps a compatible pair."""
+    from paper_1806_02343_amd.binding import DGError
+    _announce("schedule layouts")
+    gpu, wg, orc, wo = make_pair(3, 2, 6, dg.GLM)
+    dt, ch, kappa = orc.timestep(wo)
+    r_o = orc.rhs(wo, ch, kappa)
+    for v in (0 + 16 * 1, 3 + 16 * 2, 4 + 16 * 0, 9 + 16 * 0):
+        with pytest.raises(DGError):
+            gpu.autotune(wg, variant=v)
+    lds = []
+    for c in range(4):  # the LDS tile shapes built for this configuration
+        try:
+            gpu.autotune(wg, variant=c)
+            lds.append(c)
+        except DGError:
+            pass
+    assert lds
+    for v in (lds[0], 4 + 16 * 1, 8 + 16 * 3):
+        gpu.autotune(wg, variant=v)
+        out = gpu.empty_state()
+        gpu.rhs(wg, out, ch, kappa)
+        torch.cuda.synchronize()
+        err = block_rel_max(to_cells(out, orc.mesh.ncells), r_o, orc)
+        assert np.all(err < 1e-12), (v, err)
+    chosen = gpu.autotune(wg)
+    assert ((chosen >> 4) >= 1) == ((chosen & 15) >= 4), chosen
