@@ -58,6 +58,14 @@ __device__ __forceinline__ float rsqrt_nr(float x) {
   return r;
 }
 
+// sqrt(x) as x / sqrt(x) from the refined reciprocal square root: a few ulp,
+// 0 at 0, NaN for x < 0 or NaN (as sqrt would).
+template <typename T>
+__device__ __forceinline__ T sqrt_nr(T x) {
+  const T r = x * rsqrt_nr(x);
+  return x == T(0) ? T(0) : r;
+}
+
 // Thermal pressure in FP64 for a state whose 1/rho the caller holds in type T:
 // reused in FP64, recomputed by an FP64 division otherwise.
 template <typename T>
@@ -138,7 +146,7 @@ __device__ __forceinline__ void hlld_flux(const T* wl, const T* wr, T bx, double
     const T s = (gp + bb) * irho;
     T disc = s * s - T(4) * gp * bx * bx * (irho * irho);
     disc = disc > T(0) ? disc : T(0);
-    c = sqrt(T(0.5) * (s + sqrt(disc)));
+    c = sqrt_nr(T(0.5) * (s + sqrt_nr(disc)));
   };
   cf(wl, UL, FL, EL, ptL, cfL);
   cf(wr, UR, FR, ER, ptR, cfR);
@@ -186,8 +194,9 @@ __device__ __forceinline__ void hlld_flux(const T* wl, const T* wr, T bx, double
     Us[side][4] = E_s; Us[side][5] = by_s; Us[side][6] = bz_s;
     (void)U;
   }
-  const T sqL = sqrt(rs[0]), sqR = sqrt(rs[1]);
-  const T SsL = SM - fabs(bx) * recip(sqL), SsR = SM + fabs(bx) * recip(sqR);
+  const T iqL = rsqrt_nr(rs[0]), iqR = rsqrt_nr(rs[1]);  // 1/sqrt(rho*) per side
+  const T sqL = rs[0] * iqL, sqR = rs[1] * iqR;
+  const T SsL = SM - fabs(bx) * iqL, SsR = SM + fabs(bx) * iqR;
   if (SsL > T(0)) {
     for (int k = 0; k < 7; ++k) out[k] = FL[k] + SL * (Us[0][k] - UL[k]);
     return;
