@@ -1566,7 +1566,7 @@ k_face_mfma_lr(const T* __restrict__ w, T* __restrict__ ff, const T* __restrict_
 // state's precision, the modes held in registers; wave and block maxima
 // (NaN-propagating) feed one atomic per block.
 template <typename T, int D, int DEG, int NW>
-__global__ void __launch_bounds__(64 * NW) k_maxsig_mfma(const T* __restrict__ w, const T* __restrict__ FV,
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2))) k_maxsig_mfma(const T* __restrict__ w, const T* __restrict__ FV,
                                                          const T* __restrict__ FT, Grid g, Scal* sc, double gamma) {
   using C = Cfg<D, DEG, GLM>;
   using S = MfmaShape<D, DEG>;
