@@ -204,7 +204,7 @@ def _alfven_l1_error(n, d, tend=0.2):
     return (np.abs(U[ph.B1] - exact) * wq).sum() / (4 * m.ncells)
 
 
-@pytest.mark.parametrize("d", [1, 2])
+@pytest.mark.parametrize("d", [1, 2, 3])
 def test_alfven_wave_convergence_order(d):
     # Sec. 5.2.3: travelling circularly polarised Alfven wave, order d+1
     e = [_alfven_l1_error(n, d) for n in (8, 16, 32)]

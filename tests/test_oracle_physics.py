@@ -171,3 +171,34 @@ def test_face_normal_field_alfven_weighting():
     # the lighter side (larger Alfven speed) gets the larger weight
     b = ph.face_normal_field(np.array([1.0]), np.array([0.25]), np.array([0.0]), np.array([4.0]))
     assert np.isclose(b[0], 0.8)
+
+
+@pytest.mark.parametrize("wave", [-1, +1])
+@pytest.mark.parametrize("speed", [0.07, -0.05])
+@pytest.mark.parametrize("bn", [0.8, -0.6])
+def test_hlld_resolves_isolated_rotational_discontinuity(wave, speed, bn):
+    """An isolated rotational (Alfven) discontinuity is resolved exactly by
+    HLLD (its middle waves are the Alfven waves): rho, p, u_n, B_n and |B_t|
+    are continuous, B_t rotates and v_t jumps by -wave sgn(B_n) [B_t]/sqrt(rho)
+    where the discontinuity moves at u_n + wave |B_n|/sqrt(rho) (the jump
+    conditions of the ideal-MHD system in the discontinuity's frame).  The
+    exact face flux is that of the state on the face: F(U_L) if the
+    discontinuity moves right, F(U_R) if it moves left."""
+    rho, p = 1.3, 0.7
+    sq = np.sqrt(rho)
+    un = speed - wave * abs(bn) / sq          # the discontinuity moves at `speed`
+    btL = np.array([0.5, -0.35])
+    th = 1.1
+    btR = np.array([np.cos(th) * btL[0] - np.sin(th) * btL[1], np.sin(th) * btL[0] + np.cos(th) * btL[1]])
+    vtL = np.array([0.2, -0.1])
+    vtR = vtL - wave * np.sign(bn) * (btR - btL) / sq
+    UL = ph.prim_to_cons(np.array([rho]), np.array([[un], [vtL[0]], [vtL[1]]]), np.array([p]),
+                         np.array([[bn], [btL[0]], [btL[1]]]), G)
+    UR = ph.prim_to_cons(np.array([rho]), np.array([[un], [vtR[0]], [vtR[1]]]), np.array([p]),
+                         np.array([[bn], [btR[0]], [btR[1]]]), G)
+    fL, fR = ph.flux(UL, 0, G)[:, 0], ph.flux(UR, 0, G)[:, 0]
+    # the constructed pair satisfies the jump conditions at that speed
+    assert np.allclose(fR - fL, speed * (UR - UL)[:, 0], atol=1e-14)
+    F, bnF = ph.numerical_flux(UL, UR, 0, G)
+    expect = fL if speed > 0 else fR
+    assert np.allclose(F[:, 0], expect, rtol=1e-13, atol=1e-13 * np.abs(expect).max())
