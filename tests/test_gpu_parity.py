@@ -234,3 +234,34 @@ def test_schedule_pairs_face_flux_layouts():
         assert np.all(err < 1e-12), (v, err)
     chosen = gpu.autotune(wg)
     assert ((chosen >> 4) >= 1) == ((chosen & 15) >= 4), chosen
+
+
+def test_powell_dt_cap_binds_matches_oracle():
+    """Powell time-step cap (eq. powell_dt with |div B|_K from the face jumps of
+    eq. divb-cell) on a state with O(0.1) normal-field jumps at every face and
+    a small eta, so that the cap and not eq. cfl sets the step: dg_dt and two
+    SSP-RK3 steps against the oracle."""
+    from paper_1806_02343_amd import DG
+    _announce("powell cap")
+    D, d, n, eta = 3, 2, 6, 1e-6
+    orc = dg.DG(dg.Mesh.uniform(D, n), d, divb=dg.POWELL, powell_eta=eta)
+    rng = np.random.default_rng(77)
+    wo = orc.project(dg.conserved_field(wl.Smooth(1000 * D + d, D), 5.0 / 3.0, orc.nvar))
+    nl = 5 * orc.n
+    wo[:, :nl] += 0.02 * rng.normal(size=(orc.mesh.ncells, nl)) * (np.arange(nl) % orc.n != 0)
+    wo[:, nl:] += 0.05 * rng.normal(size=(orc.mesh.ncells, orc.nldf))
+    gpu = DG(D, d, n, divb=dg.POWELL, powell_eta=eta)
+    wg = torch.as_tensor(orc.to_abi(wo, gpu.ld), device="cuda")
+    dt_o, _, _ = orc.timestep(wo)
+    dt_cfl = dg.DG(dg.Mesh.uniform(D, n), d, divb=dg.POWELL).timestep(wo)[0]
+    assert dt_o < 0.2 * dt_cfl          # the cap binds by a wide margin
+    dt_g, _, _ = gpu.dt(wg)
+    assert abs(dt_g - dt_o) <= 1e-13 * dt_o
+    t_o = 0.0
+    for _ in range(2):
+        wo, dt, _, _ = orc.step(wo)
+        t_o += dt
+    t_g = gpu.step(wg, 2)
+    assert abs(t_g - t_o) <= 1e-12 * t_o
+    err = rel_l1(orc, to_cells(wg, orc.mesh.ncells), wo)
+    assert np.all(err < 1e-12), err
