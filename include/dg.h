@@ -138,6 +138,19 @@ int dg_dt(dg_handle h, const void* w, double* dt, double* ch, double* kappa);
  * given).  w and dwdt: [nmodes][ld] device arrays (distinct).  Async. */
 int dg_rhs(dg_handle h, const void* w, void* dwdt, double ch, double kappa);
 
+/* The same right-hand side as dg_rhs (same kernels, same result) for
+ * callers that cannot allocate device memory at call time: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.  Its
+ * workspace (face fluxes, Powell normal-field jumps, device scalars) lives in
+ * one 32 MiB device array of the library per device, whose address is
+ * resolved at dg_init; the call allocates nothing.  DG_EINVAL (no device
+ * work) if the mesh needs more than 32 MiB of workspace (3-D degree 3 FP64:
+ * about 9,700 cells; 2-D degree 1 FP64: about 116,000 cells) or if the
+ * current device is not the one the handle was created on.  All calls on one
+ * device share that array: calls that overlap on one device (two streams,
+ * two threads) race and must be ordered by the caller.  Async. */
+int dg_rhs_noalloc(dg_handle h, const void* w, void* dwdt, double ch, double kappa);
+
 /* Apply the limiters selected in dg_params.limiter to w in place (slope
  * limiter first, then positivity).  stats == NULL: async; otherwise the
  * stream is synchronised and stats filled. */

@@ -11,7 +11,8 @@ DG_FP64, DG_FP32 = 0, 1
 DG_LIM_TVB, DG_LIM_CHAR, DG_LIM_POS, DG_LIM_LEARNED = 1, 2, 4, 8
 DG_MESH_UNIFORM, DG_MESH_OCTREE = 0, 1
 
-EXPORTS = ["dg_init", "dg_layout", "dg_proj_points", "dg_project", "dg_dt", "dg_rhs", "dg_limit", "dg_step",
+EXPORTS = ["dg_init", "dg_layout", "dg_proj_points", "dg_project", "dg_dt", "dg_rhs", "dg_rhs_noalloc", "dg_limit",
+           "dg_step",
            "dg_mlp_scale", "dg_mlp_set", "dg_mlp_get", "dg_mlp_features", "dg_mlp_labels", "dg_mlp_record", "dg_mlp_forward",
            "dg_mlp_grad", "dg_mlp_train", "dg_time_kernel", "dg_autotune", "dg_last_error", "dg_destroy"]
 MLP_NPARAM = 24833
@@ -64,6 +65,7 @@ def load_library(path=LIB_PATH):
     lib.dg_project.argtypes = [P, P, I64, I64, P]
     lib.dg_dt.argtypes = [P, P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)]
     lib.dg_rhs.argtypes = [P, P, P, D, D]
+    lib.dg_rhs_noalloc.argtypes = [P, P, P, D, D]
     lib.dg_limit.argtypes = [P, P, ctypes.POINTER(dg_limit_stats)]
     lib.dg_step.argtypes = [P, P, I32, ctypes.POINTER(D)]
     F32P = ctypes.POINTER(ctypes.c_float)
@@ -178,6 +180,9 @@ class DG:
 
     def rhs(self, w, dwdt, ch, kappa):
         self._check(self.lib.dg_rhs(self.h, _ptr(w), _ptr(dwdt), ch, kappa))
+
+    def rhs_noalloc(self, w, dwdt, ch, kappa):
+        self._check(self.lib.dg_rhs_noalloc(self.h, _ptr(w), _ptr(dwdt), ch, kappa))
 
     def limit(self, w, stats=False):
         if stats:

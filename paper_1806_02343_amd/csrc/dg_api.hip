@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <new>
 #include <random>
 #include <sstream>
@@ -51,12 +52,40 @@ struct dg_handle_s {
   std::vector<int32_t> h_ijk;    // octree: host copy of the leaf coordinates
   double hmin = 0.0;
   size_t elem = 8;
+  int device = 0;             // HIP device current at dg_init
+  void* scratch = nullptr;    // that device's address of the file-scope scratch array
   std::string err;
 };
+
+// Workspace of dg_rhs_noalloc: the face buffer, the Powell jump buffer and
+// the device scalars of one right-hand side, for callers that cannot
+// allocate device memory.  One copy per device, held until the process ends;
+// every dg_rhs_noalloc call on a device shares it.
+static constexpr size_t kScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
 std::string g_err;  // message for failures before a handle exists
+
+// Device address of `scratch` per device, resolved once per device with
+// that device current (the host-side name is not a device address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+hipError_t scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return hipSuccess;
+}
 
 int fail(dg_handle h, int code, const std::string& msg) {
   if (h) h->err = msg; else g_err = msg;
@@ -266,6 +295,14 @@ int dg_init(const dg_params* p, const dg_mesh* m, void* hip_stream, dg_handle* o
 
   dg_handle h = new (std::nothrow) dg_handle_s();
   if (!h) return fail(nullptr, DG_ENOMEM, "host allocation");
+  {
+    hipError_t e = hipGetDevice(&h->device);
+    if (e == hipSuccess) e = scratch_address(h->device, &h->scratch);
+    if (e != hipSuccess) {
+      delete h;
+      return fail(nullptr, DG_EHIP, std::string("scratch address: ") + hipGetErrorString(e));
+    }
+  }
   h->p = *p;
   h->stream = (hipStream_t)hip_stream;
   h->elem = p->precision == DG_FP64 ? 8 : 4;
@@ -377,6 +414,34 @@ int dg_rhs(dg_handle h, const void* w, void* dwdt, double ch, double kappa) {
   h->L->face(w, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
   h->L->cell(w, w, dwdt, h->ff, h->jp, h->g, h->sc, h->sp, 0.0, 1.0, 0, h->stream);
   return check_launch(h, "rhs");
+}
+
+int dg_rhs_noalloc(dg_handle h, const void* w, void* dwdt, double ch, double kappa) {
+  if (int r = valid_state(h, w)) return r;
+  if (!dwdt || dwdt == w) return fail(h, DG_EINVAL, "dwdt must be a distinct array");
+  if (h->p.divb == DG_GLM && !(ch > 0.0)) return fail(h, DG_EINVAL, "GLM needs c_h > 0");
+  int dev = -1;
+  if (int r = check_hip(h, hipGetDevice(&dev), "get device")) return r;
+  if (dev != h->device) return fail(h, DG_EINVAL, "dg_rhs_noalloc: the handle's device is not the current device");
+  // layout in the scratch array: scalars, face buffer, Powell jump buffer
+  const size_t off_ff = (sizeof(Scal) + 255) / 256 * 256;
+  const size_t nff = h->L->face_buffer_elems(h->g) * h->elem;
+  const size_t off_jp = off_ff + (nff + 255) / 256 * 256;
+  const size_t need = off_jp + h->L->jump_buffer_elems(h->g) * h->elem;
+  if (need > kScratchBytes) {
+    std::ostringstream m;
+    m << "dg_rhs_noalloc: this mesh needs " << need << " bytes of workspace, the scratch array holds "
+      << kScratchBytes;
+    return fail(h, DG_EINVAL, m.str());
+  }
+  unsigned char* base = (unsigned char*)h->scratch;
+  Scal* sc = (Scal*)base;
+  void* ff = base + off_ff;
+  void* jp = h->L->jump_buffer_elems(h->g) ? (void*)(base + off_jp) : nullptr;
+  launch_set_scalars(sc, ch, kappa, 0.0, h->stream);
+  h->L->face(w, ff, jp, h->g, sc, h->sp, h->stream);
+  h->L->cell(w, w, dwdt, ff, jp, h->g, sc, h->sp, 0.0, 1.0, 0, h->stream);
+  return check_launch(h, "rhs_noalloc");
 }
 
 int dg_limit(dg_handle h, void* w, dg_limit_stats* stats) {

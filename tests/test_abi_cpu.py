@@ -64,6 +64,7 @@ def test_null_handle_calls_return_einval():
     lib = B.load_library()
     assert lib.dg_layout(None, None, None, None) == B.DG_EINVAL
     assert lib.dg_rhs(None, None, None, 1.0, 0.0) == B.DG_EINVAL
+    assert lib.dg_rhs_noalloc(None, None, None, 1.0, 0.0) == B.DG_EINVAL
     assert lib.dg_step(None, None, 1, None) == B.DG_EINVAL
     lib.dg_destroy(None)
 
