@@ -66,7 +66,8 @@ enum {
   DG_EHIP = -3,          /* a HIP runtime call failed */
   DG_ENOMEM = -4,        /* device allocation failed */
   DG_ENONFINITE = -5,    /* a non-finite value appeared in the state */
-  DG_ECH = -6            /* GLM with fixed c_h: c_h < 2 * max signal speed seen */
+  DG_ECH = -6            /* warning: GLM with fixed c_h below twice the largest signal
+                            speed (Sec. 4.1.5); the call completed and its outputs are valid */
 };
 enum { DG_GLM = 0, DG_POWELL = 1 };
 enum { DG_FP64 = 0, DG_FP32 = 1 };
@@ -103,9 +104,13 @@ typedef struct {
   const int32_t* ijk;  /* [host] */
 } dg_mesh;
 
-/* Limiter statistics of one dg_limit call / one dg_step (summed over stages). */
+/* Limiter statistics of one dg_limit call.  n_floor counts the cell-average
+ * floors that fired (density and pressure separately); injected_mass and
+ * injected_energy are what they added, summed over cells in a fixed order
+ * (bitwise reproducible); n_ch_violation counts the time-step evaluations of
+ * the call whose fixed c_h was below twice the largest signal speed. */
 typedef struct {
-  int64_t n_tvb_triggered, n_mlp_flagged, n_fallback, n_pos_scaled, n_floor;
+  int64_t n_tvb_triggered, n_mlp_flagged, n_fallback, n_pos_scaled, n_floor, n_ch_violation;
   double injected_mass, injected_energy, max_signal, ch;
 } dg_limit_stats;
 
@@ -130,7 +135,9 @@ int dg_proj_points(dg_handle h, double* xi /*[host] or NULL*/, int64_t* npts /*[
 int dg_project(dg_handle h, const double* prim, int64_t cell0, int64_t ncell, void* w);
 
 /* Time step of the state w (eq. cfl; Powell cap eq. powell_dt; GLM c_h and
- * kappa = c_h^2 / c_p^2 of Sec. 4.1.5).  Synchronous; outputs on the host. */
+ * kappa = c_h^2 / c_p^2 of Sec. 4.1.5).  Synchronous; outputs on the host.
+ * DG_ENONFINITE if the state's signal speed is not finite; DG_ECH (outputs
+ * valid) if a fixed c_h is below twice the largest signal speed. */
 int dg_dt(dg_handle h, const void* w, double* dt, double* ch, double* kappa);
 
 /* dwdt = M^-1 R(w): the semi-discrete right-hand side of eq. wdot including
@@ -153,7 +160,9 @@ int dg_rhs_noalloc(dg_handle h, const void* w, void* dwdt, double ch, double kap
 
 /* Apply the limiters selected in dg_params.limiter to w in place (slope
  * limiter first, then positivity).  stats == NULL: async; otherwise the
- * stream is synchronised and stats filled. */
+ * stream is synchronised, stats filled, the limited state scanned for
+ * non-finite weights (DG_ENONFINITE, state left as computed) and DG_ECH
+ * returned (state valid) if the c_h check of the call failed. */
 int dg_limit(dg_handle h, void* w, dg_limit_stats* stats /*[host] or NULL*/);
 
 /* Advance w by nsteps SSP-RK3 steps (Sec. 3.6); dt, c_h and kappa are
@@ -161,7 +170,10 @@ int dg_limit(dg_handle h, void* w, dg_limit_stats* stats /*[host] or NULL*/);
  * selected limiters run after every stage (Sec. 4.3: before any state is
  * evaluated at quadrature points again).  Limiting the initial state is the
  * caller's dg_limit call.  t (host, may be NULL) is advanced by the sum of
- * the steps' dt; a non-NULL t synchronises. */
+ * the steps' dt; a non-NULL t synchronises and checks the call: DG_ENONFINITE
+ * if a non-finite value met a time-step reduction or is left in the final
+ * state (state left as computed), else DG_ECH (state valid) if a fixed c_h
+ * was below twice the largest signal speed at some step. */
 int dg_step(dg_handle h, void* w, int32_t nsteps, double* t /*[host] in/out*/);
 
 /* Learned troubled-cell indicator (GLM on uniform grids).  The network maps

@@ -37,6 +37,7 @@ class dg_mesh(ctypes.Structure):
 class dg_limit_stats(ctypes.Structure):
     _fields_ = [("n_tvb_triggered", ctypes.c_int64), ("n_mlp_flagged", ctypes.c_int64),
                 ("n_fallback", ctypes.c_int64), ("n_pos_scaled", ctypes.c_int64), ("n_floor", ctypes.c_int64),
+                ("n_ch_violation", ctypes.c_int64),
                 ("injected_mass", ctypes.c_double), ("injected_energy", ctypes.c_double),
                 ("max_signal", ctypes.c_double), ("ch", ctypes.c_double)]
 
@@ -45,6 +46,10 @@ class DGError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"dg error {code}: {msg}")
         self.code = code
+
+
+class DGWarning(RuntimeWarning):
+    """Warning-class status (DG_ECH): the call completed, its outputs are valid."""
 
 
 _lib = None
@@ -141,7 +146,10 @@ class DG:
         self.dtype = torch.float64 if precision == DG_FP64 else torch.float32
 
     def _check(self, rc):
-        if rc != DG_OK:
+        if rc == DG_ECH:
+            import warnings
+            warnings.warn(DGWarning(self.lib.dg_last_error(self.h).decode()), stacklevel=3)
+        elif rc != DG_OK:
             raise DGError(rc, self.lib.dg_last_error(self.h).decode())
 
     def close(self):

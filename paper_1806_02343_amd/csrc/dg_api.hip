@@ -354,6 +354,7 @@ int dg_init(const dg_params* p, const dg_mesh* m, void* hip_stream, dg_handle* o
   if ((e = hipMemset(h->S1, 0, nm * g.ld * h->elem)) != hipSuccess) return cleanup(DG_EHIP, "stage buffer clear");
   if (size_t ls = h->L->limit_scratch_bytes(g)) {
     if ((e = hipMalloc(&h->lscr, ls)) != hipSuccess) return cleanup(DG_ENOMEM, "limiter scratch");
+    if ((e = hipMemset(h->lscr, 0, ls)) != hipSuccess) return cleanup(DG_EHIP, "limiter scratch clear");
   }
   if ((e = hipMalloc(&h->sc, sizeof(Scal))) != hipSuccess) return cleanup(DG_ENOMEM, "scalars");
   if ((e = hipMemset(h->sc, 0, sizeof(Scal))) != hipSuccess) return cleanup(DG_EHIP, "scalars clear");
@@ -393,8 +394,23 @@ static int dt_sequence(dg_handle h, const void* w) {
   return check_launch(h, "time step");
 }
 
+// Status of a completed call from its device counters: a non-finite value
+// first, then the warning-class c_h check (Sec. 4.1.5: c_h is checked at
+// runtime against twice the largest signal speed).
+static int call_status(dg_handle h, const Scal& s) {
+  if (s.nonfinite) return fail(h, DG_ENONFINITE, "non-finite value in the state");
+  if (s.n_ch_violation) {
+    std::ostringstream m;
+    m << "fixed c_h = " << s.ch << " is below twice the largest signal speed (" << s.n_ch_violation
+      << " time-step evaluation(s))";
+    return fail(h, DG_ECH, m.str());
+  }
+  return DG_OK;
+}
+
 int dg_dt(dg_handle h, const void* w, double* dt, double* ch, double* kappa) {
   if (int r = valid_state(h, w)) return r;
+  launch_reset_stats(h->sc, h->stream);
   if (int r = dt_sequence(h, w)) return r;
   Scal s;
   if (int r = check_hip(h, hipMemcpyAsync(&s, h->sc, sizeof(Scal), hipMemcpyDeviceToHost, h->stream), "copy")) return r;
@@ -402,8 +418,7 @@ int dg_dt(dg_handle h, const void* w, double* dt, double* ch, double* kappa) {
   if (dt) *dt = s.dt;
   if (ch) *ch = s.ch;
   if (kappa) *kappa = s.kappa;
-  if (s.nonfinite) return fail(h, DG_ENONFINITE, "non-finite signal speed");
-  return DG_OK;
+  return call_status(h, s);
 }
 
 int dg_rhs(dg_handle h, const void* w, void* dwdt, double ch, double kappa) {
@@ -457,6 +472,8 @@ int dg_limit(dg_handle h, void* w, dg_limit_stats* stats) {
   if (h->p.limiter) h->L->limit(w, h->lscr, h->g, h->sc, h->sp, h->stream);
   if (int r = check_launch(h, "limit")) return r;
   if (stats) {
+    launch_scan_nonfinite(w, h->elem, h->L->nmodes(), h->g.ld, h->g.C, h->sc, h->stream);
+    if (int r = check_launch(h, "scan")) return r;
     Scal s;
     if (int r = check_hip(h, hipMemcpyAsync(&s, h->sc, sizeof(Scal), hipMemcpyDeviceToHost, h->stream), "copy")) return r;
     if (int r = check_hip(h, hipStreamSynchronize(h->stream), "sync")) return r;
@@ -465,11 +482,12 @@ int dg_limit(dg_handle h, void* w, dg_limit_stats* stats) {
     stats->n_fallback = (int64_t)s.n_fallback;
     stats->n_pos_scaled = (int64_t)s.n_pos;
     stats->n_floor = (int64_t)s.n_floor;
+    stats->n_ch_violation = (int64_t)s.n_ch_violation;
     stats->injected_mass = s.inj_mass;
     stats->injected_energy = s.inj_energy;
     stats->max_signal = s.last_maxsig;
     stats->ch = s.ch;
-    if (s.nonfinite) return fail(h, DG_ENONFINITE, "non-finite value in the state");
+    return call_status(h, s);
   }
   return DG_OK;
 }
@@ -564,11 +582,13 @@ int dg_step(dg_handle h, void* w, int32_t nsteps, double* t) {
     }
   }
   if (t) {
+    launch_scan_nonfinite(w, h->elem, h->L->nmodes(), h->g.ld, h->g.C, h->sc, h->stream);
+    if (int r = check_launch(h, "scan")) return r;
     Scal s;
     if (int r = check_hip(h, hipMemcpyAsync(&s, h->sc, sizeof(Scal), hipMemcpyDeviceToHost, h->stream), "copy")) return r;
     if (int r = check_hip(h, hipStreamSynchronize(h->stream), "sync")) return r;
     *t += s.t;
-    if (s.nonfinite) return fail(h, DG_ENONFINITE, "non-finite value in the state");
+    return call_status(h, s);
   }
   return DG_OK;
 }

@@ -21,6 +21,7 @@ struct Scal {
   // limiter statistics (accumulated, reset by the host)
   unsigned long long n_tvb, n_pos, n_floor, n_mlp, n_fallback;
   double inj_mass, inj_energy;
+  unsigned int tally_flag;               // some cell's floor slots hold a value (k_tally_reduce)
   unsigned long long n_record_stage;     // stages recorded for the learned indicator
   // the next step's max signal and rate, folded into the last stage's
   // positivity limiter (bit patterns of non-negative doubles)
@@ -118,6 +119,9 @@ void launch_take_next(Scal* sc, hipStream_t s);   // moves them into this step's
 void launch_finalize_dt(Scal* sc, const SchemeParams& sp, int D, int d, int divb, double hmin, hipStream_t s);
 void launch_set_scalars(Scal* sc, double ch, double kappa, double dt, hipStream_t s);
 void launch_set_time(Scal* sc, double t, hipStream_t s);
-void launch_reset_stats(Scal* sc, hipStream_t s);
+void launch_reset_stats(Scal* sc, hipStream_t s);  // limiter tallies, non-finite and c_h-violation counts
+// flags any non-finite weight of w (nmodes rows of ld, C columns used)
+void launch_scan_nonfinite(const void* w, size_t elem, int64_t nmodes, int64_t ld, int64_t C, Scal* sc,
+                           hipStream_t s);
 
 }  // namespace dgmhd

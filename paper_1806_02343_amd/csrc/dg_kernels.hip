@@ -1914,6 +1914,31 @@ __global__ void k_set_time(Scal* sc, double t) { sc->t = t; }
 __global__ void k_reset_stats(Scal* sc) {
   sc->n_tvb = sc->n_pos = sc->n_floor = sc->n_mlp = sc->n_fallback = 0ULL;
   sc->inj_mass = sc->inj_energy = 0.0;
+  sc->nonfinite = 0ULL;
+  sc->n_ch_violation = 0ULL;
+}
+
+// Any non-finite weight in the used columns of the state sets the flag.
+template <typename T>
+__global__ void __launch_bounds__(256) k_scan_nonfinite(const T* __restrict__ w, int64_t nmodes, int64_t ld,
+                                                        int64_t C, Scal* sc) {
+  const int64_t n = nmodes * C;
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const int64_t m = i / C, c = i - m * C;
+    const T x = w[m * ld + c];
+    bad = bad || !(x - x == T(0));  // NaN and +-inf
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicAdd(&sc->nonfinite, 1ULL);
+}
+
+void launch_scan_nonfinite(const void* w, size_t elem, int64_t nmodes, int64_t ld, int64_t C, Scal* sc,
+                           hipStream_t s) {
+  const int64_t n = nmodes * C;
+  const int64_t blocks = (n + 255) / 256;
+  const unsigned grid = (unsigned)(blocks < 4096 ? (blocks > 0 ? blocks : 1) : 4096);
+  if (elem == 8) k_scan_nonfinite<double><<<grid, 256, 0, s>>>((const double*)w, nmodes, ld, C, sc);
+  else k_scan_nonfinite<float><<<grid, 256, 0, s>>>((const float*)w, nmodes, ld, C, sc);
 }
 
 void launch_reset_stats(Scal* sc, hipStream_t s) { k_reset_stats<<<1, 1, 0, s>>>(sc); }

@@ -72,5 +72,5 @@ def test_null_handle_calls_return_einval():
 def test_struct_layouts_match_header():
     # field order and sizes of the ABI structs (6 int32 + 13 double, etc.)
     assert ctypes.sizeof(B.dg_params) == 6 * 4 + 13 * 8
-    assert ctypes.sizeof(B.dg_limit_stats) == 5 * 8 + 4 * 8
+    assert ctypes.sizeof(B.dg_limit_stats) == 6 * 8 + 4 * 8
     assert ctypes.sizeof(B.dg_mesh) == 4 + 12 + 24 + 8 + 8 + 8
