@@ -483,6 +483,11 @@ struct Mfma<float> {
   static constexpr __host__ __device__ int row(int k, int r) { return 4 * k + r; }
 };
 
+// Matrix-core GLM kernels in FP32 on uniform grids: two waves per SIMD
+// (256 registers per lane)
+template <typename T, bool AMR>
+constexpr int cell_waves_per_eu() { return (sizeof(T) == 4 && !AMR) ? 2 : 1; }
+
 template <int D, int DEG>
 struct MfmaShape {
   using C = Cfg<D, DEG, GLM>;
@@ -501,6 +506,40 @@ struct MfmaShape {
   static constexpr int SZ_LX = KS * 16;       // [s][k][e]
   // surface product over face moments (GLM uniform grids): K = 2 D FM
   static constexpr int KSM = (2 * D * C::FM + 3) / 4;
+  // rows per (axis, variable) of the moment buffer: the FM moments, and in
+  // the FP32 deviation form two more rows (the face's reference flux minus
+  // the left and the right cell's mean flux)
+  template <typename T>
+  static constexpr int fms() { return sizeof(T) == 4 ? C::FM + 2 : C::FM; }
+  // index of the mode xi_a^k (Legendre degree k along axis a, 0 along the
+  // others) in the graded order of the modes
+  static constexpr int power_mode(int a, int k) {
+    int idx = 0;
+    for (int g = 0; g <= DEG; ++g)
+      for (int k1 = g; k1 >= 0; --k1) {
+        if (D == 2) {
+          const int e[2] = {k1, g - k1};
+          if (e[a] == k && g == k) return idx;
+          ++idx;
+        } else {
+          for (int k2 = g - k1; k2 >= 0; --k2) {
+            const int e[3] = {k1, k2, g - k1 - k2};
+            if (e[a] == k && g == k) return idx;
+            ++idx;
+          }
+        }
+      }
+    return -1;
+  }
+  struct PowModes {
+    int m[3][4];
+  };
+  static constexpr PowModes pow_modes() {
+    PowModes p{};
+    for (int a = 0; a < 3; ++a)
+      for (int k = 0; k < 4; ++k) p.m[a][k] = (a < D && k <= DEG) ? power_mode(a, k) : 0;
+    return p;
+  }
   static constexpr int SZ_LM = NMT * KSM * 64;
   static constexpr int SZ_LXM = KSM * 16;
 };
@@ -653,11 +692,28 @@ void mfma_tables(const Tables& t, std::vector<double>& fv, std::vector<double>& 
 // AMR: octree grid; the surface term is then an owner gather of the 1 or
 // 2^(D-1) (sub-)face fluxes of each side with the sub-face tables LFS,
 // accumulated on the vector ALU straight into the accumulator elements.
+//
+// FP32 deviation form (DEV: FP32 state on uniform grids).  A constant flux c
+// added to every volume and face flux of a cell changes nothing in exact
+// arithmetic (the quadrature integrates d_a phi over the cell and phi over
+// its faces exactly, and the two cancel), but in FP32 the products of a
+// large constant background flux leave rounding noise of ~1e-7 of it in
+// every mode of a quiet region.  So the FP32 products act on deviations
+// only: the nodal product omits mode 0 (the deviation du from the cell
+// mean), the volume flux is the flux deviation f_a(mean + du) - f_a(mean)
+// in the rearranged form of mhd_dflux, and the face moments are those of
+// F* - c with c the FP32-rounded flux of the face's left-cell mean.  The
+// face kernel also stores, in two extra rows, c - f_a(mean) of the left and
+// of the right cell (FP64 differences, small, rounded to FP32); each cell adds
+// the lift of its side's constant over the face, which turns every face term
+// into F* minus the cell's own mean flux.  The lift of a constant over a
+// face only reaches the modes xi_a^k.  A uniform state gives zero up to FP64
+// rounding.
 template <typename T, int D, int DEG, bool PF, bool AMR>
 __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w, const T* w0, T* out,
                                                const T* __restrict__ ff, const T* FV, const T* FG, const T* FL,
                                                const T* GX, const T* LX, const T* __restrict__ LFS,
-                                               const T* __restrict__ Minv, const Grid& g,
+                                               const T* __restrict__ L1, const T* __restrict__ Minv, const Grid& g,
                                                const Scal* __restrict__ sc, double gamma, double a0, double b0,
                                                int mode) {
   using C = Cfg<D, DEG, GLM>;
@@ -667,6 +723,8 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
   constexpr int N = C::N, Q = C::Q, FP = C::FP, NV = 9;
   constexpr bool XR = S::XR && !AMR;        // last modes on the vector ALU
   constexpr int NMU = XR ? 1 : S::NMT;      // mode tiles on the matrix cores
+  constexpr bool DEV = sizeof(T) == 4 && !AMR;
+  constexpr int FMS = S::template fms<T>();
   const int kq = lane >> 4, cl = lane & 15;
   const int64_t K = c0 + cl;
   const bool live = K < g.C;
@@ -674,6 +732,14 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
   const int64_t ld = g.ld;
   const T ch = (T)sc->ch;
   const T ch2 = ch * ch;
+  // DEV: the cell's mean state as the reference of the flux deviations
+  MeanRef mref;
+  if constexpr (DEV) {
+    float ub[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ub[v] = (float)w[(int64_t)(v * N) * ld + Kc];
+    mref.init(ub, gamma);
+  }
   v4 R[NV][S::NMT];
 #pragma unroll
   for (int v = 0; v < NV; ++v)
@@ -695,7 +761,7 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
     const int a = kv ? k / (2 * FM) : 0, side = (k / FM) % 2, r = k % FM;
     const int64_t Kf = side ? Kc : nbr(Kc, a, -1, g);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) fv[v] = kv ? ff[((int64_t)(a * NV + v) * FM + r) * ld + Kf] : T(0);
+    for (int v = 0; v < NV; ++v) fv[v] = kv ? ff[((int64_t)(a * NV + v) * FMS + r) * ld + Kf] : T(0);
 #pragma unroll
     for (int mt = 0; mt < NMU; ++mt) la[mt] = FL[(mt * S::KSM + s) * 64 + lane];
     if (XR) {
@@ -747,7 +813,7 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const int n = 4 * s + kq;
-        bw[PF ? s : 0][v] = n < N ? w[(int64_t)(v * N + n) * ld + Kc] : T(0);
+        bw[PF ? s : 0][v] = (n < N && !(DEV && n == 0)) ? w[(int64_t)(v * N + n) * ld + Kc] : T(0);
       }
   }
 
@@ -770,7 +836,7 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
         const T ac = FV[(rt * S::NKS + s) * 64 + lane];
         T bc[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) bc[v] = n < N ? w[(int64_t)(v * N + n) * ld + Kc] : T(0);
+        for (int v = 0; v < NV; ++v) bc[v] = (n < N && !(DEV && n == 0)) ? w[(int64_t)(v * N + n) * ld + Kc] : T(0);
 #pragma unroll
         for (int v = 0; v < NV; ++v) U[v] = M::mma(ac, bc[v], U[v]);
       }
@@ -785,10 +851,18 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
         u[0] = T(1);
         u[4] = T(1);
       }
+      DevPoint dq;
+      if constexpr (DEV) dev_point(mref, (const float*)u, gamma, dq);
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         T f[9];
-        mhd_flux<T, NV>(u, a, gamma, ch2, f);
+        if constexpr (DEV) {
+          if (a == 0) mhd_dflux<NV, 0>(mref, (const float*)u, dq, (float)ch2, (float*)f);
+          else if (a == 1) mhd_dflux<NV, 1>(mref, (const float*)u, dq, (float)ch2, (float*)f);
+          else mhd_dflux<NV, 2>(mref, (const float*)u, dq, (float)ch2, (float*)f);
+        } else {
+          mhd_flux<T, NV>(u, a, gamma, ch2, f);
+        }
 #pragma unroll
         for (int mt = 0; mt < NMU; ++mt) {
           const T ga = FG[((((a * S::NMT + mt) * S::QT + rt) * 4 + j) * 64) + lane];
@@ -825,6 +899,35 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
         RX[v][e] += __shfl_xor(RX[v][e], 16);
         RX[v][e] += __shfl_xor(RX[v][e], 32);
       }
+  }
+  if constexpr (DEV) {
+    // each face carries F* - c: add the lift of the stored constant
+    // c - f_a(cell mean) of the cell's side over the face (L1[side][a][n],
+    // signed as the lift tables; nonzero only for the modes xi_a^k)
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      T dl[NV], dr[NV];
+      const int64_t Kb = nbr(Kc, a, -1, g);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        dl[v] = ff[((int64_t)(a * NV + v) * FMS + C::FM) * ld + Kc];       // +a face: this cell is its left cell
+        dr[v] = ff[((int64_t)(a * NV + v) * FMS + C::FM + 1) * ld + Kb];   // -a face: this cell is its right cell
+      }
+      constexpr typename S::PowModes PM = S::pow_modes();
+#pragma unroll
+      for (int k = 0; k <= DEG; ++k) {
+        const int n = PM.m[a][k];
+        const T lp = L1[(1 * D + a) * N + n], lm = L1[(0 * D + a) * N + n];
+        const int mt = n / 16, kown = (n % 16) / 4, e = n % 4;  // FP32 accumulator layout: row 4 k + e
+        if (XR && mt == 1) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) RX[v][n - 16] += lp * dl[v] + lm * dr[v];
+        } else if (kq == kown) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) R[v][mt][e] += lp * dl[v] + lm * dr[v];
+        }
+      }
+    }
   }
   if (AMR && live) {
     constexpr int NSUB = 1 + (1 << (D - 1)), NQ = 1 << (D - 1);
@@ -918,14 +1021,15 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
 }
 
 template <typename T, int D, int DEG, int NW, bool PF, bool AMR>
-__global__ void __launch_bounds__(64 * NW)
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(cell_waves_per_eu<T, AMR>())))
     k_cell_mfma(const T* w, const T* w0, T* out, const T* __restrict__ ff, const T* __restrict__ FV,
                 const T* __restrict__ FG, const T* __restrict__ FL, const T* __restrict__ GX,
-                const T* __restrict__ LX, const T* __restrict__ LFS, const T* __restrict__ Minv, Grid g,
-                const Scal* __restrict__ sc, double gamma, double a0, double b0, int mode) {
+                const T* __restrict__ LX, const T* __restrict__ LFS, const T* __restrict__ L1,
+                const T* __restrict__ Minv, Grid g, const Scal* __restrict__ sc, double gamma, double a0, double b0,
+                int mode) {
   const int64_t c0 = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * NW + (threadIdx.x >> 6)) * 16;
   if (c0 >= g.C) return;  // whole wave; the kernel has no barrier
-  cell_tile_mfma<T, D, DEG, PF, AMR>(c0, threadIdx.x & 63, w, w0, out, ff, FV, FG, FL, GX, LX, LFS, Minv, g, sc,
+  cell_tile_mfma<T, D, DEG, PF, AMR>(c0, threadIdx.x & 63, w, w0, out, ff, FV, FG, FL, GX, LX, LFS, L1, Minv, g, sc,
                                      gamma, a0, b0, mode);
 }
 
@@ -936,8 +1040,9 @@ template <typename T, int D, int DEG, int NW, bool AMR>
 __global__ void __launch_bounds__(64 * NW)
     k_cell_mfma_p(const T* w, const T* w0, T* out, const T* __restrict__ ff, const T* __restrict__ FV,
                   const T* __restrict__ FG, const T* __restrict__ FL, const T* __restrict__ GX,
-                  const T* __restrict__ LX, const T* __restrict__ LFS, const T* __restrict__ Minv, Grid g,
-                  const Scal* __restrict__ sc, double gamma, double a0, double b0, int mode) {
+                  const T* __restrict__ LX, const T* __restrict__ LFS, const T* __restrict__ L1,
+                  const T* __restrict__ Minv, Grid g, const Scal* __restrict__ sc, double gamma, double a0,
+                  double b0, int mode) {
   using S = MfmaShape<D, DEG>;
   __shared__ T sV[S::SZ_V], sG[S::SZ_G], sL[S::SZ_LM], sGX[S::SZ_GX], sLX[S::SZ_LXM];
   for (int i = threadIdx.x; i < S::SZ_V; i += 64 * NW) sV[i] = FV[i];
@@ -951,8 +1056,8 @@ __global__ void __launch_bounds__(64 * NW)
   const int64_t t0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * per;
   const int64_t t1 = t0 + per < ntiles ? t0 + per : ntiles;
   for (int64_t t = t0 + (threadIdx.x >> 6); t < t1; t += NW)
-    cell_tile_mfma<T, D, DEG, true, AMR>(t * 16, threadIdx.x & 63, w, w0, out, ff, sV, sG, sL, sGX, sLX, LFS, Minv,
-                                         g, sc, gamma, a0, b0, mode);
+    cell_tile_mfma<T, D, DEG, true, AMR>(t * 16, threadIdx.x & 63, w, w0, out, ff, sV, sG, sL, sGX, sLX, LFS, L1,
+                                         Minv, g, sc, gamma, a0, b0, mode);
 }
 
 // ---------------------------------------------------------------------------
@@ -1365,6 +1470,7 @@ __device__ __forceinline__ void store_face_moments(FX&& fx, const T* __restrict_
   using M = Mfma<T>;
   using V4 = typename M::v4;
   constexpr int NV = 9, FM = C::FM;
+  constexpr int FMS = MfmaShape<D, DEG>::template fms<T>();
   T mt[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) mt[s] = FT[S::SZ + (A * 4 + s) * 64 + lane];
@@ -1378,11 +1484,53 @@ __device__ __forceinline__ void store_face_moments(FX&& fx, const T* __restrict_
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int m = M::row(kq, e);
-        if (m < FM) ff[((int64_t)(A * NV + v) * FM + m) * ld + F] = acc[e];
+        if (m < FM) ff[((int64_t)(A * NV + v) * FMS + m) * ld + F] = acc[e];
       }
     }
   }
 }
+
+// FP32 deviation form of the face kernels (see cell_tile_mfma): the traces
+// are FP32 products of the modes above the mean, the Riemann problem is
+// solved in FP64 on mean + deviation, and the stored point fluxes are
+// F* - c with c the FP32 flux of the left cell's mean (written to the extra
+// row of the moment buffer for both cells to use).
+template <int NV>
+struct FaceDev {
+  double ubL[NV], ubR[NV], cL[NV];
+  template <int A, int NVS, int FMS, int FM>
+  __device__ __forceinline__ void init(const float* __restrict__ w, int N, int64_t ld, int64_t FL, int64_t FR,
+                                       double gamma, double ch, float* __restrict__ ff, int64_t F, bool store) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      ubL[v] = (double)w[(int64_t)(v * N) * ld + FL];
+      ubR[v] = (double)w[(int64_t)(v * N) * ld + FR];
+    }
+    double fl[NV], fr[NV];
+    mhd_flux<double, NV>(ubL, A, gamma, ch * ch, fl);
+    mhd_flux<double, NV>(ubR, A, gamma, ch * ch, fr);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      cL[v] = (double)(float)fl[v];
+      if (store) {
+        ff[((int64_t)(A * NVS + v) * FMS + FM) * ld + F] = (float)(cL[v] - fl[v]);
+        ff[((int64_t)(A * NVS + v) * FMS + FM + 1) * ld + F] = (float)(cL[v] - fr[v]);
+      }
+    }
+  }
+  template <int A>
+  __device__ __forceinline__ void flux(const float* dL, const float* dR, double gamma, double ch, float* Fx) const {
+    double uL[NV], uR[NV], F[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      uL[v] = ubL[v] + (double)dL[v];
+      uR[v] = ubR[v] + (double)dR[v];
+    }
+    (void)face_flux_a<double, NV, A>(uL, uR, gamma, ch, F);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fx[v] = (float)(F[v] - cL[v]);
+  }
+};
 
 template <typename T, int D, int DEG, int NW>
 __global__ void __launch_bounds__(64 * NW) k_face_mfma(const T* __restrict__ w, T* __restrict__ ff,
@@ -1412,6 +1560,8 @@ __global__ void __launch_bounds__(64 * NW) k_face_mfma(const T* __restrict__ w, 
     UL[v] = v4{0, 0, 0, 0};
     UR[v] = v4{0, 0, 0, 0};
   }
+  constexpr bool DEV = sizeof(T) == 4;
+  constexpr int FMS = MfmaShape<D, DEG>::template fms<T>();
   // the left cell's operands of every k-step are loaded together, then the
   // right cell's are loaded while the left traces are multiplied
   {
@@ -1421,7 +1571,7 @@ __global__ void __launch_bounds__(64 * NW) k_face_mfma(const T* __restrict__ w, 
       const int n = 4 * s + kq;
       tk[s] = FT[((a * 2 + 1) * S::NKS + s) * 64 + lane];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) bk[s][v] = n < N ? w[(int64_t)(v * N + n) * ld + FL] : T(0);
+      for (int v = 0; v < NV; ++v) bk[s][v] = (n < N && !(DEV && n == 0)) ? w[(int64_t)(v * N + n) * ld + FL] : T(0);
     }
 #pragma unroll
     for (int s = 0; s < S::NKS; ++s)
@@ -1432,7 +1582,7 @@ __global__ void __launch_bounds__(64 * NW) k_face_mfma(const T* __restrict__ w, 
       const int n = 4 * s + kq;
       tk[s] = FT[((a * 2 + 0) * S::NKS + s) * 64 + lane];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) bk[s][v] = n < N ? w[(int64_t)(v * N + n) * ld + FR] : T(0);
+      for (int v = 0; v < NV; ++v) bk[s][v] = (n < N && !(DEV && n == 0)) ? w[(int64_t)(v * N + n) * ld + FR] : T(0);
     }
 #pragma unroll
     for (int s = 0; s < S::NKS; ++s)
@@ -1446,6 +1596,10 @@ __global__ void __launch_bounds__(64 * NW) k_face_mfma(const T* __restrict__ w, 
   // zero fluxes).
   auto riemann = [&](auto axis) {
     constexpr int A = decltype(axis)::value;
+    FaceDev<NV> dv;
+    if constexpr (DEV)
+      dv.template init<A, NV, FMS, C::FM>((const float*)w, N, ld, FL, FR, gamma, sc->ch, (float*)ff, F,
+                                          live && kq == 0);
     v4 FX[NV];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -1458,7 +1612,8 @@ __global__ void __launch_bounds__(64 * NW) k_face_mfma(const T* __restrict__ w, 
           uL[v] = UL[v][j];
           uR[v] = UR[v][j];
         }
-        (void)face_flux_a<T, NV, A>(uL, uR, gamma, ch, Fx);
+        if constexpr (DEV) dv.template flux<A>((const float*)uL, (const float*)uR, gamma, sc->ch, (float*)Fx);
+        else (void)face_flux_a<T, NV, A>(uL, uR, gamma, ch, Fx);
       } else {
 #pragma unroll
         for (int v = 0; v < NV; ++v) Fx[v] = T(0);
@@ -1499,6 +1654,8 @@ k_face_mfma_lr(const T* __restrict__ w, T* __restrict__ ff, const T* __restrict_
   const int64_t FL = live ? F : f0;
   const int64_t FR = nbr(FL, a, +1, g);
   const int64_t ld = g.ld;
+  constexpr bool DEV = sizeof(T) == 4;
+  constexpr int FMS = MfmaShape<D, DEG>::template fms<T>();
   __shared__ T sU[NW][NV * 4 * 64];
   T* const su = sU[threadIdx.x >> 6];
   v4 UL[NV], UR[NV];
@@ -1515,8 +1672,8 @@ k_face_mfma_lr(const T* __restrict__ w, T* __restrict__ ff, const T* __restrict_
     T bl[NV], br[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      bl[v] = n < N ? w[(int64_t)(v * N + n) * ld + FL] : T(0);
-      br[v] = n < N ? w[(int64_t)(v * N + n) * ld + FR] : T(0);
+      bl[v] = (n < N && !(DEV && n == 0)) ? w[(int64_t)(v * N + n) * ld + FL] : T(0);
+      br[v] = (n < N && !(DEV && n == 0)) ? w[(int64_t)(v * N + n) * ld + FR] : T(0);
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -1532,6 +1689,10 @@ k_face_mfma_lr(const T* __restrict__ w, T* __restrict__ ff, const T* __restrict_
   const T ch = (T)sc->ch;
   auto riemann = [&](auto axis) __attribute__((always_inline)) {
     constexpr int A = decltype(axis)::value;
+    FaceDev<NV> dv;
+    if constexpr (DEV)
+      dv.template init<A, NV, FMS, C::FM>((const float*)w, N, ld, FL, FR, gamma, sc->ch, (float*)ff, F,
+                                          live && kq == 0);
     // the point fluxes replace the right traces in LDS, slot by slot
 #pragma unroll 1
     for (int j = 0; j < 4; ++j) {
@@ -1544,7 +1705,8 @@ k_face_mfma_lr(const T* __restrict__ w, T* __restrict__ ff, const T* __restrict_
           uL[v] = j == 0 ? UL[v][0] : j == 1 ? UL[v][1] : j == 2 ? UL[v][2] : UL[v][3];
           uR[v] = su[(v * 4 + j) * 64 + lane];
         }
-        (void)face_flux_a<T, NV, A>(uL, uR, gamma, ch, Fx);
+        if constexpr (DEV) dv.template flux<A>((const float*)uL, (const float*)uR, gamma, sc->ch, (float*)Fx);
+        else (void)face_flux_a<T, NV, A>(uL, uR, gamma, ch, Fx);
       } else {
 #pragma unroll
         for (int v = 0; v < NV; ++v) Fx[v] = T(0);
@@ -1972,6 +2134,7 @@ struct LauncherImpl : Launcher {
   double *vpw = nullptr, *pvpw = nullptr, *minv64 = nullptr;
   const T *mfv = nullptr, *mfg = nullptr, *mfl = nullptr;  // fragment-order tables of the matrix-core cell kernel
   const T *mgx = nullptr, *mlx = nullptr;                   // and its vector-ALU rows (modes 16..19)
+  const T* ml1 = nullptr;                                   // lift of a constant over each -a face
   // (GLM: mfl and mlx lift face moments; Powell: face points)
   const T *mpv = nullptr, *mpg = nullptr, *mpl = nullptr;  // and its LDF (Powell) tables
   const T* mft = nullptr;                                   // and of the matrix-core face kernel
@@ -2030,6 +2193,27 @@ struct LauncherImpl : Launcher {
       if ((e = up<T>(flm, mfl)) != hipSuccess) return e;
       if ((e = up<T>(gx, mgx)) != hipSuccess) return e;
       if ((e = up<T>(lxm, mlx)) != hipSuccess) return e;
+      // lift of a constant over the -a (side 0) and +a (side 1) face, signed
+      // as the lift tables: [side][a][n] = -+ sum_r w_r phi_n (deviation form)
+      std::vector<double> l1((size_t)2 * D * C::N, 0.0);
+      for (int side = 0; side < 2; ++side)
+        for (int a = 0; a < D; ++a)
+          for (int n = 0; n < C::N; ++n)
+            for (int r = 0; r < C::FP; ++r)
+              l1[((size_t)side * D + a) * C::N + n] +=
+                  (side ? -1.0 : 1.0) * t.LF[((a * 2 + side) * C::FP + r) * C::N + n];
+      if ((e = up<T>(l1, ml1)) != hipSuccess) return e;
+      for (int a = 0; a < D; ++a)  // the modes the lift of a constant reaches are the powers xi_a^k
+        for (int n = 0; n < C::N; ++n) {
+          bool pw = false;
+          for (int k = 0; k <= DEG; ++k) pw = pw || MfmaShape<D, DEG>::power_mode(a, k) == n;
+          for (int b = 0; b < 3; ++b) {
+            const int want = b == a ? -1 : 0;
+            if (pw && want == 0 && t.expo[3 * n + b] != 0) return hipErrorInvalidValue;
+          }
+          if (!pw && (std::fabs(l1[(size_t)a * C::N + n]) > 1e-14 || std::fabs(l1[((size_t)D + a) * C::N + n]) > 1e-14))
+            return hipErrorInvalidValue;
+        }
       std::vector<double> ft, fta;
       mfma_face_tables<T, D, DEG>(t, qb, ft);
       if ((e = up<T>(ft, mft)) != hipSuccess) return e;
@@ -2075,7 +2259,10 @@ struct LauncherImpl : Launcher {
     bufs.clear();
   }
   size_t face_buffer_elems(const Grid& g) const override {
-    return g.level ? (size_t)C::NV * C::FP * g.ldf : (size_t)D * C::NV * C::FP * g.ld;
+    // uniform grids: point fluxes (FP rows per axis and variable) or face
+    // moments (FM rows, FM + 1 in the FP32 deviation form)
+    constexpr int rows = C::FP > C::FM + 2 ? C::FP : C::FM + 2;
+    return g.level ? (size_t)C::NV * C::FP * g.ldf : (size_t)D * C::NV * rows * g.ld;
   }
   size_t jump_buffer_elems(const Grid& g) const override {
     return DIVB == POWELL ? (size_t)D * 2 * C::FP * g.ld : 0;
@@ -2142,11 +2329,11 @@ struct LauncherImpl : Launcher {
       const unsigned grid = (unsigned)(groups < nb ? groups : nb);
       if (g.level)
         k_cell_mfma_p<T, D, DEG, NW, true><<<grid, 64 * NW, 0, s>>>((const T*)w, (const T*)w0, (T*)out,
-                                                                    (const T*)ff, mfv, mfg, mfl, mgx, mlx, tb.LFS, tb.Minv, g,
+                                                                    (const T*)ff, mfv, mfg, mfl, mgx, mlx, tb.LFS, ml1, tb.Minv, g,
                                                                     sc, sp.gamma, a0, b0, mode);
       else
         k_cell_mfma_p<T, D, DEG, NW, false><<<grid, 64 * NW, 0, s>>>((const T*)w, (const T*)w0, (T*)out,
-                                                                     (const T*)ff, mfv, mfg, mfl, mgx, mlx, tb.LFS, tb.Minv, g,
+                                                                     (const T*)ff, mfv, mfg, mfl, mgx, mlx, tb.LFS, ml1, tb.Minv, g,
                                                                      sc, sp.gamma, a0, b0, mode);
       return true;
     }
@@ -2160,11 +2347,11 @@ struct LauncherImpl : Launcher {
       const unsigned grid = (unsigned)((tiles + NW - 1) / NW);
       if (g.level)
         k_cell_mfma<T, D, DEG, NW, PF, true><<<grid, 64 * NW, 0, s>>>((const T*)w, (const T*)w0, (T*)out,
-                                                                      (const T*)ff, mfv, mfg, mfl, mgx, mlx, tb.LFS, tb.Minv, g,
+                                                                      (const T*)ff, mfv, mfg, mfl, mgx, mlx, tb.LFS, ml1, tb.Minv, g,
                                                                       sc, sp.gamma, a0, b0, mode);
       else
         k_cell_mfma<T, D, DEG, NW, PF, false><<<grid, 64 * NW, 0, s>>>((const T*)w, (const T*)w0, (T*)out,
-                                                                       (const T*)ff, mfv, mfg, mfl, mgx, mlx, tb.LFS, tb.Minv, g,
+                                                                       (const T*)ff, mfv, mfg, mfl, mgx, mlx, tb.LFS, ml1, tb.Minv, g,
                                                                        sc, sp.gamma, a0, b0, mode);
       return true;
     }

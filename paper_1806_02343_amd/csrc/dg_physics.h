@@ -101,6 +101,85 @@ __device__ __forceinline__ void mhd_flux(const T* u, int a, double gamma, T ch2,
   }
 }
 
+// Flux deviation f_a(ubar + du) - f_a(ubar) of a state given as a cell-mean
+// reference plus a deviation, written as an exact rearrangement of
+// eq. mhd-flux into products that carry a deviation factor (with
+// v = vbar + dv: m_b v_a - mbar_b vbar_a = mbar_b dv_a + dm_b v_a, and so on),
+// so that FP32 rounding stays relative to the deviation instead of to the
+// background flux.  The thermal-pressure deviation is recovered in FP64:
+//   dp = (gamma-1) (dE - (dm.v + mbar.dv)/2 - (Bbar.dB + |dB|^2/2)).
+// vbar may carry rounding: dv = (dm - vbar drho)/rho keeps the rearrangement
+// exact up to terms proportional to the deviation.
+struct MeanRef {
+  float u[9];  // conserved mean state (GLM: 9 components)
+  float v[3];  // mean velocity
+  float ept;   // Ebar + pbar + |Bbar|^2 / 2
+  float vb;    // vbar . Bbar
+  __device__ __forceinline__ void init(const float* ub, double gamma) {
+    double ud[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      u[k] = ub[k];
+      ud[k] = (double)ub[k];
+    }
+    const double ir = 1.0 / ud[0];
+    double vd[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      vd[b] = ud[1 + b] * ir;
+      v[b] = (float)vd[b];
+    }
+    const double b2 = ud[5] * ud[5] + ud[6] * ud[6] + ud[7] * ud[7];
+    ept = (float)(ud[4] + pressure64_ir(ud, gamma, ir) + 0.5 * b2);
+    vb = (float)(vd[0] * ud[5] + vd[1] * ud[6] + vd[2] * ud[7]);
+  }
+};
+
+// Per-point quantities shared by the D axes.
+struct DevPoint {
+  float dv[3], v[3], B[3];
+  float dpt;   // deviation of p + |B|^2/2
+  float dEpt;  // deviation of E + p + |B|^2/2
+  float dvB;   // deviation of v . B
+};
+
+__device__ __forceinline__ void dev_point(const MeanRef& m, const float* du, double gamma, DevPoint& q) {
+  const float ir = recip(m.u[0] + du[0]);
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    q.dv[b] = (du[1 + b] - m.v[b] * du[0]) * ir;
+    q.v[b] = m.v[b] + q.dv[b];
+    q.B[b] = m.u[5 + b] + du[5 + b];
+  }
+  double dke = 0.0, dme = 0.0;
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    dke += (double)du[1 + b] * (double)q.v[b] + (double)m.u[1 + b] * (double)q.dv[b];
+    dme += (double)m.u[5 + b] * (double)du[5 + b] + 0.5 * (double)du[5 + b] * (double)du[5 + b];
+  }
+  const double dp = (gamma - 1.0) * ((double)du[4] - 0.5 * dke - dme);
+  q.dpt = (float)(dp + dme);
+  q.dEpt = du[4] + q.dpt;
+  q.dvB = q.dv[0] * m.u[5] + q.dv[1] * m.u[6] + q.dv[2] * m.u[7] + q.v[0] * du[5] + q.v[1] * du[6] + q.v[2] * du[7];
+}
+
+template <int NV, int A>
+__device__ __forceinline__ void mhd_dflux(const MeanRef& m, const float* du, const DevPoint& q, float ch2, float* f) {
+  const float va = q.v[A], dva = q.dv[A], Ba = q.B[A], dBa = du[5 + A];
+  f[0] = du[1 + A];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) f[1 + b] = (m.u[1 + b] * dva + du[1 + b] * va) - (du[5 + b] * Ba + m.u[5 + b] * dBa);
+  f[1 + A] += q.dpt;
+  f[4] = (q.dEpt * va + m.ept * dva) - (q.dvB * Ba + m.vb * dBa);
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+    f[5 + b] = b == A ? 0.0f : (du[5 + b] * va + m.u[5 + b] * dva) - (q.dv[b] * Ba + m.v[b] * dBa);
+  if (NV == 9) {
+    f[5 + A] = du[8];
+    f[8] = ch2 * dBa;
+  }
+}
+
 // sum_a (|v_a| + c), c = sqrt(gamma p / rho + B^2 / rho), over the first D
 // axes; max(p, 0) in the sound speed and no contribution where rho <= 0 (a
 // state that the positivity limiter has not seen yet).
