@@ -75,7 +75,10 @@ enum { DG_LIM_TVB = 1, DG_LIM_CHAR = 2, DG_LIM_POS = 4, DG_LIM_LEARNED = 8 };
 enum { DG_MESH_UNIFORM = 0, DG_MESH_OCTREE = 1 };
 
 /* Scheme parameters (Sec. 3.6, 4.1, 4.2, 4.3; defaults of the paper in
- * brackets).  rk_stages must be 3 (SSP-RK3).  cfl_glm is C' of Sec. 4.1.5
+ * brackets).  rk_stages selects the SSP Runge-Kutta scheme of Sec. 3.6 (order
+ * 1 to 4): 1 forward Euler, 2 SSP-RK2, 3 SSP-RK3 (Shu-Osher), 5 the
+ * five-stage fourth-order SSP scheme of Spiteri & Ruuth (in the survey the
+ * paper cites, Gottlieb 2005); other values DG_EUNSUPPORTED.  cfl_glm is C' of Sec. 4.1.5
  * (0 selects min(2 cfl, 0.9)); glm_cr is c_r = c_p^2 / c_h [0.18];
  * glm_ch_fixed > 0 fixes c_h (required on octree meshes).  tvb_Mtilde [5],
  * tvb_beta [2], tvb_eps [1e-8]; eps_rho = eps_p [1e-12]; powell_eta [0.2].
@@ -165,7 +168,7 @@ int dg_rhs_noalloc(dg_handle h, const void* w, void* dwdt, double ch, double kap
  * returned (state valid) if the c_h check of the call failed. */
 int dg_limit(dg_handle h, void* w, dg_limit_stats* stats /*[host] or NULL*/);
 
-/* Advance w by nsteps SSP-RK3 steps (Sec. 3.6); dt, c_h and kappa are
+/* Advance w by nsteps steps of the selected SSP-RK scheme (Sec. 3.6); dt, c_h and kappa are
  * computed on the device from the state at the start of each step and the
  * selected limiters run after every stage (Sec. 4.3: before any state is
  * evaluated at quadrature points again).  Limiting the initial state is the

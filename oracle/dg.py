@@ -41,6 +41,35 @@ from .quadrature import gauss_legendre, tensor_rule
 GLM, POWELL = 0, 1
 
 
+def ssp_rk(stages):
+    """Shu-Osher coefficients (alpha, beta) of the SSP Runge-Kutta schemes of
+    selectable order 1-4 (Sec. 3.6, citing the Gottlieb 2005 survey):
+    u_i = sum_{j<i} alpha[i-1][j] u_j + beta[i-1][j] dt L(u_j), u_0 = u^n,
+    u^{n+1} = u_s.  stages 1, 2, 3: the s-stage order-s schemes (forward Euler,
+    SSP-RK2, Shu-Osher SSP-RK3); 5: the five-stage fourth-order scheme of
+    Spiteri & Ruuth as listed in that survey (15 digits)."""
+    if stages == 1:
+        return [[1.0]], [[1.0]]
+    if stages == 2:
+        return [[1.0], [0.5, 0.5]], [[1.0], [0.0, 0.5]]
+    if stages == 3:
+        return ([[1.0], [0.75, 0.25], [1.0 / 3.0, 0.0, 2.0 / 3.0]],
+                [[1.0], [0.0, 0.25], [0.0, 0.0, 2.0 / 3.0]])
+    if stages == 5:
+        alpha = [[1.0],
+                 [0.444370493651235, 0.555629506348765],
+                 [0.620101851488403, 0.0, 0.379898148511597],
+                 [0.178079954393132, 0.0, 0.0, 0.821920045606868],
+                 [0.0, 0.0, 0.517231671970585, 0.096059710526147, 0.386708617503269]]
+        beta = [[0.391752226571890],
+                [0.0, 0.368410593050371],
+                [0.0, 0.0, 0.251891774271694],
+                [0.0, 0.0, 0.0, 0.544974750228521],
+                [0.0, 0.0, 0.0, 0.063692468666290, 0.226007483236906]]
+        return alpha, beta
+    raise ValueError("stages must be 1, 2, 3 or 5")
+
+
 class Mesh:
     """Cells (centres, sizes) and faces of a periodic box."""
 
@@ -330,15 +359,19 @@ class DG:
     # ------------------------------------------------------------------
     # SSP-RK3
 
-    def step(self, w, limiter=None):
-        """One SSP-RK3 step (Shu-Osher form).  limiter(w, ch) -> w is applied
+    def step(self, w, limiter=None, rk=3):
+        """One step of the SSP Runge-Kutta scheme with `rk` stages (ssp_rk; the
+        default is SSP-RK3), in Shu-Osher form.  limiter(w, ch) -> w is applied
         after every stage with the step's c_h.  Returns (w_new, dt, ch, kappa)."""
         dt, ch, kappa = self.timestep(w)
         lim = (lambda x: limiter(x, ch)) if limiter is not None else (lambda x: x)
-        u1 = lim(w + dt * self.rhs(w, ch, kappa))
-        u2 = lim(0.75 * w + 0.25 * (u1 + dt * self.rhs(u1, ch, kappa)))
-        u3 = lim(w / 3.0 + 2.0 / 3.0 * (u2 + dt * self.rhs(u2, ch, kappa)))
-        return u3, dt, ch, kappa
+        alpha, beta = ssp_rk(rk)
+        us, dls = [w], []
+        for i in range(len(alpha)):
+            dls.append(dt * self.rhs(us[-1], ch, kappa))
+            u = sum(alpha[i][j] * us[j] + beta[i][j] * dls[j] for j in range(i + 1))
+            us.append(lim(u))
+        return us[-1], dt, ch, kappa
 
     # ------------------------------------------------------------------
     # initial-condition projection (d+3 points per dimension)

@@ -108,14 +108,15 @@ class DG:
 
     def __init__(self, dim, degree, n, box=1.0, divb=DG_GLM, precision=DG_FP64, limiter=0, gamma=5.0 / 3.0,
                  cfl=0.3, cfl_glm=0.0, glm_cr=0.18, glm_ch_fixed=0.0, tvb_Mtilde=5.0, tvb_beta=2.0, tvb_eps=1e-8,
-                 eps_rho=1e-12, eps_p=1e-12, powell_eta=0.2, mlp_lo=0.0, mlp_hi=0.0, stream=None, octree=None):
+                 eps_rho=1e-12, eps_p=1e-12, powell_eta=0.2, mlp_lo=0.0, mlp_hi=0.0, stream=None, octree=None,
+                 rk_stages=3):
         """octree: optional (level[int8, C], ijk[int32, C x 3]) leaves on the level
         grids of the base grid n (kind DG_MESH_OCTREE)."""
         import torch
         self.torch = torch
         self.lib = load_library()
         self.dim, self.degree, self.divb, self.precision = dim, degree, divb, precision
-        p = dg_params(dim, degree, divb, precision, 3, limiter, gamma, cfl, cfl_glm, glm_cr, glm_ch_fixed,
+        p = dg_params(dim, degree, divb, precision, rk_stages, limiter, gamma, cfl, cfl_glm, glm_cr, glm_ch_fixed,
                       tvb_Mtilde, tvb_beta, tvb_eps, eps_rho, eps_p, powell_eta, mlp_lo, mlp_hi)
         nn = list(n) if hasattr(n, "__len__") else [n] * dim
         bb = list(box) if hasattr(box, "__len__") else [box] * dim

@@ -32,6 +32,8 @@ struct dg_handle_s {
   void* ff = nullptr;     // face fluxes
   void* jp = nullptr;     // Powell normal-field jumps
   void* S1 = nullptr;     // stage state
+  void* S2 = nullptr;     // SSP-RK(5,4): two more stage states
+  void* S3 = nullptr;
   void* jsum = nullptr;   // Powell per-face jump integrals
   void* lscr = nullptr;   // limiter scratch
   Scal* sc = nullptr;     // device scalars
@@ -265,7 +267,8 @@ int dg_init(const dg_params* p, const dg_mesh* m, void* hip_stream, dg_handle* o
   if (p->divb != DG_GLM && p->divb != DG_POWELL) return fail(nullptr, DG_EINVAL, "unknown divb");
   if (p->divb == DG_POWELL && p->dim != 3) return fail(nullptr, DG_EUNSUPPORTED, "Powell/LDF is built for 3-D");
   if (p->precision != DG_FP64 && p->precision != DG_FP32) return fail(nullptr, DG_EINVAL, "unknown precision");
-  if (p->rk_stages != 3) return fail(nullptr, DG_EUNSUPPORTED, "only SSP-RK3 (rk_stages = 3)");
+  if (p->rk_stages != 1 && p->rk_stages != 2 && p->rk_stages != 3 && p->rk_stages != 5)
+    return fail(nullptr, DG_EUNSUPPORTED, "rk_stages must be 1, 2, 3 (SSP-RK of that order) or 5 (SSP-RK(5,4))");
   if (!(p->gamma > 1.0) || !(p->cfl > 0.0) || !(p->cfl < 1.0)) return fail(nullptr, DG_EINVAL, "gamma/cfl");
   if (m->kind != DG_MESH_UNIFORM && m->kind != DG_MESH_OCTREE) return fail(nullptr, DG_EINVAL, "unknown mesh kind");
   if (m->kind == DG_MESH_OCTREE) {
@@ -352,6 +355,12 @@ int dg_init(const dg_params* p, const dg_mesh* m, void* hip_stream, dg_handle* o
   }
   if ((e = hipMalloc(&h->S1, nm * g.ld * h->elem)) != hipSuccess) return cleanup(DG_ENOMEM, "stage buffer");
   if ((e = hipMemset(h->S1, 0, nm * g.ld * h->elem)) != hipSuccess) return cleanup(DG_EHIP, "stage buffer clear");
+  if (p->rk_stages == 5) {
+    for (void** b : {&h->S2, &h->S3}) {
+      if ((e = hipMalloc(b, nm * g.ld * h->elem)) != hipSuccess) return cleanup(DG_ENOMEM, "stage buffer");
+      if ((e = hipMemset(*b, 0, nm * g.ld * h->elem)) != hipSuccess) return cleanup(DG_EHIP, "stage buffer clear");
+    }
+  }
   if (size_t ls = h->L->limit_scratch_bytes(g)) {
     if ((e = hipMalloc(&h->lscr, ls)) != hipSuccess) return cleanup(DG_ENOMEM, "limiter scratch");
     if ((e = hipMemset(h->lscr, 0, ls)) != hipSuccess) return cleanup(DG_EHIP, "limiter scratch clear");
@@ -427,7 +436,7 @@ int dg_rhs(dg_handle h, const void* w, void* dwdt, double ch, double kappa) {
   if (h->p.divb == DG_GLM && !(ch > 0.0)) return fail(h, DG_EINVAL, "GLM needs c_h > 0");
   launch_set_scalars(h->sc, ch, kappa, 0.0, h->stream);
   h->L->face(w, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
-  h->L->cell(w, w, dwdt, h->ff, h->jp, h->g, h->sc, h->sp, 0.0, 1.0, 0, h->stream);
+  h->L->cell(w, w, dwdt, h->ff, h->jp, h->g, h->sc, h->sp, 0.0, 1.0, 1.0, 0, h->stream);
   return check_launch(h, "rhs");
 }
 
@@ -455,7 +464,7 @@ int dg_rhs_noalloc(dg_handle h, const void* w, void* dwdt, double ch, double kap
   void* jp = h->L->jump_buffer_elems(h->g) ? (void*)(base + off_jp) : nullptr;
   launch_set_scalars(sc, ch, kappa, 0.0, h->stream);
   h->L->face(w, ff, jp, h->g, sc, h->sp, h->stream);
-  h->L->cell(w, w, dwdt, ff, jp, h->g, sc, h->sp, 0.0, 1.0, 0, h->stream);
+  h->L->cell(w, w, dwdt, ff, jp, h->g, sc, h->sp, 0.0, 1.0, 1.0, 0, h->stream);
   return check_launch(h, "rhs_noalloc");
 }
 
@@ -515,22 +524,61 @@ static void step_sequence(dg_handle h, void* w, bool first) {
       (void)h->L->mlp_record(u, h->rec_X, h->rec_y, h->rec_counter, h->rec_cap, h->rec_qpos, h->rec_q, h->rec_seed,
                              h->g, h->sc, h->sp, h->stream);
   };
-  // stage 1: S1 = w + dt L(w)
-  h->L->face(w, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
-  h->L->cell(w, w, h->S1, h->ff, h->jp, h->g, h->sc, h->sp, 0.0, 1.0, 1, h->stream);
-  record(h->S1);
-  if (lim) h->L->limit(h->S1, h->lscr, h->g, h->sc, h->sp, h->stream);
-  // stage 2: S1 = 3/4 w + 1/4 (S1 + dt L(S1))
-  h->L->face(h->S1, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
-  h->L->cell(h->S1, w, h->S1, h->ff, h->jp, h->g, h->sc, h->sp, 0.75, 0.25, 1, h->stream);
-  record(h->S1);
-  if (lim) h->L->limit(h->S1, h->lscr, h->g, h->sc, h->sp, h->stream);
-  // stage 3: w = 1/3 w + 2/3 (S1 + dt L(S1))
-  h->L->face(h->S1, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
-  h->L->cell(h->S1, w, w, h->ff, h->jp, h->g, h->sc, h->sp, 1.0 / 3.0, 2.0 / 3.0, 1, h->stream);
-  record(w);
-  if (fused) launch_reset_next(h->sc, h->stream);
-  if (lim) h->L->limit(w, h->lscr, h->g, h->sc, h->sp, h->stream, fused);
+  // one Shu-Osher stage: out = a0 base + b0 (in + c0 dt L(in)), then the
+  // limiters (the last stage of the step also folds the next step's signal)
+  auto stage = [&](void* in, void* base, void* out, double a0, double b0, double c0, bool last) {
+    h->L->face(in, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
+    h->L->cell(in, base, out, h->ff, h->jp, h->g, h->sc, h->sp, a0, b0, c0, 1, h->stream);
+    record(out);
+    if (last && fused) launch_reset_next(h->sc, h->stream);
+    if (lim) h->L->limit(out, h->lscr, h->g, h->sc, h->sp, h->stream, last && fused);
+  };
+  switch (h->p.rk_stages) {
+    case 1:  // forward Euler: w = w + dt L(w)
+      stage(w, w, w, 0.0, 1.0, 1.0, true);
+      break;
+    case 2:  // SSP-RK2: S1 = w + dt L(w); w = w/2 + (S1 + dt L(S1))/2
+      stage(w, w, h->S1, 0.0, 1.0, 1.0, false);
+      stage(h->S1, w, w, 0.5, 0.5, 1.0, true);
+      break;
+    case 5: {
+      // SSP-RK(5,4) in Shu-Osher form (coefficients of the five-stage,
+      // fourth-order SSP scheme):
+      //   u1 = u0 + b10 dt L0;   u2 = a20 u0 + a21 u1 + b21 dt L1;
+      //   u3 = a30 u0 + a32 u2 + b32 dt L2;   u4 = a40 u0 + a43 u3 + b43 dt L3;
+      //   u5 = a52 u2 + a53 u3 + b53 dt L3 + a54 u4 + b54 dt L4.
+      // Buffers: u1 -> S1, u2 -> S2, u3 -> S1, u4 -> S3.  Before u4 is
+      // limited, Q = a52 u2 + a53 u3 + b53 dt L3 is formed into S2 with
+      // dt L3 = (u4 - a40 u0 - a43 u3) / b43; then u5 = Q + a54 (u4 + b54/a54 dt L4).
+      const double b10 = 0.391752226571890;
+      const double a20 = 0.444370493651235, a21 = 0.555629506348765, b21 = 0.368410593050371;
+      const double a30 = 0.620101851488403, a32 = 0.379898148511597, b32 = 0.251891774271694;
+      const double a40 = 0.178079954393132, a43 = 0.821920045606868, b43 = 0.544974750228521;
+      const double a52 = 0.517231671970585, a53 = 0.096059710526147, b53 = 0.063692468666290;
+      const double a54 = 0.386708617503269, b54 = 0.226007483236906;
+      stage(w, w, h->S1, 0.0, 1.0, b10, false);
+      stage(h->S1, w, h->S2, a20, a21, b21 / a21, false);
+      stage(h->S2, w, h->S1, a30, a32, b32 / a32, false);
+      // u4 unlimited, then Q, then the limiters on u4
+      h->L->face(h->S1, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
+      h->L->cell(h->S1, w, h->S3, h->ff, h->jp, h->g, h->sc, h->sp, a40, a43, b43 / a43, 1, h->stream);
+      {
+        const double k = b53 / b43;
+        const void* x[4] = {w, h->S1, h->S2, h->S3};
+        const double c[4] = {-k * a40, a53 - k * a43, a52, k};
+        launch_lincomb(h->S2, x, c, h->elem, h->L->nmodes(), h->g.ld, h->g.C, h->stream);
+      }
+      record(h->S3);
+      if (lim) h->L->limit(h->S3, h->lscr, h->g, h->sc, h->sp, h->stream);
+      stage(h->S3, h->S2, w, 1.0, a54, b54 / a54, true);
+      break;
+    }
+    default:  // SSP-RK3 (Shu-Osher)
+      stage(w, w, h->S1, 0.0, 1.0, 1.0, false);                     // S1 = w + dt L(w)
+      stage(h->S1, w, h->S1, 0.75, 0.25, 1.0, false);               // S1 = 3/4 w + 1/4 (S1 + dt L(S1))
+      stage(h->S1, w, w, 1.0 / 3.0, 2.0 / 3.0, 1.0, true);          // w = 1/3 w + 2/3 (S1 + dt L(S1))
+      break;
+  }
 }
 
 static void drop_graph(dg_handle h) {
@@ -614,8 +662,8 @@ int dg_time_kernel(dg_handle h, const void* w, int32_t which, int32_t reps, doub
       case 1:
         // the step's mix: one stage-1 form (w -> S1) per two stage-2/3 forms
         // (S1 and w read, S1 written in place); w is only read
-        if (i % 3 == 0) h->L->cell(w, w, h->S1, h->ff, h->jp, h->g, h->sc, h->sp, 0.0, 1.0, 1, h->stream);
-        else h->L->cell(h->S1, w, h->S1, h->ff, h->jp, h->g, h->sc, h->sp, 0.75, 0.25, 1, h->stream);
+        if (i % 3 == 0) h->L->cell(w, w, h->S1, h->ff, h->jp, h->g, h->sc, h->sp, 0.0, 1.0, 1.0, 1, h->stream);
+        else h->L->cell(h->S1, w, h->S1, h->ff, h->jp, h->g, h->sc, h->sp, 0.75, 0.25, 1.0, 1, h->stream);
         break;
       case 2: (void)dt_sequence(h, w); break;
       default: h->L->limit(h->S1, h->lscr, h->g, h->sc, h->sp, h->stream); break;
@@ -931,6 +979,8 @@ void dg_destroy(dg_handle h) {
   if (h->jp) (void)hipFree(h->jp);
   if (h->jsum) (void)hipFree(h->jsum);
   if (h->S1) (void)hipFree(h->S1);
+  if (h->S2) (void)hipFree(h->S2);
+  if (h->S3) (void)hipFree(h->S3);
   if (h->lscr) (void)hipFree(h->lscr);
   if (h->sc) (void)hipFree(h->sc);
   for (void* q : h->mesh_bufs) (void)hipFree(q);

@@ -72,9 +72,10 @@ struct Launcher {
   // face fluxes of state w into ff (and Powell jumps into jp)
   virtual void face(const void* w, void* ff, void* jp, const Grid& g, const Scal* sc, const SchemeParams& sp,
                     hipStream_t s) = 0;
-  // mode 0: out = M^-1 R;  mode 1: out = a0 w0 + b0 (w + dt M^-1 R)
+  // mode 0: out = M^-1 R;  mode 1: out = a0 w0 + b0 (w + cdt dt M^-1 R)
   virtual void cell(const void* w, const void* w0, void* out, const void* ff, const void* jp, const Grid& g,
-                    const Scal* sc, const SchemeParams& sp, double a0, double b0, int mode, hipStream_t s) = 0;
+                    const Scal* sc, const SchemeParams& sp, double a0, double b0, double cdt, int mode,
+                    hipStream_t s) = 0;
   // tile-shape variants of the cell kernel (autotuner)
   virtual int cell_variant_count() const = 0;
   virtual bool cell_variant_valid(int v) const = 0;
@@ -118,6 +119,11 @@ void launch_reset_next(Scal* sc, hipStream_t s);  // clears the next step's sign
 void launch_take_next(Scal* sc, hipStream_t s);   // moves them into this step's reduction
 void launch_finalize_dt(Scal* sc, const SchemeParams& sp, int D, int d, int divb, double hmin, hipStream_t s);
 void launch_set_scalars(Scal* sc, double ch, double kappa, double dt, hipStream_t s);
+// out = c[0] x[0] + c[1] x[1] + c[2] x[2] + c[3] x[3] (FP64 arithmetic) over
+// nmodes rows of ld elements, C columns used; x[k] may be null when c[k] = 0
+// and out may alias any x[k]
+void launch_lincomb(void* out, const void* const x[4], const double c[4], size_t elem, int64_t nmodes, int64_t ld,
+                    int64_t C, hipStream_t s);
 void launch_set_time(Scal* sc, double t, hipStream_t s);
 void launch_reset_stats(Scal* sc, hipStream_t s);  // limiter tallies, non-finite and c_h-violation counts
 // flags any non-finite weight of w (nmodes rows of ld, C columns used)

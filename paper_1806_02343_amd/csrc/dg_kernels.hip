@@ -253,7 +253,7 @@ __global__ void __launch_bounds__(NT)
            const T* __restrict__ tV, const T* __restrict__ tGW, const T* __restrict__ tLF,
            const T* __restrict__ tMinv, const T* __restrict__ tPV, const T* __restrict__ tPGW,
            const T* __restrict__ tPLF, const T* __restrict__ tPmean, const T* __restrict__ tLFS, Grid g,
-           const Scal* __restrict__ sc, double gamma, double a0, double b0, int mode) {
+           const Scal* __restrict__ sc, double gamma, double a0, double b0, double cdt, int mode) {
   using C = Cfg<D, DEG, DIVB>;
   using CT = CellTile<T, D, DEG, DIVB, TC, NT>;
   // tables as restrict-qualified arguments: wave-uniform reads become scalar loads
@@ -344,7 +344,7 @@ __global__ void __launch_bounds__(NT)
     }
   }
 
-  const double dt = sc->dt;
+  const double dt = sc->dt * cdt;  // the stage's multiple of the step
   const T kappa = (T)sc->kappa;
 #pragma unroll
   for (int k = 0; k < IPT; ++k) {
@@ -714,7 +714,7 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
                                                const T* __restrict__ ff, const T* FV, const T* FG, const T* FL,
                                                const T* GX, const T* LX, const T* __restrict__ LFS,
                                                const T* __restrict__ L1, const T* __restrict__ Minv, const Grid& g,
-                                               const Scal* __restrict__ sc, double gamma, double a0, double b0,
+                                               const Scal* __restrict__ sc, double gamma, double a0, double b0, double cdt,
                                                int mode) {
   using C = Cfg<D, DEG, GLM>;
   using S = MfmaShape<D, DEG>;
@@ -963,7 +963,7 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
       }
   }
   if (!live) return;
-  const double dt = sc->dt;
+  const double dt = sc->dt * cdt;  // the stage's multiple of the step
   const T kappa = (T)sc->kappa;
   const T two_h = T(2.0 / cell_h(g, K));
   // out may be w or w0 (stages 2 and 3 update in place), so the compiler
@@ -1025,12 +1025,12 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(ce
     k_cell_mfma(const T* w, const T* w0, T* out, const T* __restrict__ ff, const T* __restrict__ FV,
                 const T* __restrict__ FG, const T* __restrict__ FL, const T* __restrict__ GX,
                 const T* __restrict__ LX, const T* __restrict__ LFS, const T* __restrict__ L1,
-                const T* __restrict__ Minv, Grid g, const Scal* __restrict__ sc, double gamma, double a0, double b0,
+                const T* __restrict__ Minv, Grid g, const Scal* __restrict__ sc, double gamma, double a0, double b0, double cdt,
                 int mode) {
   const int64_t c0 = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * NW + (threadIdx.x >> 6)) * 16;
   if (c0 >= g.C) return;  // whole wave; the kernel has no barrier
   cell_tile_mfma<T, D, DEG, PF, AMR>(c0, threadIdx.x & 63, w, w0, out, ff, FV, FG, FL, GX, LX, LFS, L1, Minv, g, sc,
-                                     gamma, a0, b0, mode);
+                                     gamma, a0, b0, cdt, mode);
 }
 
 // Persistent form: one workgroup per resident slot copies the fragment
@@ -1042,7 +1042,7 @@ __global__ void __launch_bounds__(64 * NW)
                   const T* __restrict__ FG, const T* __restrict__ FL, const T* __restrict__ GX,
                   const T* __restrict__ LX, const T* __restrict__ LFS, const T* __restrict__ L1,
                   const T* __restrict__ Minv, Grid g, const Scal* __restrict__ sc, double gamma, double a0,
-                  double b0, int mode) {
+                  double b0, double cdt, int mode) {
   using S = MfmaShape<D, DEG>;
   __shared__ T sV[S::SZ_V], sG[S::SZ_G], sL[S::SZ_LM], sGX[S::SZ_GX], sLX[S::SZ_LXM];
   for (int i = threadIdx.x; i < S::SZ_V; i += 64 * NW) sV[i] = FV[i];
@@ -1057,7 +1057,7 @@ __global__ void __launch_bounds__(64 * NW)
   const int64_t t1 = t0 + per < ntiles ? t0 + per : ntiles;
   for (int64_t t = t0 + (threadIdx.x >> 6); t < t1; t += NW)
     cell_tile_mfma<T, D, DEG, true, AMR>(t * 16, threadIdx.x & 63, w, w0, out, ff, sV, sG, sL, sGX, sLX, LFS, L1,
-                                         Minv, g, sc, gamma, a0, b0, mode);
+                                         Minv, g, sc, gamma, a0, b0, cdt, mode);
 }
 
 // ---------------------------------------------------------------------------
@@ -1128,7 +1128,7 @@ __device__ __forceinline__ void cell_tile_mfma_powell(int64_t c0, int lane, cons
                                                       const T* FV, const T* FG, const T* FL, const T* PVt,
                                                       const T* PGt, const T* PLt, const T* __restrict__ Pmean,
                                                       const T* __restrict__ Minv, const Grid& g,
-                                                      const Scal* __restrict__ sc, double gamma, double a0, double b0,
+                                                      const Scal* __restrict__ sc, double gamma, double a0, double b0, double cdt,
                                                       int mode) {
   using C = Cfg<D, DEG, POWELL>;
   using S = MfmaShape<D, DEG>;
@@ -1256,7 +1256,7 @@ __device__ __forceinline__ void cell_tile_mfma_powell(int64_t c0, int lane, cons
     }
   }
   if (!live) return;
-  const double dt = sc->dt;
+  const double dt = sc->dt * cdt;  // the stage's multiple of the step
   const T two_h = T(2.0 / g.h);
   auto finish = [&](int m, T racc) {
     T dw = racc * two_h * Minv[m];
@@ -1307,11 +1307,11 @@ __global__ void __launch_bounds__(64 * NW)
                        const T* __restrict__ FV, const T* __restrict__ FG, const T* __restrict__ FL,
                        const T* __restrict__ PVt, const T* __restrict__ PGt, const T* __restrict__ PLt,
                        const T* __restrict__ Pmean, const T* __restrict__ Minv, Grid g, const Scal* __restrict__ sc,
-                       double gamma, double a0, double b0, int mode) {
+                       double gamma, double a0, double b0, double cdt, int mode) {
   const int64_t c0 = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * NW + (threadIdx.x >> 6)) * 16;
   if (c0 >= g.C) return;  // whole wave; no barrier in this kernel
   cell_tile_mfma_powell<T, D, DEG>(c0, threadIdx.x & 63, w, w0, out, ff, jp, FV, FG, FL, PVt, PGt, PLt, Pmean, Minv, g,
-                                   sc, gamma, a0, b0, mode);
+                                   sc, gamma, a0, b0, cdt, mode);
 }
 
 // Face kernel on octree meshes on the matrix cores: one wave per tile of 16
@@ -2116,6 +2116,37 @@ void launch_set_scalars(Scal* sc, double ch, double kappa, double dt, hipStream_
   k_set_scalars<<<1, 1, 0, s>>>(sc, ch, kappa, dt);
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) k_lincomb(T* out, const T* x0, const T* x1, const T* x2, const T* x3,
+                                                 double c0, double c1, double c2, double c3, int64_t nmodes,
+                                                 int64_t ld, int64_t C) {
+  const int64_t n = nmodes * C;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const int64_t m = i / C, at = m * ld + (i - m * C);
+    double v = 0.0;
+    if (x0) v += c0 * (double)x0[at];
+    if (x1) v += c1 * (double)x1[at];
+    if (x2) v += c2 * (double)x2[at];
+    if (x3) v += c3 * (double)x3[at];
+    out[at] = (T)v;
+  }
+}
+
+void launch_lincomb(void* out, const void* const x[4], const double c[4], size_t elem, int64_t nmodes, int64_t ld,
+                    int64_t C, hipStream_t s) {
+  const int64_t n = nmodes * C;
+  const int64_t blocks = (n + 255) / 256;
+  const unsigned grid = (unsigned)(blocks < 8192 ? (blocks > 0 ? blocks : 1) : 8192);
+  auto X = [&](int k) { return c[k] != 0.0 ? x[k] : nullptr; };
+  if (elem == 8)
+    k_lincomb<double><<<grid, 256, 0, s>>>((double*)out, (const double*)X(0), (const double*)X(1),
+                                           (const double*)X(2), (const double*)X(3), c[0], c[1], c[2], c[3], nmodes,
+                                           ld, C);
+  else
+    k_lincomb<float><<<grid, 256, 0, s>>>((float*)out, (const float*)X(0), (const float*)X(1), (const float*)X(2),
+                                          (const float*)X(3), c[0], c[1], c[2], c[3], nmodes, ld, C);
+}
+
 }  // namespace dgmhd
 
 #include "dg_limiters.inc"
@@ -2321,7 +2352,7 @@ struct LauncherImpl : Launcher {
   int pos_blocks = 0, maxsig_blocks = 0;
   template <int NW>
   bool launch_cell_mfma_p(const void* w, const void* w0, void* out, const void* ff, const Grid& g, const Scal* sc,
-                          const SchemeParams& sp, double a0, double b0, int mode, hipStream_t s) {
+                          const SchemeParams& sp, double a0, double b0, double cdt, int mode, hipStream_t s) {
     if constexpr (DIVB == GLM) {
       const int nb = g.level ? persist_blocks_amr[NW == 4 ? 0 : 1] : persist_blocks[NW == 4 ? 0 : 1];
       if (nb <= 0) return false;
@@ -2330,35 +2361,35 @@ struct LauncherImpl : Launcher {
       if (g.level)
         k_cell_mfma_p<T, D, DEG, NW, true><<<grid, 64 * NW, 0, s>>>((const T*)w, (const T*)w0, (T*)out,
                                                                     (const T*)ff, mfv, mfg, mfl, mgx, mlx, tb.LFS, ml1, tb.Minv, g,
-                                                                    sc, sp.gamma, a0, b0, mode);
+                                                                    sc, sp.gamma, a0, b0, cdt, mode);
       else
         k_cell_mfma_p<T, D, DEG, NW, false><<<grid, 64 * NW, 0, s>>>((const T*)w, (const T*)w0, (T*)out,
                                                                      (const T*)ff, mfv, mfg, mfl, mgx, mlx, tb.LFS, ml1, tb.Minv, g,
-                                                                     sc, sp.gamma, a0, b0, mode);
+                                                                     sc, sp.gamma, a0, b0, cdt, mode);
       return true;
     }
     return false;
   }
   template <int NW, bool PF>
   bool launch_cell_mfma(const void* w, const void* w0, void* out, const void* ff, const Grid& g, const Scal* sc,
-                        const SchemeParams& sp, double a0, double b0, int mode, hipStream_t s) {
+                        const SchemeParams& sp, double a0, double b0, double cdt, int mode, hipStream_t s) {
     if constexpr (DIVB == GLM) {
       const int64_t tiles = (g.C + 15) / 16;
       const unsigned grid = (unsigned)((tiles + NW - 1) / NW);
       if (g.level)
         k_cell_mfma<T, D, DEG, NW, PF, true><<<grid, 64 * NW, 0, s>>>((const T*)w, (const T*)w0, (T*)out,
                                                                       (const T*)ff, mfv, mfg, mfl, mgx, mlx, tb.LFS, ml1, tb.Minv, g,
-                                                                      sc, sp.gamma, a0, b0, mode);
+                                                                      sc, sp.gamma, a0, b0, cdt, mode);
       else
         k_cell_mfma<T, D, DEG, NW, PF, false><<<grid, 64 * NW, 0, s>>>((const T*)w, (const T*)w0, (T*)out,
                                                                        (const T*)ff, mfv, mfg, mfl, mgx, mlx, tb.LFS, ml1, tb.Minv, g,
-                                                                       sc, sp.gamma, a0, b0, mode);
+                                                                       sc, sp.gamma, a0, b0, cdt, mode);
       return true;
     }
     return false;
   }
   bool launch_cell_powell(int nw, const void* w, const void* w0, void* out, const void* ff, const void* jp,
-                          const Grid& g, const Scal* sc, const SchemeParams& sp, double a0, double b0, int mode,
+                          const Grid& g, const Scal* sc, const SchemeParams& sp, double a0, double b0, double cdt, int mode,
                           hipStream_t s) {
     if constexpr (DIVB == POWELL) {
       if (g.level) return false;
@@ -2366,18 +2397,18 @@ struct LauncherImpl : Launcher {
       if (nw == 4)
         k_cell_mfma_powell<T, D, DEG, 4><<<grid, 256, 0, s>>>((const T*)w, (const T*)w0, (T*)out, (const T*)ff,
                                                               (const T*)jp, mfv, mfg, mfl, mpv, mpg, mpl, tb.Pmean,
-                                                              tb.Minv, g, sc, sp.gamma, a0, b0, mode);
+                                                              tb.Minv, g, sc, sp.gamma, a0, b0, cdt, mode);
       else
         k_cell_mfma_powell<T, D, DEG, 2><<<grid, 128, 0, s>>>((const T*)w, (const T*)w0, (T*)out, (const T*)ff,
                                                               (const T*)jp, mfv, mfg, mfl, mpv, mpg, mpl, tb.Pmean,
-                                                              tb.Minv, g, sc, sp.gamma, a0, b0, mode);
+                                                              tb.Minv, g, sc, sp.gamma, a0, b0, cdt, mode);
       return true;
     }
     return false;
   }
   template <int V>
   bool launch_cell_v(const void* w, const void* w0, void* out, const void* ff, const void* jp, const Grid& g,
-                     const Scal* sc, const SchemeParams& sp, double a0, double b0, int mode, hipStream_t s) {
+                     const Scal* sc, const SchemeParams& sp, double a0, double b0, double cdt, int mode, hipStream_t s) {
     constexpr int TC = CellVariants<T, D, DEG, DIVB>::tc(V), NT = CellVariants<T, D, DEG, DIVB>::nt(V);
     if constexpr (CellTile<T, D, DEG, DIVB, TC, NT>::valid) {
       const int nb = (int)((g.C + TC - 1) / TC);
@@ -2385,11 +2416,11 @@ struct LauncherImpl : Launcher {
         if constexpr (DIVB == GLM)
           k_cell<T, D, DEG, DIVB, TC, NT, 1><<<nb, NT, 0, s>>>(
               (const T*)w, (const T*)w0, (T*)out, (const T*)ff, (const T*)jp, tb.V, tb.GW, tb.LF, tb.Minv, tb.PV,
-              tb.PGW, tb.PLF, tb.Pmean, tb.LFS, g, sc, sp.gamma, a0, b0, mode);
+              tb.PGW, tb.PLF, tb.Pmean, tb.LFS, g, sc, sp.gamma, a0, b0, cdt, mode);
       } else {
         k_cell<T, D, DEG, DIVB, TC, NT, 0><<<nb, NT, 0, s>>>((const T*)w, (const T*)w0, (T*)out, (const T*)ff,
                                                              (const T*)jp, tb.V, tb.GW, tb.LF, tb.Minv, tb.PV, tb.PGW,
-                                                             tb.PLF, tb.Pmean, tb.LFS, g, sc, sp.gamma, a0, b0, mode);
+                                                             tb.PLF, tb.Pmean, tb.LFS, g, sc, sp.gamma, a0, b0, cdt, mode);
       }
       return true;
     } else {
@@ -2427,32 +2458,32 @@ struct LauncherImpl : Launcher {
   void set_cell_variant(int v) override { cell_variant = v; }
   int get_cell_variant() const override { return cell_variant; }
   void cell(const void* w, const void* w0, void* out, const void* ff, const void* jp, const Grid& g, const Scal* sc,
-            const SchemeParams& sp, double a0, double b0, int mode, hipStream_t s) override {
+            const SchemeParams& sp, double a0, double b0, double cdt, int mode, hipStream_t s) override {
     int v = cell_variant;
     if (v < 0) v = DIVB == GLM ? 6 : 8;  // default: a matrix-core kernel
     if (!cell_variant_valid(v)) {
       v = 0;
       while (v < 4 && !cell_variant_valid(v)) ++v;
     }
-    if (v == 4 && launch_cell_mfma<4, false>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
-    if (v == 5 && launch_cell_mfma<2, false>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
-    if (v == 6 && launch_cell_mfma<4, true>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
-    if (v == 7 && launch_cell_mfma<2, true>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
-    if (v == 8 && launch_cell_mfma_p<4>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
-    if (v == 9 && launch_cell_mfma_p<2>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
-    if ((v == 8 || v == 9) && launch_cell_powell(v == 8 ? 4 : 2, w, w0, out, ff, jp, g, sc, sp, a0, b0, mode, s)) return;
+    if (v == 4 && launch_cell_mfma<4, false>(w, w0, out, ff, g, sc, sp, a0, b0, cdt, mode, s)) return;
+    if (v == 5 && launch_cell_mfma<2, false>(w, w0, out, ff, g, sc, sp, a0, b0, cdt, mode, s)) return;
+    if (v == 6 && launch_cell_mfma<4, true>(w, w0, out, ff, g, sc, sp, a0, b0, cdt, mode, s)) return;
+    if (v == 7 && launch_cell_mfma<2, true>(w, w0, out, ff, g, sc, sp, a0, b0, cdt, mode, s)) return;
+    if (v == 8 && launch_cell_mfma_p<4>(w, w0, out, ff, g, sc, sp, a0, b0, cdt, mode, s)) return;
+    if (v == 9 && launch_cell_mfma_p<2>(w, w0, out, ff, g, sc, sp, a0, b0, cdt, mode, s)) return;
+    if ((v == 8 || v == 9) && launch_cell_powell(v == 8 ? 4 : 2, w, w0, out, ff, jp, g, sc, sp, a0, b0, cdt, mode, s)) return;
     // GLM: a persistent form that cannot be resident runs the batched one
     // (same face-flux layout)
-    if (v >= 8 && launch_cell_mfma<4, true>(w, w0, out, ff, g, sc, sp, a0, b0, mode, s)) return;
+    if (v >= 8 && launch_cell_mfma<4, true>(w, w0, out, ff, g, sc, sp, a0, b0, cdt, mode, s)) return;
     if (v >= 4) {  // not built for this configuration
       v = 0;
       while (v < 4 && !cell_variant_valid(v)) ++v;
     }
     switch (v) {
-      case 0: launch_cell_v<0>(w, w0, out, ff, jp, g, sc, sp, a0, b0, mode, s); break;
-      case 1: launch_cell_v<1>(w, w0, out, ff, jp, g, sc, sp, a0, b0, mode, s); break;
-      case 2: launch_cell_v<2>(w, w0, out, ff, jp, g, sc, sp, a0, b0, mode, s); break;
-      default: launch_cell_v<3>(w, w0, out, ff, jp, g, sc, sp, a0, b0, mode, s); break;
+      case 0: launch_cell_v<0>(w, w0, out, ff, jp, g, sc, sp, a0, b0, cdt, mode, s); break;
+      case 1: launch_cell_v<1>(w, w0, out, ff, jp, g, sc, sp, a0, b0, cdt, mode, s); break;
+      case 2: launch_cell_v<2>(w, w0, out, ff, jp, g, sc, sp, a0, b0, cdt, mode, s); break;
+      default: launch_cell_v<3>(w, w0, out, ff, jp, g, sc, sp, a0, b0, cdt, mode, s); break;
     }
   }
   void maxsig(const void* w, const Grid& g, Scal* sc, const SchemeParams& sp, hipStream_t s) override {

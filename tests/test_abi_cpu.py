@@ -45,6 +45,8 @@ def _mesh(n=(4, 4, 4), box=(1.0, 1.0, 1.0), kind=B.DG_MESH_UNIFORM):
     (dict(divb=7), {}, B.DG_EINVAL),
     (dict(precision=3), {}, B.DG_EINVAL),
     (dict(rk_stages=4), {}, B.DG_EUNSUPPORTED),
+    (dict(rk_stages=0), {}, B.DG_EUNSUPPORTED),
+    (dict(rk_stages=6), {}, B.DG_EUNSUPPORTED),
     (dict(cfl=1.5), {}, B.DG_EINVAL),
     (dict(gamma=1.0), {}, B.DG_EINVAL),
     (dict(dim=2, divb=B.DG_POWELL), {}, B.DG_EUNSUPPORTED),

@@ -1,4 +1,4 @@
-"""hipGraph replay of the SSP-RK3 step (handles on a non-null stream) gives
+"""hipGraph replay of the SSP-RK step (handles on a non-null stream) gives
 bitwise the same states as direct launches, replay after replay, with eager
 work and synchronisations between replays."""
 import numpy as np
@@ -10,15 +10,17 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("D,d,n,lim,field", [(3, 2, 6, 0, "smooth"), (3, 3, 5, 7, "blast"), (2, 1, 32, 0, "smooth")])
-def test_graph_replays_match_direct_launches(D, d, n, lim, field):
+@pytest.mark.parametrize("D,d,n,lim,field,rk", [(3, 2, 6, 0, "smooth", 3), (3, 3, 5, 7, "blast", 3),
+                                                (2, 1, 32, 0, "smooth", 3), (3, 2, 6, 7, "blast", 5),
+                                                (2, 2, 12, 0, "smooth", 2)])
+def test_graph_replays_match_direct_launches(D, d, n, lim, field, rk):
     from paper_1806_02343_amd import DG
-    print("case graph", D, d, n, lim, flush=True)
+    print("case graph", D, d, n, lim, rk, flush=True)
     f = wl.Smooth(11, D) if field == "smooth" else wl.Blast(2000)
     s = torch.cuda.Stream()
-    direct = DG(D, d, n, limiter=lim)                 # null stream: direct launches
+    direct = DG(D, d, n, limiter=lim, rk_stages=rk)   # null stream: direct launches
     with torch.cuda.stream(s):
-        graphed = DG(D, d, n, limiter=lim, stream=s.cuda_stream)
+        graphed = DG(D, d, n, limiter=lim, stream=s.cuda_stream, rk_stages=rk)
         wa = graphed.empty_state()
         graphed.project_field(f, wa)
         if lim:

@@ -295,3 +295,53 @@ def test_fp32_matrix_core_path_preserves_a_uniform_state(case):
         r = out[:, :orc.mesh.ncells].double().cpu().numpy()
         r[8 * orc.n] += 0.5 * 0.25          # the GLM damping of psi is the only nonzero term
         assert np.abs(r).max() < 1e-10, (v, np.abs(r).max())
+
+
+RK_CASES = [(2, 1, 16, dg.GLM, 1), (2, 2, 12, dg.GLM, 2), (3, 3, 5, dg.GLM, 5), (3, 2, 6, dg.POWELL, 5),
+            (3, 1, 7, dg.GLM, 2), (3, 2, 5, dg.POWELL, 1)]
+
+
+@pytest.mark.parametrize("case", RK_CASES, ids=lambda c: ids(c[:4]) + f"rk{c[4]}")
+def test_ssp_rk_schemes_match_oracle(case):
+    """Forward Euler, SSP-RK2 and the five-stage fourth-order SSP scheme
+    (Sec. 3.6: order 1-4) against the oracle's Shu-Osher steps, FP64 to 1e-12."""
+    D, d, n, divb, rk = case
+    nsteps = 4
+    _announce("rk", case)
+    gpu, wg, orc, wo = make_pair(D, d, n, divb, rk_stages=rk)
+    t_o = 0.0
+    for _ in range(nsteps):
+        wo, dt, ch, k = orc.step(wo, rk=rk)
+        t_o += dt
+    t_g = gpu.step(wg, nsteps)
+    assert abs(t_g - t_o) <= 1e-12 * t_o
+    err = rel_l1(orc, to_cells(wg, orc.mesh.ncells), wo, ch=max(ch, 1.0))
+    assert np.all(err < 1e-12), err
+
+
+@pytest.mark.parametrize("rk", [2, 5])
+def test_ssp_rk_with_limiters_match_oracle(rk):
+    """The limited blast with SSP-RK2 and SSP-RK(5,4): the limiters after every
+    stage, including the fourth stage of the (5,4) scheme, whose unlimited
+    state also enters the final combination."""
+    from oracle import limiters
+    _announce("rk limited", rk)
+    gpu, wg, orc, wo = make_pair(3, 2, 6, dg.GLM, field=wl.Blast(2000), limiter=7, rk_stages=rk)
+    olim = limiters.make_stage_limiter(orc, 7)
+    wo = olim(wo)
+    gpu.limit(wg)
+    for _ in range(3):
+        wo, dt, ch, k = orc.step(wo, limiter=olim, rk=rk)
+    gpu.step(wg, 3)
+    err = rel_l1(orc, to_cells(wg, orc.mesh.ncells), wo, ch=ch)
+    assert np.all(err < 1e-12), err
+
+
+def test_ssp_rk4_fp32_matches_oracle():
+    _announce("rk5 fp32")
+    gpu, wg, orc, wo = make_pair(3, 2, 6, dg.GLM, precision=1, rk_stages=5)
+    for _ in range(3):
+        wo, dt, ch, k = orc.step(wo, rk=5)
+    gpu.step(wg, 3)
+    err = rel_l1(orc, to_cells(wg, orc.mesh.ncells), wo, ch=max(ch, 1.0))
+    assert np.all(err < 1e-5), err
