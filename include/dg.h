@@ -73,6 +73,7 @@ enum { DG_GLM = 0, DG_POWELL = 1 };
 enum { DG_FP64 = 0, DG_FP32 = 1 };
 enum { DG_LIM_TVB = 1, DG_LIM_CHAR = 2, DG_LIM_POS = 4, DG_LIM_LEARNED = 8 };
 enum { DG_MESH_UNIFORM = 0, DG_MESH_OCTREE = 1 };
+enum { DG_POWELL_Q_MEAN = 0, DG_POWELL_Q_INTERP = 1 };
 
 /* Scheme parameters (Sec. 3.6, 4.1, 4.2, 4.3; defaults of the paper in
  * brackets).  rk_stages selects the SSP Runge-Kutta scheme of Sec. 3.6 (order
@@ -83,9 +84,14 @@ enum { DG_MESH_UNIFORM = 0, DG_MESH_OCTREE = 1 };
  * glm_ch_fixed > 0 fixes c_h (required on octree meshes).  tvb_Mtilde [5],
  * tvb_beta [2], tvb_eps [1e-8]; eps_rho = eps_p [1e-12]; powell_eta [0.2].
  * mlp_lo / mlp_hi bound the band of learned-indicator outputs that falls
- * back to the plain TVB detector. */
+ * back to the plain TVB detector.  powell_q (Powell scheme only) selects the
+ * state q-dagger of the face term eq. powell-src-face: DG_POWELL_Q_MEAN, q of
+ * the cell average (eq. powellq-average, the paper's default), or
+ * DG_POWELL_Q_INTERP, q integrated along the straight path in primitive
+ * variables from the cell's trace to the HLLD interface state
+ * (eq. powellq-interp). */
 typedef struct {
-  int32_t dim, degree, divb, precision, rk_stages, limiter;
+  int32_t dim, degree, divb, precision, rk_stages, limiter, powell_q;
   double gamma, cfl, cfl_glm, glm_cr, glm_ch_fixed;
   double tvb_Mtilde, tvb_beta, tvb_eps, eps_rho, eps_p, powell_eta;
   double mlp_lo, mlp_hi;

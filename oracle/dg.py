@@ -11,7 +11,9 @@ with (d+1)-point Gauss-Legendre rules for the volume and the faces.
 Powell (Sec. 4.1.3, eq. powell-src-face with q-dagger = q(<u>_K),
 eq. powellq-average): each cell adds
   -(2/h) sum_faces sum_r w_r (q(<u>_K) . phi_l)(B^n_F - B^n_K)
-with the outward normal.  GLM (Sec. 4.1.5): psi flux and damping source
+with the outward normal; optionally (eq. powellq-interp) q-dagger varies over
+the face points, q integrated along the straight path in primitive variables
+from the cell's own trace to the HLLD interface state.  GLM (Sec. 4.1.5): psi flux and damping source
 -kappa psi, kappa = c_h^2 / c_p^2.
 
 Time step (Sec. 3.6, eq. cfl; Sec. 4.1.4, eq. powell_dt; Sec. 4.1.5 for c_h,
@@ -116,12 +118,18 @@ class DG:
     the N_div LDF weights of the magnetic field."""
 
     def __init__(self, mesh, d, divb=GLM, gamma=5.0 / 3.0, cfl=0.3, cfl_glm=None, glm_cr=0.18,
-                 glm_ch_fixed=0.0, powell_eta=0.2):
+                 glm_ch_fixed=0.0, powell_eta=0.2, powell_q="mean"):
+        """powell_q: the state q-dagger of the Powell face term, "mean"
+        (q of the cell average, eq. powellq-average) or "interp" (eq.
+        powellq-interp, with the HLLD interface state)."""
         D = mesh.D
         self.mesh, self.D, self.d = mesh, D, d
         self.divb, self.gamma, self.cfl = divb, gamma, cfl
         self.cfl_glm = cfl_glm if cfl_glm is not None else min(2.0 * cfl, 0.9)
         self.glm_cr, self.glm_ch_fixed, self.powell_eta = glm_cr, glm_ch_fixed, powell_eta
+        if powell_q not in ("mean", "interp"):
+            raise ValueError(powell_q)
+        self.powell_q = powell_q
         self.n = B.n_modes(D, d)
         P = d + 1
         self.P = P
@@ -269,7 +277,11 @@ class DG:
                     tR = self._basis_at(self.face_points(a, -1, subR))
                     UL = self.nodal(w[L], tabs=tL)
                     UR = self.nodal(w[Rc], tabs=tR)
-                    Fs, bnF = ph.numerical_flux(UL, UR, a, g, glm, ch)
+                    interp = self.divb == POWELL and self.powell_q == "interp"
+                    if interp:
+                        Fs, bnF, vF, BF = ph.numerical_flux(UL, UR, a, g, glm, ch, state=True)
+                    else:
+                        Fs, bnF = ph.numerical_flux(UL, UR, a, g, glm, ch)
                     wL = self.wf * self.sub_weight(subL)
                     wR = self.wf * self.sub_weight(subR)
                     cL = self.project_test(Fs, tL, wL) * (2.0 / h[L])[:, None]
@@ -279,8 +291,12 @@ class DG:
                     if self.divb == POWELL:
                         jL = bnF - UL[ph.B1 + a]     # B^n_F - B^n_L (outward +e_a)
                         jR = UR[ph.B1 + a] - bnF     # (-B^n_F) - (-B^n_R)
-                        qL = ph.powell_q(Ub[:, L])[:, :, None] * jL[None]
-                        qR = ph.powell_q(Ub[:, Rc])[:, :, None] * jR[None]
+                        if interp:
+                            qL = ph.powell_q_interp(UL, vF, BF) * jL[None]
+                            qR = ph.powell_q_interp(UR, vF, BF) * jR[None]
+                        else:
+                            qL = ph.powell_q(Ub[:, L])[:, :, None] * jL[None]
+                            qR = ph.powell_q(Ub[:, Rc])[:, :, None] * jR[None]
                         pL = self.project_test(qL, tL, wL) * (2.0 / h[L])[:, None]
                         pR = self.project_test(qR, tR, wR) * (2.0 / h[Rc])[:, None]
                         np.subtract.at(R, L, pL)

@@ -85,12 +85,15 @@ def _sgn(x):
     return np.where(x >= 0.0, 1.0, -1.0)
 
 
-def hlld(WL, WR, bx, gamma):
+def hlld(WL, WR, bx, gamma, state=False):
     """HLLD flux of Miyoshi & Kusano (2005) in the face frame.
 
     WL, WR: primitive states (rho, u, v, w, p, By, Bz) on axis 0; bx the common
     normal field.  Returns the 8-component flux of (rho, m_n, m_t1, m_t2, E,
-    B_n, B_t1, B_t2), the B_n component being zero."""
+    B_n, B_t1, B_t2), the B_n component being zero.  state=True also returns
+    the state of the fan region that contains the face (x/t = 0) as
+    (rho, u, v, w, By, Bz): the interface state of Sec. 4.1.3 ("Interface
+    state U_F")."""
     g = gamma
 
     def cons_and_flux(W):
@@ -175,7 +178,22 @@ def hlld(WL, WR, bx, gamma):
           np.where(SM > 0.0, FssL,
           np.where(SsR > 0.0, FssR,
           np.where(SR > 0.0, FsR, FR)))))
-    return out
+    if not state:
+        return out
+    # the same fan regions, as primitive states
+    SMa = np.broadcast_to(SM, rsL.shape)
+    stL = np.stack([rL, uL, vL, wL, byL, bzL])
+    stR = np.stack([rR, uR, vR, wR, byR, bzR])
+    stsL = np.stack([rsL, SMa, vsL, wsL, bysL, bzsL])
+    stsR = np.stack([rsR, SMa, vsR, wsR, bysR, bzsR])
+    stssL = np.stack([rsL, SMa, vss, wss, byss, bzss])
+    stssR = np.stack([rsR, SMa, vss, wss, byss, bzss])
+    st = np.where(SL > 0.0, stL,
+         np.where(SsL > 0.0, stsL,
+         np.where(SM > 0.0, stssL,
+         np.where(SsR > 0.0, stssR,
+         np.where(SR > 0.0, stsR, stR)))))
+    return out, st
 
 
 def face_frame(a):
@@ -183,11 +201,14 @@ def face_frame(a):
     return a, (a + 1) % 3, (a + 2) % 3
 
 
-def numerical_flux(UL, UR, a, gamma, glm=False, ch=0.0):
+def numerical_flux(UL, UR, a, gamma, glm=False, ch=0.0, state=False):
     """Numerical flux through a face with normal +e_a (global components).
 
     Returns (F, bnF): F has the components of U; bnF is the face normal field
-    B^n_F (also needed by the Powell face term and the divergence norm)."""
+    B^n_F (also needed by the Powell face term and the divergence norm).
+    state=True returns (F, bnF, vF, BF) with the velocity and magnetic field
+    of the HLLD interface state in global components (its normal field is
+    B^n_F)."""
     n, t1, t2 = face_frame(a)
 
     def prim(U):
@@ -199,7 +220,10 @@ def numerical_flux(UL, UR, a, gamma, glm=False, ch=0.0):
     WR = np.stack(prim(UR))
     bnL, bnR = UL[B1 + n], UR[B1 + n]
     bnF = face_normal_field(bnL, UL[RHO], bnR, UR[RHO])
-    Fn = hlld(WL, WR, bnF, gamma)
+    if state:
+        Fn, st = hlld(WL, WR, bnF, gamma, state=True)
+    else:
+        Fn = hlld(WL, WR, bnF, gamma)
     F = np.zeros_like(UL)
     F[RHO] = Fn[0]
     F[M1 + n], F[M1 + t1], F[M1 + t2] = Fn[1], Fn[2], Fn[3]
@@ -211,7 +235,26 @@ def numerical_flux(UL, UR, a, gamma, glm=False, ch=0.0):
         psi_star = 0.5 * (psiL + psiR) - 0.5 * ch * (bnR - bnL)
         F[B1 + n] = psi_star
         F[PSI] = ch * ch * bn_star
-    return F, bnF
+    if not state:
+        return F, bnF
+    vF = np.empty((3,) + np.shape(bnF))
+    BF = np.empty((3,) + np.shape(bnF))
+    vF[n], vF[t1], vF[t2] = st[1], st[2], st[3]
+    BF[n], BF[t1], BF[t2] = bnF, st[4], st[5]
+    return F, bnF, vF, BF
+
+
+def powell_q_interp(U, vF, BF):
+    """q-dagger of eq. powellq-interp for a side whose trace is U (conserved)
+    and the interface velocity vF and field BF:
+    (0, (B + B_F)/2, (2 B.v + B.v_F + B_F.v + 2 B_F.v_F)/6, (v + v_F)/2)."""
+    rho = U[RHO]
+    v = np.stack([U[M1] / rho, U[M2] / rho, U[M3] / rho])
+    B = np.stack([U[B1], U[B2], U[B3]])
+    dot = lambda x, y: (x * y).sum(axis=0)
+    e = (2.0 * dot(B, v) + dot(B, vF) + dot(BF, v) + 2.0 * dot(BF, vF)) / 6.0
+    return np.stack([np.zeros_like(rho), 0.5 * (B[0] + BF[0]), 0.5 * (B[1] + BF[1]), 0.5 * (B[2] + BF[2]), e,
+                     0.5 * (v[0] + vF[0]), 0.5 * (v[1] + vF[1]), 0.5 * (v[2] + vF[2])])
 
 
 def powell_q(U):

@@ -10,6 +10,7 @@ DG_GLM, DG_POWELL = 0, 1
 DG_FP64, DG_FP32 = 0, 1
 DG_LIM_TVB, DG_LIM_CHAR, DG_LIM_POS, DG_LIM_LEARNED = 1, 2, 4, 8
 DG_MESH_UNIFORM, DG_MESH_OCTREE = 0, 1
+DG_POWELL_Q_MEAN, DG_POWELL_Q_INTERP = 0, 1
 
 EXPORTS = ["dg_init", "dg_layout", "dg_proj_points", "dg_project", "dg_dt", "dg_rhs", "dg_rhs_noalloc", "dg_limit",
            "dg_step",
@@ -21,6 +22,7 @@ MLP_NPARAM = 24833
 class dg_params(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("degree", ctypes.c_int32), ("divb", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("rk_stages", ctypes.c_int32), ("limiter", ctypes.c_int32),
+                ("powell_q", ctypes.c_int32),
                 ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("cfl_glm", ctypes.c_double),
                 ("glm_cr", ctypes.c_double), ("glm_ch_fixed", ctypes.c_double),
                 ("tvb_Mtilde", ctypes.c_double), ("tvb_beta", ctypes.c_double), ("tvb_eps", ctypes.c_double),
@@ -109,14 +111,15 @@ class DG:
     def __init__(self, dim, degree, n, box=1.0, divb=DG_GLM, precision=DG_FP64, limiter=0, gamma=5.0 / 3.0,
                  cfl=0.3, cfl_glm=0.0, glm_cr=0.18, glm_ch_fixed=0.0, tvb_Mtilde=5.0, tvb_beta=2.0, tvb_eps=1e-8,
                  eps_rho=1e-12, eps_p=1e-12, powell_eta=0.2, mlp_lo=0.0, mlp_hi=0.0, stream=None, octree=None,
-                 rk_stages=3):
+                 rk_stages=3, powell_q=0):
         """octree: optional (level[int8, C], ijk[int32, C x 3]) leaves on the level
         grids of the base grid n (kind DG_MESH_OCTREE)."""
         import torch
         self.torch = torch
         self.lib = load_library()
         self.dim, self.degree, self.divb, self.precision = dim, degree, divb, precision
-        p = dg_params(dim, degree, divb, precision, rk_stages, limiter, gamma, cfl, cfl_glm, glm_cr, glm_ch_fixed,
+        p = dg_params(dim, degree, divb, precision, rk_stages, limiter, powell_q, gamma, cfl, cfl_glm, glm_cr,
+                      glm_ch_fixed,
                       tvb_Mtilde, tvb_beta, tvb_eps, eps_rho, eps_p, powell_eta, mlp_lo, mlp_hi)
         nn = list(n) if hasattr(n, "__len__") else [n] * dim
         bb = list(box) if hasattr(box, "__len__") else [box] * dim

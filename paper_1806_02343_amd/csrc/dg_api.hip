@@ -277,6 +277,10 @@ int dg_init(const dg_params* p, const dg_mesh* m, void* hip_stream, dg_handle* o
     if (!(p->glm_ch_fixed > 0.0)) return fail(nullptr, DG_EINVAL, "octree meshes need a fixed c_h (glm_ch_fixed)");
     if (m->nleaves <= 0 || !m->level || !m->ijk) return fail(nullptr, DG_EINVAL, "octree leaves missing");
   }
+  if (p->powell_q != DG_POWELL_Q_MEAN && p->powell_q != DG_POWELL_Q_INTERP)
+    return fail(nullptr, DG_EINVAL, "unknown powell_q");
+  if (p->powell_q == DG_POWELL_Q_INTERP && p->divb != DG_POWELL)
+    return fail(nullptr, DG_EINVAL, "powell_q selects the Powell scheme's q-dagger: divb must be DG_POWELL");
   if (p->limiter & ~(DG_LIM_TVB | DG_LIM_CHAR | DG_LIM_POS | DG_LIM_LEARNED))
     return fail(nullptr, DG_EINVAL, "unknown limiter flags");
   if ((p->limiter & DG_LIM_TVB) && p->divb == DG_POWELL)
@@ -334,6 +338,7 @@ int dg_init(const dg_params* p, const dg_mesh* m, void* hip_stream, dg_handle* o
   sp.eps_rho = p->eps_rho > 0.0 ? p->eps_rho : 1e-12;
   sp.eps_p = p->eps_p > 0.0 ? p->eps_p : 1e-12;
   sp.limiter = p->limiter;
+  sp.powell_q = p->powell_q;
   sp.mlp_lo = p->mlp_lo;
   sp.mlp_hi = p->mlp_hi > 0.0 ? p->mlp_hi : 0.5;
   sp.mlp_Pb = nullptr;
@@ -349,7 +354,7 @@ int dg_init(const dg_params* p, const dg_mesh* m, void* hip_stream, dg_handle* o
   if (e != hipSuccess) return cleanup(DG_EHIP, std::string("table upload: ") + hipGetErrorString(e));
   const size_t nm = (size_t)h->L->nmodes();
   if ((e = hipMalloc(&h->ff, h->L->face_buffer_elems(g) * h->elem)) != hipSuccess) return cleanup(DG_ENOMEM, "face buffer");
-  if (size_t nj = h->L->jump_buffer_elems(g)) {
+  if (size_t nj = h->L->jump_buffer_elems(g, p->powell_q)) {
     if ((e = hipMalloc(&h->jp, nj * h->elem)) != hipSuccess) return cleanup(DG_ENOMEM, "jump buffer");
     if ((e = hipMalloc(&h->jsum, (size_t)2 * p->dim * g.C * sizeof(double))) != hipSuccess) return cleanup(DG_ENOMEM, "jump sums");
   }
@@ -451,7 +456,7 @@ int dg_rhs_noalloc(dg_handle h, const void* w, void* dwdt, double ch, double kap
   const size_t off_ff = (sizeof(Scal) + 255) / 256 * 256;
   const size_t nff = h->L->face_buffer_elems(h->g) * h->elem;
   const size_t off_jp = off_ff + (nff + 255) / 256 * 256;
-  const size_t need = off_jp + h->L->jump_buffer_elems(h->g) * h->elem;
+  const size_t need = off_jp + h->L->jump_buffer_elems(h->g, h->p.powell_q) * h->elem;
   if (need > kScratchBytes) {
     std::ostringstream m;
     m << "dg_rhs_noalloc: this mesh needs " << need << " bytes of workspace, the scratch array holds "
@@ -461,7 +466,7 @@ int dg_rhs_noalloc(dg_handle h, const void* w, void* dwdt, double ch, double kap
   unsigned char* base = (unsigned char*)h->scratch;
   Scal* sc = (Scal*)base;
   void* ff = base + off_ff;
-  void* jp = h->L->jump_buffer_elems(h->g) ? (void*)(base + off_jp) : nullptr;
+  void* jp = h->L->jump_buffer_elems(h->g, h->p.powell_q) ? (void*)(base + off_jp) : nullptr;
   launch_set_scalars(sc, ch, kappa, 0.0, h->stream);
   h->L->face(w, ff, jp, h->g, sc, h->sp, h->stream);
   h->L->cell(w, w, dwdt, ff, jp, h->g, sc, h->sp, 0.0, 1.0, 1.0, 0, h->stream);

@@ -55,6 +55,7 @@ struct SchemeParams {
   double gamma, cfl, cfl_glm, glm_cr, glm_ch_fixed, powell_eta;
   double tvb_Mtilde, tvb_beta, tvb_eps, eps_rho, eps_p;
   int limiter;
+  int powell_q;  // Powell q-dagger: 0 cell mean (eq. powellq-average), 1 interpolated (eq. powellq-interp)
   // learned indicator (device pointers, null until installed)
   double mlp_lo, mlp_hi;
   const uint16_t* mlp_Pb;
@@ -68,7 +69,7 @@ struct Launcher {
   virtual hipError_t upload_tables(const Tables& t) = 0;
   virtual void free_tables() = 0;
   virtual size_t face_buffer_elems(const Grid& g) const = 0;
-  virtual size_t jump_buffer_elems(const Grid& g) const = 0;
+  virtual size_t jump_buffer_elems(const Grid& g, int powell_q) const = 0;
   // face fluxes of state w into ff (and Powell jumps into jp)
   virtual void face(const void* w, void* ff, void* jp, const Grid& g, const Scal* sc, const SchemeParams& sp,
                     hipStream_t s) = 0;

@@ -123,7 +123,7 @@ struct FaceTile {
 template <typename T, int D, int DEG, int DIVB>
 __global__ void __launch_bounds__((FaceTile<T, D, DEG, DIVB>::NT))
     k_face(const T* __restrict__ w, T* __restrict__ ff, T* __restrict__ jp, DevTab<T> tb, Grid g,
-           const Scal* __restrict__ sc, double gamma) {
+           const Scal* __restrict__ sc, double gamma, int qint) {
   using C = Cfg<D, DEG, DIVB>;
   constexpr int TF = FaceTile<T, D, DEG, DIVB>::TF, NT = FaceTile<T, D, DEG, DIVB>::NT;
   constexpr int NM = C::NMODES, N = C::N;
@@ -180,6 +180,24 @@ __global__ void __launch_bounds__((FaceTile<T, D, DEG, DIVB>::NT))
     }
   }
   T F[9];
+  if constexpr (DIVB == POWELL) {
+    if (qint) {
+      // interpolated q-dagger (eq. powellq-interp) with the HLLD interface
+      // state: the Powell term of each side is added here, the left cell's
+      // face values to ff, the right cell's to jp (same layout as ff)
+      T vf[3], bf[3], ql[8], qr[8];
+      const T bnF = face_flux<T, C::NV>(uL, uR, a, gamma, (T)sc->ch, F, vf, bf);
+      powell_q_interp<T>(uL, vf, bf, ql);
+      powell_q_interp<T>(uR, vf, bf, qr);
+      const T jl = bnF - uL[5 + a], jr = uR[5 + a] - bnF;
+#pragma unroll
+      for (int v = 0; v < C::NV; ++v) {
+        ff[((int64_t)(a * C::NV + v) * C::FP + r) * ld + f] = F[v] + ql[v] * jl;
+        jp[((int64_t)(a * C::NV + v) * C::FP + r) * ld + f] = F[v] - qr[v] * jr;
+      }
+      return;
+    }
+  }
   const T bnF = face_flux<T, C::NV>(uL, uR, a, gamma, (T)sc->ch, F);
 #pragma unroll
   for (int v = 0; v < C::NV; ++v) ff[((int64_t)(a * C::NV + v) * C::FP + r) * ld + f] = F[v];
@@ -376,6 +394,9 @@ __global__ void __launch_bounds__(NT)
         }
     }
     T qv[8];
+    // interpolated q-dagger (mode bit 2): the face kernel added each side's
+    // Powell term to that side's face values (left: ff, right: jp)
+    const bool qint = DIVB == POWELL && (mode & 2);
     if constexpr (DIVB == POWELL) {
       // q(<u>_K) = (0, B, v.B, v) from the cell means (eq. powellq-average)
       const T rho = sw[0 * TC + c];
@@ -390,6 +411,8 @@ __global__ void __launch_bounds__(NT)
       qv[0] = 0; qv[1] = bm[0]; qv[2] = bm[1]; qv[3] = bm[2];
       qv[4] = v0 * bm[0] + v1 * bm[1] + v2 * bm[2];
       qv[5] = v0; qv[6] = v1; qv[7] = v2;
+      if (qint)
+        for (int v = 0; v < 8; ++v) qv[v] = T(0);
     }
     for (int a = 0; a < (AMR ? 0 : D); ++a) {
       const int64_t Km = nbr(K, a, -1, g);
@@ -398,27 +421,32 @@ __global__ void __launch_bounds__(NT)
       if (blk < C::NLEG) {
         const int v = C::legvar(blk);
         const T* fv = ff + (int64_t)(a * C::NV + v) * C::FP * ld;
+        const T* fvm = qint ? jp + (int64_t)(a * C::NV + v) * C::FP * ld : fv;  // the -a face's values
         for (int r = 0; r < C::FP; ++r) {
-          const T fp = fv[(int64_t)r * ld + K], fm = fv[(int64_t)r * ld + Km];
+          const T fp = fv[(int64_t)r * ld + K], fm = fvm[(int64_t)r * ld + Km];
           const T* lfp = tb.LF + ((a * 2 + 1) * C::FP + r) * N;
           const T* lfm = tb.LF + ((a * 2 + 0) * C::FP + r) * N;
 #pragma unroll
           for (int l = 0; l < N; ++l) acc[k][l] += lfm[l] * fm - lfp[l] * fp;
           if constexpr (DIVB == POWELL) {
-            const T ql = qv[v] * jl[(int64_t)r * ld + K], qr = qv[v] * jr[(int64_t)r * ld + Km];
+            if (!qint) {
+              const T ql = qv[v] * jl[(int64_t)r * ld + K], qr = qv[v] * jr[(int64_t)r * ld + Km];
 #pragma unroll
-            for (int l = 0; l < N; ++l) acc[k][l] -= lfp[l] * ql + lfm[l] * qr;
+              for (int l = 0; l < N; ++l) acc[k][l] -= lfp[l] * ql + lfm[l] * qr;
+            }
           }
         }
       } else if constexpr (C::NLDF > 0) {
         const int h = blk - C::NLEG;
         for (int cc = 0; cc < D; ++cc) {
           const T* fv = ff + (int64_t)(a * C::NV + 5 + cc) * C::FP * ld;
+          const T* fvm = qint ? jp + (int64_t)(a * C::NV + 5 + cc) * C::FP * ld : fv;
           for (int r = 0; r < C::FP; ++r) {
-            const T fp = fv[(int64_t)r * ld + K], fm = fv[(int64_t)r * ld + Km];
+            const T fp = fv[(int64_t)r * ld + K], fm = fvm[(int64_t)r * ld + Km];
             const T* pp = tb.PLF + (((a * 2 + 1) * D + cc) * C::FP + r) * C::NLDF + h * N;
             const T* pm = tb.PLF + (((a * 2 + 0) * D + cc) * C::FP + r) * C::NLDF + h * N;
-            const T ql = qv[5 + cc] * jl[(int64_t)r * ld + K], qr = qv[5 + cc] * jr[(int64_t)r * ld + Km];
+            const T ql = qint ? T(0) : qv[5 + cc] * jl[(int64_t)r * ld + K];
+            const T qr = qint ? T(0) : qv[5 + cc] * jr[(int64_t)r * ld + Km];
 #pragma unroll
             for (int i = 0; i < N; ++i)
               if (h * N + i < C::NLDF) acc[k][i] += pm[i] * fm - pp[i] * fp - (pp[i] * ql + pm[i] * qr);
@@ -432,7 +460,7 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
     for (int l = 0; l < N; ++l) {
       const int m = blk < C::NLEG ? blk * N + l : C::NLEG * N + (blk - C::NLEG) * N + l;
-      base[l] = (mode != 0 && m < NM) ? w0[(int64_t)m * ld + K] : T(0);
+      base[l] = ((mode & 1) && m < NM) ? w0[(int64_t)m * ld + K] : T(0);
     }
 #pragma unroll
     for (int l = 0; l < N; ++l) {
@@ -443,7 +471,7 @@ __global__ void __launch_bounds__(NT)
       if constexpr (DIVB == GLM) {
         if (m >= 8 * N) dw -= kappa * wm;
       }
-      if (mode == 0) out[(int64_t)m * ld + K] = dw;
+      if (!(mode & 1)) out[(int64_t)m * ld + K] = dw;
       else out[(int64_t)m * ld + K] = (T)a0 * base[l] + (T)b0 * (wm + (T)dt * dw);
     }
   }
@@ -987,8 +1015,8 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
       for (int r = 0; r < 4; ++r) {
         const int n = 16 * mt + M::row(kq, r);
         const int64_t at = (int64_t)(v * N + (n < N ? n : 0)) * ld + K;
-        wm[mt][r] = (v == 8 || mode != 0) ? w[at] : T(0);
-        base[mt][r] = mode != 0 ? w0[at] : T(0);
+        wm[mt][r] = (v == 8 || (mode & 1)) ? w[at] : T(0);
+        base[mt][r] = (mode & 1) ? w0[at] : T(0);
         mi[mt][r] = n < N ? Minv[v * N + n] : T(0);
       }
   };
@@ -1014,7 +1042,7 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
         }
         T dw = racc * two_h * mi[mt][r];
         if (v == 8) dw -= kappa * wm[mt][r];
-        if (mode == 0) out[(int64_t)m * ld + K] = dw;
+        if (!(mode & 1)) out[(int64_t)m * ld + K] = dw;
         else out[(int64_t)m * ld + K] = (T)a0 * base[mt][r] + (T)b0 * (wm[mt][r] + (T)dt * dw);
       }
   }
@@ -1166,6 +1194,10 @@ __device__ __forceinline__ void cell_tile_mfma_powell(int64_t c0, int lane, cons
     qv[4] = v0 * bm[0] + v1 * bm[1] + v2 * bm[2];
     qv[5] = v0; qv[6] = v1; qv[7] = v2;
   }
+  const bool qint = (mode & 2) != 0;  // interpolated q-dagger: the Powell terms come with the face values
+  if (qint)
+#pragma unroll
+    for (int v = 0; v < 8; ++v) qv[v] = T(0);
   // surface first: flux + Powell term of face point k = 4 s + kq as one B operand per variable
 #pragma unroll 1
   for (int s = 0; s < S::KS; ++s) {
@@ -1174,11 +1206,14 @@ __device__ __forceinline__ void cell_tile_mfma_powell(int64_t c0, int lane, cons
     const int a = kv ? k / (2 * FP) : 0, side = (k / FP) % 2, r = k % FP;
     const int64_t Kf = side ? Kc : nbr(Kc, a, -1, g);
     // side +a: jump B^n_F - B^n_K at face K; side -a: B^n_K - B^n_F at face K-a
-    const T jmp = kv ? jp[((int64_t)(a * 2 + (side ? 0 : 1)) * FP + r) * ld + Kf] : T(0);
+    // (interpolated q-dagger: the face kernel added each side's Powell term
+    // to its face values, the left side's in ff, the right side's in jp)
+    const T jmp = (kv && !qint) ? jp[((int64_t)(a * 2 + (side ? 0 : 1)) * FP + r) * ld + Kf] : T(0);
+    const T* src = (qint && !side) ? jp : ff;
     T bv[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const T f = kv ? ff[((int64_t)(a * NV + v) * FP + r) * ld + Kf] : T(0);
+      const T f = kv ? src[((int64_t)(a * NV + v) * FP + r) * ld + Kf] : T(0);
       bv[v] = side ? f + qv[v] * jmp : f - qv[v] * jmp;
     }
 #pragma unroll
@@ -1260,7 +1295,7 @@ __device__ __forceinline__ void cell_tile_mfma_powell(int64_t c0, int lane, cons
   const T two_h = T(2.0 / g.h);
   auto finish = [&](int m, T racc) {
     T dw = racc * two_h * Minv[m];
-    if (mode == 0) return dw;
+    if (!(mode & 1)) return dw;
     return (T)a0 * w0[(int64_t)m * ld + K] + (T)b0 * (w[(int64_t)m * ld + K] + (T)dt * dw);
   };
   // out may alias w or w0: every element's loads precede its store, grouped per block
@@ -2295,8 +2330,11 @@ struct LauncherImpl : Launcher {
     constexpr int rows = C::FP > C::FM + 2 ? C::FP : C::FM + 2;
     return g.level ? (size_t)C::NV * C::FP * g.ldf : (size_t)D * C::NV * rows * g.ld;
   }
-  size_t jump_buffer_elems(const Grid& g) const override {
-    return DIVB == POWELL ? (size_t)D * 2 * C::FP * g.ld : 0;
+  size_t jump_buffer_elems(const Grid& g, int powell_q) const override {
+    // Powell: the normal-field jumps, or with the interpolated q-dagger the
+    // right cells' face values (the layout of the face buffer)
+    if (DIVB != POWELL) return 0;
+    return powell_q ? (size_t)D * C::NV * C::FP * g.ld : (size_t)D * 2 * C::FP * g.ld;
   }
   int nmodes() const override { return C::NMODES; }
 
@@ -2339,7 +2377,8 @@ struct LauncherImpl : Launcher {
     }
     using FT = FaceTile<T, D, DEG, DIVB>;
     dim3 grid((unsigned)((g.C + FT::TF - 1) / FT::TF), D);
-    k_face<T, D, DEG, DIVB><<<grid, FT::NT, 0, s>>>((const T*)w, (T*)ff, (T*)jp, tb, g, sc, sp.gamma);
+    k_face<T, D, DEG, DIVB><<<grid, FT::NT, 0, s>>>((const T*)w, (T*)ff, (T*)jp, tb, g, sc, sp.gamma,
+                                                     DIVB == POWELL && sp.powell_q ? 1 : 0);
   }
   int cell_variant = -1;  // -1: default
 
@@ -2458,7 +2497,9 @@ struct LauncherImpl : Launcher {
   void set_cell_variant(int v) override { cell_variant = v; }
   int get_cell_variant() const override { return cell_variant; }
   void cell(const void* w, const void* w0, void* out, const void* ff, const void* jp, const Grid& g, const Scal* sc,
-            const SchemeParams& sp, double a0, double b0, double cdt, int mode, hipStream_t s) override {
+            const SchemeParams& sp, double a0, double b0, double cdt, int mode_in, hipStream_t s) override {
+    // mode bit 1: the stage update; bit 2: interpolated Powell q-dagger
+    const int mode = mode_in | ((DIVB == POWELL && sp.powell_q) ? 2 : 0);
     int v = cell_variant;
     if (v < 0) v = DIVB == GLM ? 6 : 8;  // default: a matrix-core kernel
     if (!cell_variant_valid(v)) {

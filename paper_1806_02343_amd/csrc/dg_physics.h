@@ -198,9 +198,10 @@ __device__ __forceinline__ double signal_sum(const T* u, double gamma) {
 
 // HLLD in the face frame.  wl/wr: (rho, u, v, w, p, By, Bz); bx common normal
 // field.  Output flux of (rho, m_n, m_t1, m_t2, E, B_t1, B_t2) (the normal-B
-// flux is zero and not returned).
+// flux is zero and not returned).  st (may be null): the state of the fan
+// region that contains the face, x/t = 0, as (rho, u, v, w, By, Bz).
 template <typename T>
-__device__ __forceinline__ void hlld_flux(const T* wl, const T* wr, T bx, double gamma, T* out) {
+__device__ __forceinline__ void hlld_flux(const T* wl, const T* wr, T bx, double gamma, T* out, T* st = nullptr) {
   // divisions are products with reciprocals computed once (1/(gamma-1),
   // 1/rho per side, 1/den, 1/(S - S_M) per side)
   const T g = (T)gamma;
@@ -233,8 +234,19 @@ __device__ __forceinline__ void hlld_flux(const T* wl, const T* wr, T bx, double
   const T cmax = cfL > cfR ? cfL : cfR;
   const T SL = (uL < uR ? uL : uR) - cmax;
   const T SR = (uL > uR ? uL : uR) + cmax;
-  if (SL > T(0)) { for (int k = 0; k < 7; ++k) out[k] = FL[k]; return; }
-  if (SR <= T(0)) { for (int k = 0; k < 7; ++k) out[k] = FR[k]; return; }
+  auto state = [&](T r, T u, T v, T w, T by, T bz) {
+    if (st) { st[0] = r; st[1] = u; st[2] = v; st[3] = w; st[4] = by; st[5] = bz; }
+  };
+  if (SL > T(0)) {
+    for (int k = 0; k < 7; ++k) out[k] = FL[k];
+    state(wl[0], wl[1], wl[2], wl[3], wl[5], wl[6]);
+    return;
+  }
+  if (SR <= T(0)) {
+    for (int k = 0; k < 7; ++k) out[k] = FR[k];
+    state(wr[0], wr[1], wr[2], wr[3], wr[5], wr[6]);
+    return;
+  }
   const T dL = (SL - uL) * rL, dR = (SR - uR) * rR;
   const T iden = recip(dR - dL);
   const T SM = (dR * uR - dL * uL - ptR + ptL) * iden;
@@ -278,10 +290,12 @@ __device__ __forceinline__ void hlld_flux(const T* wl, const T* wr, T bx, double
   const T SsL = SM - fabs(bx) * iqL, SsR = SM + fabs(bx) * iqR;
   if (SsL > T(0)) {
     for (int k = 0; k < 7; ++k) out[k] = FL[k] + SL * (Us[0][k] - UL[k]);
+    state(rs[0], SM, vs[0], ws[0], bys[0], bzs[0]);
     return;
   }
   if (SsR <= T(0)) {
     for (int k = 0; k < 7; ++k) out[k] = FR[k] + SR * (Us[1][k] - UR[k]);
+    state(rs[1], SM, vs[1], ws[1], bys[1], bzs[1]);
     return;
   }
   const T s = bx >= T(0) ? T(1) : T(-1);
@@ -295,17 +309,22 @@ __device__ __forceinline__ void hlld_flux(const T* wl, const T* wr, T bx, double
     const T Ess = Es[0] - sqL * (vbs[0] - vbss) * s;
     const T Uss[7] = {rs[0], rs[0] * SM, rs[0] * vss, rs[0] * wss, Ess, byss, bzss};
     for (int k = 0; k < 7; ++k) out[k] = FL[k] + SL * (Us[0][k] - UL[k]) + SsL * (Uss[k] - Us[0][k]);
+    state(rs[0], SM, vss, wss, byss, bzss);
   } else {
     const T Ess = Es[1] + sqR * (vbs[1] - vbss) * s;
     const T Uss[7] = {rs[1], rs[1] * SM, rs[1] * vss, rs[1] * wss, Ess, byss, bzss};
     for (int k = 0; k < 7; ++k) out[k] = FR[k] + SR * (Us[1][k] - UR[k]) + SsR * (Uss[k] - Us[1][k]);
+    state(rs[1], SM, vss, wss, byss, bzss);
   }
 }
 
 // Numerical flux through a face with normal +e_a between traces uL and uR
-// (global components).  Writes F (NV components) and returns B^n_F.
+// (global components).  Writes F (NV components) and returns B^n_F.  vf, bf
+// (may be null): velocity and magnetic field of the HLLD interface state
+// (global components; its normal field is B^n_F).
 template <typename T, int NV, int A>
-__device__ __forceinline__ T face_flux_a(const T* uL, const T* uR, double gamma, T ch, T* F) {
+__device__ __forceinline__ T face_flux_a(const T* uL, const T* uR, double gamma, T ch, T* F, T* vf = nullptr,
+                                         T* bf = nullptr) {
   constexpr int n = A, t1 = (A + 1) % 3, t2 = (A + 2) % 3;
   T wl[7], wr[7];
   {
@@ -321,8 +340,12 @@ __device__ __forceinline__ T face_flux_a(const T* uL, const T* uR, double gamma,
   const T bnL = uL[5 + n], bnR = uR[5 + n];
   const T iL = rsqrt_nr(uL[0]), iR = rsqrt_nr(uR[0]);
   const T bnF = (bnL * iL + bnR * iR) * recip(iL + iR);
-  T fn[7];
-  hlld_flux<T>(wl, wr, bnF, gamma, fn);
+  T fn[7], st[6];
+  hlld_flux<T>(wl, wr, bnF, gamma, fn, vf ? st : nullptr);
+  if (vf) {
+    vf[n] = st[1]; vf[t1] = st[2]; vf[t2] = st[3];
+    bf[n] = bnF; bf[t1] = st[4]; bf[t2] = st[5];
+  }
   F[0] = fn[0];
   F[1 + n] = fn[1]; F[1 + t1] = fn[2]; F[1 + t2] = fn[3];
   F[4] = fn[4];
@@ -340,10 +363,34 @@ __device__ __forceinline__ T face_flux_a(const T* uL, const T* uR, double gamma,
 // The same with a run-time axis (one branch per axis, so that every component
 // index inside is a compile-time constant).
 template <typename T, int NV>
-__device__ __forceinline__ T face_flux(const T* uL, const T* uR, int a, double gamma, T ch, T* F) {
-  if (a == 0) return face_flux_a<T, NV, 0>(uL, uR, gamma, ch, F);
-  if (a == 1) return face_flux_a<T, NV, 1>(uL, uR, gamma, ch, F);
-  return face_flux_a<T, NV, 2>(uL, uR, gamma, ch, F);
+__device__ __forceinline__ T face_flux(const T* uL, const T* uR, int a, double gamma, T ch, T* F, T* vf = nullptr,
+                                       T* bf = nullptr) {
+  if (a == 0) return face_flux_a<T, NV, 0>(uL, uR, gamma, ch, F, vf, bf);
+  if (a == 1) return face_flux_a<T, NV, 1>(uL, uR, gamma, ch, F, vf, bf);
+  return face_flux_a<T, NV, 2>(uL, uR, gamma, ch, F, vf, bf);
+}
+
+// q-dagger of eq. powellq-interp for the side whose trace is u (conserved):
+// q integrated along the straight path in primitive variables from the
+// trace (v_s, B_s) to the interface state (v_F, B_F):
+// (0, (B_s + B_F)/2, (2 B_s.v_s + B_s.v_F + B_F.v_s + 2 B_F.v_F)/6, (v_s + v_F)/2).
+template <typename T>
+__device__ __forceinline__ void powell_q_interp(const T* u, const T* vf, const T* bf, T* q) {
+  const T ir = recip(u[0]);
+  const T vs[3] = {u[1] * ir, u[2] * ir, u[3] * ir};
+  const T bs[3] = {u[5], u[6], u[7]};
+  q[0] = T(0);
+  T ss = 0, sf = 0, fs = 0, ff_ = 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    q[1 + c] = T(0.5) * (bs[c] + bf[c]);
+    q[5 + c] = T(0.5) * (vs[c] + vf[c]);
+    ss += bs[c] * vs[c];
+    sf += bs[c] * vf[c];
+    fs += bf[c] * vs[c];
+    ff_ += bf[c] * vf[c];
+  }
+  q[4] = (T(2) * ss + sf + fs + T(2) * ff_) * T(1.0 / 6.0);
 }
 
 }  // namespace dgmhd

@@ -27,7 +27,8 @@ def test_library_exports_every_declared_symbol():
 
 
 def _params(**kw):
-    p = dict(dim=3, degree=2, divb=B.DG_GLM, precision=B.DG_FP64, rk_stages=3, limiter=0, gamma=5 / 3, cfl=0.3,
+    p = dict(dim=3, degree=2, divb=B.DG_GLM, precision=B.DG_FP64, rk_stages=3, limiter=0, powell_q=0,
+             gamma=5 / 3, cfl=0.3,
              cfl_glm=0.0, glm_cr=0.18, glm_ch_fixed=0.0, tvb_Mtilde=5.0, tvb_beta=2.0, tvb_eps=1e-8,
              eps_rho=1e-12, eps_p=1e-12, powell_eta=0.2, mlp_lo=0.0, mlp_hi=0.0)
     p.update(kw)
@@ -50,6 +51,8 @@ def _mesh(n=(4, 4, 4), box=(1.0, 1.0, 1.0), kind=B.DG_MESH_UNIFORM):
     (dict(cfl=1.5), {}, B.DG_EINVAL),
     (dict(gamma=1.0), {}, B.DG_EINVAL),
     (dict(dim=2, divb=B.DG_POWELL), {}, B.DG_EUNSUPPORTED),
+    (dict(powell_q=2, divb=B.DG_POWELL), {}, B.DG_EINVAL),
+    (dict(powell_q=1), {}, B.DG_EINVAL),
     ({}, dict(n=(4, 0, 4)), B.DG_EINVAL),
     ({}, dict(box=(1.0, 2.0, 1.0)), B.DG_EINVAL),
 ])
@@ -73,6 +76,6 @@ def test_null_handle_calls_return_einval():
 
 def test_struct_layouts_match_header():
     # field order and sizes of the ABI structs (6 int32 + 13 double, etc.)
-    assert ctypes.sizeof(B.dg_params) == 6 * 4 + 13 * 8
+    assert ctypes.sizeof(B.dg_params) == 7 * 4 + 4 + 13 * 8   # 7 int32, padding to the doubles
     assert ctypes.sizeof(B.dg_limit_stats) == 6 * 8 + 4 * 8
     assert ctypes.sizeof(B.dg_mesh) == 4 + 12 + 24 + 8 + 8 + 8

@@ -345,3 +345,46 @@ def test_ssp_rk4_fp32_matches_oracle():
     gpu.step(wg, 3)
     err = rel_l1(orc, to_cells(wg, orc.mesh.ncells), wo, ch=max(ch, 1.0))
     assert np.all(err < 1e-5), err
+
+
+@pytest.mark.parametrize("case", [(3, 1, 5, dg.POWELL), (3, 2, 6, dg.POWELL), (3, 3, 4, dg.POWELL)], ids=ids)
+def test_powell_interpolated_q_matches_oracle(case):
+    """Powell face term with the interpolated q-dagger (eq. powellq-interp,
+    HLLD interface state) on a state with normal-field jumps at every face:
+    the right-hand side of every cell-kernel variant and three SSP-RK3 steps
+    against the oracle, FP64 to 1e-12."""
+    from paper_1806_02343_amd import DG
+    D, d, n, divb = case
+    _announce("powell interp", case)
+    orc = dg.DG(dg.Mesh.uniform(D, n), d, divb=dg.POWELL, powell_q="interp")
+    rng = np.random.default_rng(88 + d)
+    wo = orc.project(dg.conserved_field(wl.Smooth(1000 * D + d, D), 5.0 / 3.0, orc.nvar))
+    nl = 5 * orc.n
+    wo[:, :nl] += 0.01 * rng.normal(size=(orc.mesh.ncells, nl)) * (np.arange(nl) % orc.n != 0)
+    wo[:, nl:] += 0.03 * rng.normal(size=(orc.mesh.ncells, orc.nldf))
+    gpu = DG(D, d, n, divb=dg.POWELL, powell_q=1)
+    wg = torch.as_tensor(orc.to_abi(wo, gpu.ld), device="cuda")
+    dt, ch, kappa = orc.timestep(wo)
+    r_o = orc.rhs(wo, ch, kappa)
+    ran = 0
+    for v in list(range(10)):
+        try:
+            gpu.autotune(wg, variant=v)
+        except Exception:
+            continue
+        out = gpu.empty_state()
+        gpu.rhs(wg, out, 0.0, 0.0)
+        torch.cuda.synchronize()
+        err = block_rel_max(to_cells(out, orc.mesh.ncells), r_o, orc)
+        assert np.all(err < 1e-12), (v, err)
+        ran += 1
+    assert ran >= 2
+    gpu.autotune(wg, variant=-1)
+    t_o = 0.0
+    for _ in range(3):
+        wo, dt, _, _ = orc.step(wo)
+        t_o += dt
+    t_g = gpu.step(wg, 3)
+    assert abs(t_g - t_o) <= 1e-12 * t_o
+    err = rel_l1(orc, to_cells(wg, orc.mesh.ncells), wo)
+    assert np.all(err < 1e-12), err

@@ -202,3 +202,71 @@ def test_hlld_resolves_isolated_rotational_discontinuity(wave, speed, bn):
     F, bnF = ph.numerical_flux(UL, UR, 0, G)
     expect = fL if speed > 0 else fR
     assert np.allclose(F[:, 0], expect, rtol=1e-13, atol=1e-13 * np.abs(expect).max())
+
+
+def test_powell_q_interp_is_the_path_integral_of_q():
+    """eq. powellq-interp: q integrated along the straight path in primitive
+    variables (v, B) from the trace to the interface state; a 3-point
+    Gauss-Legendre rule in the path parameter integrates the quadratic v.B
+    exactly."""
+    rng = np.random.default_rng(9)
+    U = random_states(rng, 30, glm=False)
+    vF = rng.uniform(-1, 1, (3, 30))
+    BF = rng.uniform(-1, 1, (3, 30))
+    q = ph.powell_q_interp(U, vF, BF)
+    v = U[1:4] / U[0]
+    Bv = U[5:8]
+    xs, ws = np.polynomial.legendre.leggauss(3)
+    acc = np.zeros_like(q)
+    for x, wgt in zip(xs, ws):
+        s = 0.5 * (x + 1.0)
+        vs = (1 - s) * v + s * vF
+        Bs = (1 - s) * Bv + s * BF
+        Us = ph.prim_to_cons(np.ones(30), vs, np.ones(30), Bs, G)
+        acc += 0.5 * wgt * ph.powell_q(Us)
+    assert np.allclose(q, acc, rtol=1e-14, atol=1e-14)
+    # no interface jump: q-dagger is q of the trace
+    assert np.allclose(ph.powell_q_interp(U, v, Bv), ph.powell_q(U), rtol=1e-14, atol=1e-15)
+
+
+@pytest.mark.parametrize("speed", [0.07, -0.05])
+def test_hlld_interface_state_of_a_rotational_discontinuity(speed):
+    """The fan state on the face: the left state when the isolated rotational
+    discontinuity moves right, the right state when it moves left."""
+    rho, p, bn = 1.3, 0.7, 0.8
+    sq = np.sqrt(rho)
+    un = speed + abs(bn) / sq          # left-going Alfven discontinuity moving at `speed`
+    btL = np.array([0.5, -0.35])
+    th = 1.1
+    btR = np.array([np.cos(th) * btL[0] - np.sin(th) * btL[1], np.sin(th) * btL[0] + np.cos(th) * btL[1]])
+    vtL = np.array([0.2, -0.1])
+    vtR = vtL + np.sign(bn) * (btR - btL) / sq
+    UL = ph.prim_to_cons(np.array([rho]), np.array([[un], [vtL[0]], [vtL[1]]]), np.array([p]),
+                         np.array([[bn], [btL[0]], [btL[1]]]), G)
+    UR = ph.prim_to_cons(np.array([rho]), np.array([[un], [vtR[0]], [vtR[1]]]), np.array([p]),
+                         np.array([[bn], [btR[0]], [btR[1]]]), G)
+    F, bnF, vF, BF = ph.numerical_flux(UL, UR, 0, G, state=True)
+    up = UL if speed > 0 else UR
+    assert np.allclose(vF[:, 0], up[1:4, 0] / up[0, 0], atol=1e-13)
+    assert np.allclose(BF[:, 0], up[5:8, 0], atol=1e-13)
+    # and the flux is that of the interface state
+    assert np.allclose(F[:, 0], ph.flux(up, 0, G)[:, 0], atol=1e-13)
+
+
+def test_hlld_interface_state_limits():
+    rng = np.random.default_rng(12)
+    U = random_states(rng, 40, glm=False)
+    F, bnF, vF, BF = ph.numerical_flux(U, U, 1, G, state=True)
+    assert np.allclose(vF, U[1:4] / U[0], rtol=1e-13, atol=1e-14)
+    assert np.allclose(BF, U[5:8], rtol=1e-13, atol=1e-14)
+    # supersonic flow to the right: the interface state is the left state (B_n set to B^n_F)
+    A, Bs = random_states(rng, 40, glm=False), random_states(rng, 40, glm=False)
+    for Ux in (A, Bs):
+        rho = Ux[0]
+        v = Ux[1:4] / rho
+        p = ph.pressure(Ux, G)
+        v[0] += 30.0
+        Ux[:] = ph.prim_to_cons(rho, v, p, Ux[5:8], G)
+    F, bnF, vF, BF = ph.numerical_flux(A, Bs, 0, G, state=True)
+    assert np.allclose(vF, A[1:4] / A[0], rtol=1e-14)
+    assert np.allclose(BF[1:], A[6:8], rtol=1e-14) and np.allclose(BF[0], bnF)

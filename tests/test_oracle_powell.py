@@ -112,7 +112,7 @@ class _Brute:
         return out
 
 
-def _brute_rhs_powell(d, n, w):
+def _brute_rhs_powell(d, n, w, interp=False):
     """R/M of eq. wdot with the Powell face term on an n^3 periodic grid of
     the unit box, written cell by cell: volume integral with the analytic
     flux, face fluxes of both faces of every axis with the outward normal,
@@ -150,12 +150,13 @@ def _brute_rhs_powell(d, n, w):
                 pout = np.insert(br.tpts, a, -side, axis=1)
                 Ui, Uo = br.state(w[cell], pin), br.state(w[idx(nb)], pout)
                 if side > 0:
-                    F, bnF = ph.numerical_flux(Ui, Uo, a, G)
+                    F, bnF, vF, BF = ph.numerical_flux(Ui, Uo, a, G, state=True)
                 else:
-                    F, bnF = ph.numerical_flux(Uo, Ui, a, G)
+                    F, bnF, vF, BF = ph.numerical_flux(Uo, Ui, a, G, state=True)
                 R[cell] -= side * (2 / h) * br.test_products(F, pin, br.tw)
                 jump = side * (bnF - Ui[ph.B1 + a])     # (B_F - B_K) . n
-                R[cell] -= (2 / h) * br.test_products(q[:, None] * jump[None, :], pin, br.tw)
+                qd = ph.powell_q_interp(Ui, vF, BF) if interp else q[:, None]
+                R[cell] -= (2 / h) * br.test_products(qd * jump[None, :], pin, br.tw)
     M = np.concatenate([np.tile(br.mleg, 5), br.mldf])
     return R / M[None, :]
 
@@ -170,12 +171,12 @@ def _perturbed_powell_state(s, seed):
     return w
 
 
-@pytest.mark.parametrize("d,n", [(1, 3), (2, 2)])
-def test_powell_rhs_matches_brute_force(d, n):
-    s = dg.DG(dg.Mesh.uniform(3, n), d, divb=dg.POWELL)
+@pytest.mark.parametrize("d,n,qmode", [(1, 3, "mean"), (2, 2, "mean"), (1, 3, "interp"), (2, 2, "interp")])
+def test_powell_rhs_matches_brute_force(d, n, qmode):
+    s = dg.DG(dg.Mesh.uniform(3, n), d, divb=dg.POWELL, powell_q=qmode)
     w = _perturbed_powell_state(s, 40 + d)
     r = s.rhs(w)
-    rb = _brute_rhs_powell(d, n, w)
+    rb = _brute_rhs_powell(d, n, w, interp=qmode == "interp")
     # the jumps are really there: the Powell part is a sizable share of R
     assert np.abs(rb).max() > 0.1
     assert np.allclose(r, rb, rtol=1e-12, atol=1e-12 * np.abs(rb).max())
@@ -276,3 +277,16 @@ def test_powell_dt_cap_binds_and_matches_hand_value():
     # with the paper's eta = 0.2 the same state is CFL-limited
     s2 = dg.DG(dg.Mesh.uniform(3, n), d, divb=dg.POWELL)
     assert math.isclose(s2.timestep(w)[0], min(dt_cfl, cap * 0.2 / eta), rel_tol=1e-12)
+
+
+def test_interpolated_q_differs_from_the_mean_and_conserves_mass():
+    s = dg.DG(dg.Mesh.uniform(3, 3), 1, divb=dg.POWELL)
+    si = dg.DG(dg.Mesh.uniform(3, 3), 1, divb=dg.POWELL, powell_q="interp")
+    w = _perturbed_powell_state(s, 5)
+    r, ri = s.rhs(w), si.rhs(w)
+    vol = s.mesh.h ** 3
+    assert abs((ri[:, 0] * vol).sum()) < 1e-13
+    # the two q-daggers give different Powell terms in momentum and energy
+    assert np.abs(ri[:, s.n:5 * s.n] - r[:, s.n:5 * s.n]).max() > 1e-3 * np.abs(r).max()
+    # and the same fluxes: the mass equation is untouched
+    assert np.allclose(ri[:, :s.n], r[:, :s.n], rtol=0, atol=1e-13 * np.abs(r[:, :s.n]).max())
