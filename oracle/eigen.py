@@ -20,6 +20,13 @@ as^2 = (c_f^2 - a^2)/(c_f^2 - c_s^2) (af = 1, as = 0 when c_f = c_s).
 Conserved right eigenvectors are dU/dW times these; the left eigenvectors are
 the matrix inverse.  Under GLM cleaning the (B_n, psi) pair adds the exact
 block r = (1, +- c_h), l = (1, +- 1/c_h)/2 (eigenvalues +- c_h).
+
+Powell scheme (8 waves, Sec. 4.1.3): with the source term the normal field
+obeys dB_n/dt + u dB_n/dx = 0 and no other primitive equation contains
+dB_n/dx, so in primitive variables B_n is a decoupled advected quantity, the
+divergence wave lambda = u.  Its conserved right eigenvector is dU/dW e_{B_n}
+= (0, 0, 0, 0, B_n, 1, 0, 0) in the frame order (rho, m_n, m_t1, m_t2, E,
+B_n, B_t1, B_t2); the other seven are the 7-wave vectors with B_n component 0.
 """
 import numpy as np
 
@@ -94,7 +101,8 @@ def frame_permutation(a):
 
 def char_matrices(ubar, a, gamma, ch, nvar=9):
     """(L, R) in global conserved components for normal axis a at the state
-    ubar (nvar = 9: 7-wave MHD block + GLM pair; L R = I)."""
+    ubar (nvar = 9: 7-wave MHD block + GLM pair; nvar = 8: the Powell 8-wave
+    system; L R = I)."""
     perm = frame_permutation(a)[:nvar]
     uf = ubar[perm]
     rho = uf[0]
@@ -112,7 +120,11 @@ def char_matrices(ubar, a, gamma, ch, nvar=9):
         Rf[np.ix_(IDXG, IDXG)] = [[1.0, 1.0], [ch, -ch]]
         Lf[np.ix_(IDXG, IDXG)] = [[0.5, 0.5 / ch], [0.5, -0.5 / ch]]
     else:
-        Rf[5, 5] = Lf[5, 5] = 1.0
+        # Powell divergence wave: r = (0, 0, 0, 0, B_n, 1, 0, 0); L = R^-1 block-wise
+        Rf[5, 5] = 1.0
+        Rf[4, 5] = bn
+        Lf[5, 5] = 1.0
+        Lf[IDX7, 5] = -L7[:, 4] * bn
     # back to global component order
     P = np.zeros((nvar, nvar))
     for i, g in enumerate(perm):

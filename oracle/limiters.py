@@ -45,8 +45,11 @@ def tvb_sigma(a, dl, dr, Mtilde, h, beta):
 
 
 def slope_limit(s, w, Mtilde=5.0, beta=2.0, eps=1e-8, characteristic=True, ch=1.0):
-    """TVB (characteristic) slope limiter on a uniform grid (GLM, Legendre
-    basis).  Returns (w_new, troubled flags)."""
+    """TVB (characteristic) slope limiter on a uniform grid.  GLM: Legendre
+    basis, 9 variables.  Powell: the LDF magnetic field (slope_limit_powell).
+    Returns (w_new, troubled flags)."""
+    if s.divb == POWELL:
+        return slope_limit_powell(s, w, Mtilde, beta, eps, characteristic)
     assert s.divb == GLM
     D, n = s.D, s.n
     C = w.shape[0]
@@ -83,6 +86,81 @@ def slope_limit(s, w, Mtilde=5.0, beta=2.0, eps=1e-8, characteristic=True, ch=1.
             out[sel, v * n + 1 + a] = sig_cons[v, sel]
     hi = [v * n + l for v in range(9) for l in range(D + 1, n)]
     out[np.ix_(troubled, hi)] = 0.0
+    return out, troubled
+
+
+def ldf_moments(s):
+    """For each LDF function l and component c: its cell average (Pm[c, l])
+    and its linear coefficient along xi_b, <Phi_lc, xi_b>/<xi_b, xi_b>
+    (Pl[c, b, l]), by the (d+2)-point rule (exact: degree <= d + 1)."""
+    from .quadrature import tensor_rule
+    xq, wq = tensor_rule(s.d + 2, s.D)
+    from . import basis as Bm
+    Phi = Bm.ldf_values(s.D, s.d, xq)                      # [c, q, l]
+    vol = 2.0 ** s.D
+    Pm = np.einsum("q,cql->cl", wq, Phi) / vol
+    Pl = np.einsum("q,qb,cql->cbl", wq, xq, Phi) / (vol / 3.0)
+    return Pm, Pl
+
+
+def slope_limit_powell(s, w, Mtilde=5.0, beta=2.0, eps=1e-8, characteristic=True):
+    """TVB slope limiter for the Powell scheme (Sec. 4.2.1-4.2.2, 4.2.4).
+    Per cell and direction b the 8-component slope (rho, m, E and the linear
+    coefficients S[c, b] of the LDF magnetic field) and the neighbour mean
+    differences go to the 8-wave characteristic variables (eigen, nvar = 8)
+    and are limited as in slope_limit.  A troubled cell: rho, m, E take the
+    limited slopes of the triggered directions and lose their modes of degree
+    >= 2; the magnetic field becomes the linear field mean + S' xi, S' the
+    limited slope matrix with its diagonal made divergence-free by the
+    delta+- rescaling (ldf_divfree_fix), L2-projected onto the LDF basis
+    (exact: a divergence-free linear field)."""
+    D, n = s.D, s.n
+    C = w.shape[0]
+    h = s.mesh.h
+    means = s.cell_means(w)                                 # [8, C]
+    nl = len(s.leg_vars) * n
+    wb = w[:, nl:]
+    Pm, Pl = ldf_moments(s)
+    S = np.einsum("cbl,kl->kcb", Pl, wb)                    # [C, c, b] magnetic slopes
+    out = w.copy()
+    troubled = np.zeros(C, dtype=bool)
+    new_slopes = {}
+    for a in range(D):
+        up = s.mesh.neighbor(a, +1)
+        dn = s.mesh.neighbor(a, -1)
+        slope = np.zeros((8, C))
+        for j, v in enumerate(s.leg_vars):
+            slope[v] = w[:, j * n + 1 + a]
+        for c in range(D):
+            slope[ph.B1 + c] = S[:, c, a]
+        dl = 0.5 * (means[:, up] - means)
+        dr = 0.5 * (means - means[:, dn])
+        sig_cons = np.empty_like(slope)
+        trig = np.zeros(C, dtype=bool)
+        for k in range(C):
+            if characteristic:
+                L, R = eigen.char_matrices(means[:, k], a, s.gamma, None, nvar=8)
+            else:
+                L = R = np.eye(8)
+            ca, cl, cr = L @ slope[:, k], L @ dl[:, k], L @ dr[:, k]
+            sig = tvb_sigma(ca, cl, cr, Mtilde, h[k], beta)
+            t = np.abs(sig - ca) > eps
+            trig[k] = t.any()
+            sig_cons[:, k] = R @ np.where(t, sig, ca)
+        new_slopes[a] = (trig, sig_cons)
+        troubled |= trig
+    for a in range(D):
+        trig, sig_cons = new_slopes[a]
+        sel = troubled & trig
+        for j, v in enumerate(s.leg_vars):
+            out[sel, j * n + 1 + a] = sig_cons[v, sel]
+        for c in range(D):
+            S[sel, c, a] = sig_cons[ph.B1 + c, sel]
+    hi = [j * n + l for j in range(len(s.leg_vars)) for l in range(D + 1, n)]
+    out[np.ix_(troubled, hi)] = 0.0
+    for k in np.nonzero(troubled)[0]:
+        Sk = ldf_divfree_fix(S[k])
+        out[k, nl:] = ldf_project_linear(s, means[ph.B1:ph.B1 + D, k], Sk)
     return out, troubled
 
 

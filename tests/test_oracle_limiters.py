@@ -195,3 +195,106 @@ def test_ldf_projection_of_divfree_linear_field_is_exact():
     Phi = Bb.ldf_values(3, 2, xq)
     Bq = np.einsum("cpl,l->cp", Phi, wl_)
     assert np.allclose(Bq, Bm[:, None] + S @ xq.T, atol=1e-13)
+
+
+def _fd_jacobian_powell(u8, a):
+    """A = dF/dU + q(U) e_{B_n}^T in the frame order (rho, m_n, m_t1, m_t2, E,
+    B_n, B_t1, B_t2): the flux Jacobian along a with B_n a variable, plus the
+    Powell source -q dB_n/dx written as a transport term (Sec. 4.1.3,
+    eq. powell-src with q of eq. powell-q)."""
+    perm = eigen.frame_permutation(a)[:8]
+
+    def F8(uf):
+        ug = np.zeros(8)
+        ug[perm] = uf
+        return ph.flux(ug[:, None], a, G)[:, 0][perm]
+    uf = u8[perm]
+    J = np.zeros((8, 8))
+    for k in range(8):
+        e = np.zeros(8)
+        hh = 1e-6 * max(1.0, abs(uf[k]))
+        e[k] = hh
+        J[:, k] = (F8(uf + e) - F8(uf - e)) / (2 * hh)
+    q = ph.powell_q(u8[:, None])[:, 0][perm]
+    J[:, 5] += q
+    return J
+
+
+@pytest.mark.parametrize("kind", ["generic", "bt_zero", "bn_zero", "triple"])
+def test_powell_eight_wave_system_diagonalises_the_powell_jacobian(kind):
+    """Powell scheme (f1 of the scope): L A R = diag(lambda) with A the
+    Jacobian of the Powell system and the eigenvalues u - c_f <= u - c_a <=
+    u - c_s <= u <= u + c_s <= u + c_a <= u + c_f plus the divergence wave u."""
+    rng = np.random.default_rng({"generic": 11, "bt_zero": 12, "bn_zero": 13, "triple": 14}[kind])
+    for _ in range(4):
+        rho, v, p, B = rng.uniform(0.5, 2), rng.uniform(-1, 1, 3), rng.uniform(0.1, 2), rng.uniform(-1, 1, 3)
+        for a in range(3):
+            BB = B.copy()
+            n, t1, t2 = ph.face_frame(a)
+            if kind == "bt_zero":
+                BB[t1] = BB[t2] = 0.0
+            if kind == "bn_zero":
+                BB[n] = 0.0
+            if kind == "triple":
+                BB[t1] = BB[t2] = 0.0
+                BB[n] = np.sqrt(G * p)
+            u = ph.prim_to_cons(np.array(rho), v, np.array(p), BB, G)
+            L, R = eigen.char_matrices(u, a, G, None, nvar=8)
+            assert np.abs(L @ R - np.eye(8)).max() < 1e-12
+            perm = eigen.frame_permutation(a)[:8]
+            A = _fd_jacobian_powell(u, a)
+            Dm = L[:, perm] @ A @ R[perm, :]
+            off = Dm - np.diag(np.diag(Dm))
+            assert np.abs(off).max() < 1e-7 * max(1.0, np.abs(Dm).max())
+            lam = np.diag(Dm)
+            un = v[n]
+            # the divergence wave (B_n column of the frame) travels with the flow
+            assert abs(lam[perm.index(ph.B1 + n)] - un) < 1e-7
+            waves = np.sort(np.delete(lam, perm.index(ph.B1 + n)))
+            assert abs(waves[3] - un) < 1e-7 and np.all(np.diff(waves) > -1e-7)
+
+
+def _powell_blast(n=8, d=2, seed=2000):
+    s = dg.DG(dg.Mesh.uniform(3, n), d, divb=dg.POWELL)
+    w = s.project(dg.conserved_field(wl.Blast(seed), G, 8))
+    return s, w
+
+
+def test_powell_slope_limiter_invariants():
+    """Powell + LDF limiting (Sec. 4.2.4): means unchanged; every troubled cell
+    leaves a divergence-free linear magnetic field (its LDF weights are those
+    of a linear field whose diagonal slopes sum to zero, up to rounding); cells
+    not troubled are bitwise unchanged; linear data is left alone."""
+    s, w = _powell_blast()
+    w2, tr = limiters.slope_limit(s, w)
+    assert tr.any() and not tr.all()
+    assert np.array_equal(w2[~tr], w[~tr])
+    m1, m2 = s.cell_means(w), s.cell_means(w2)
+    assert np.allclose(m1, m2, rtol=0, atol=1e-13 * np.abs(m1).max())
+    Pm, Pl = limiters.ldf_moments(s)
+    nl = len(s.leg_vars) * s.n
+    for k in np.nonzero(tr)[0]:
+        S = np.einsum("cbl,l->cb", Pl, w2[k, nl:])
+        assert abs(np.trace(S)) < 1e-12 * max(1.0, np.abs(S).max())
+        # the limited field is linear: reprojecting its linear part gives it back
+        back = limiters.ldf_project_linear(s, m2[ph.B1:ph.B1 + 3, k], S)
+        assert np.allclose(back, w2[k, nl:], rtol=0, atol=1e-12 * max(1.0, np.abs(back).max()))
+        # Legendre variables: no modes of degree >= 2 left
+        for j in range(5):
+            assert np.all(w2[k, j * s.n + 4:(j + 1) * s.n] == 0.0)
+    # a linear state (every variable and the field linear, divergence-free) is not limited
+    lin = np.array([1.2, 0.1, -0.2, 0.05, 3.0, 0.4, -0.3, 0.2])
+    grad = np.array([[0.01, 0, 0], [0, 0.01, 0], [0, 0, 0.0], [0.0, 0, 0.01], [0.02, 0.01, 0],
+                     [0.01, 0.02, 0], [0.03, -0.01, 0], [0, 0.01, 0.0]])   # field rows: trace zero
+
+    def field(x):
+        U = lin[:, None] + grad @ (x.T - 0.5)
+        return {"rho": U[0], "v": [U[1] / U[0], U[2] / U[0], U[3] / U[0]], "p": np.full(x.shape[0], 1.0),
+                "B": [U[5], U[6], U[7]]}
+    s2 = dg.DG(dg.Mesh.uniform(3, 4, box=1.0), 1, divb=dg.POWELL)
+    # a non-periodic linear field would jump at the box edge: keep it to the interior cells
+    wl_ = s2.project(dg.conserved_field(field, G, 8))
+    w3, tr3 = limiters.slope_limit(s2, wl_, Mtilde=0.0)
+    ijk = [(np.arange(64) // 4 ** a) % 4 for a in range(3)]
+    interior = np.all([(c >= 1) & (c <= 2) for c in ijk], axis=0)
+    assert not tr3[interior].any()
