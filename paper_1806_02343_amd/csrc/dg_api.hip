@@ -283,8 +283,6 @@ int dg_init(const dg_params* p, const dg_mesh* m, void* hip_stream, dg_handle* o
     return fail(nullptr, DG_EINVAL, "powell_q selects the Powell scheme's q-dagger: divb must be DG_POWELL");
   if (p->limiter & ~(DG_LIM_TVB | DG_LIM_CHAR | DG_LIM_POS | DG_LIM_LEARNED))
     return fail(nullptr, DG_EINVAL, "unknown limiter flags");
-  if ((p->limiter & DG_LIM_TVB) && p->divb == DG_POWELL)
-    return fail(nullptr, DG_EUNSUPPORTED, "slope limiter with the Powell/LDF basis not built");
   if ((p->limiter & (DG_LIM_CHAR | DG_LIM_LEARNED)) && !(p->limiter & DG_LIM_TVB))
     return fail(nullptr, DG_EINVAL, "characteristic/learned flags need DG_LIM_TVB");
   if ((p->limiter & DG_LIM_LEARNED) && (p->divb != DG_GLM || m->kind != DG_MESH_UNIFORM))

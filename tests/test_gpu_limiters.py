@@ -83,6 +83,45 @@ def test_limited_steps_fp32_error_stated():
     assert np.all(err < 1e-5), err
 
 
+@pytest.mark.parametrize("d,n,lim", [(2, 8, 7), (2, 8, 5), (1, 8, 7), (3, 6, 7), (2, 8, 1)])
+def test_powell_limit_matches_oracle(d, n, lim):
+    """Powell scheme with the LDF field (Sec. 4.2.4): 8-wave characteristic
+    (or componentwise) TVB decisions, limited Legendre slopes, the
+    divergence-free re-projected field and positivity against the oracle."""
+    _announce("powell limit", d, n, lim)
+    gpu, wg, orc, wo = make_pair(3, d, n, dg.POWELL, field=wl.Blast(2000), limiter=lim)
+    st_o = {}
+    wo2 = limiters.make_stage_limiter(orc, lim, stats=st_o)(wo)
+    st_g = gpu.limit(wg, stats=True)
+    wg2 = to_cells(wg, orc.mesh.ncells)
+    assert st_o["n_tvb"] > 0
+    assert st_g["n_tvb_triggered"] == st_o["n_tvb"]
+    assert st_g["n_pos_scaled"] == st_o.get("n_pos_scaled", 0)
+    err = block_rel_max(wg2, wo2, orc)
+    assert np.all(err < 1e-12), err
+    # every troubled cell carries a divergence-free linear field (positivity
+    # scales it about its mean, which keeps it so)
+    _, troubled = limiters.slope_limit(orc, wo, characteristic=bool(lim & 2))
+    Pm, Pl = limiters.ldf_moments(orc)
+    nl = len(orc.leg_vars) * orc.n
+    S = np.einsum("cbl,kl->kcb", Pl, wg2[troubled, nl:])
+    tr = np.abs(np.trace(S, axis1=1, axis2=2))
+    assert np.all(tr < 1e-12 * np.maximum(1.0, np.abs(S).max(axis=(1, 2)))), tr.max()
+
+
+def test_powell_limited_steps_match_oracle():
+    _announce("powell limited steps")
+    gpu, wg, orc, wo = make_pair(3, 2, 8, dg.POWELL, field=wl.Blast(2000), limiter=7)
+    olim = limiters.make_stage_limiter(orc, 7)
+    wo = olim(wo)
+    gpu.limit(wg)
+    for _ in range(3):
+        wo, dt, ch, k = orc.step(wo, limiter=olim)
+    gpu.step(wg, 3)
+    err = rel_l1(orc, to_cells(wg, orc.mesh.ncells), wo)
+    assert np.all(err < 1e-12), err
+
+
 @pytest.mark.parametrize("D,d,precision", [(3, 3, 0), (3, 2, 0), (3, 3, 1), (2, 3, 0)])
 def test_positivity_near_floors_matches_oracle(D, d, precision):
     """Positivity limiter on states built around the floors, in tiles of 16
