@@ -265,7 +265,6 @@ int dg_init(const dg_params* p, const dg_mesh* m, void* hip_stream, dg_handle* o
   if (p->dim != 2 && p->dim != 3) return fail(nullptr, DG_EINVAL, "dim must be 2 or 3");
   if (p->degree < 1 || p->degree > 3) return fail(nullptr, DG_EUNSUPPORTED, "degree must be 1..3");
   if (p->divb != DG_GLM && p->divb != DG_POWELL) return fail(nullptr, DG_EINVAL, "unknown divb");
-  if (p->divb == DG_POWELL && p->dim != 3) return fail(nullptr, DG_EUNSUPPORTED, "Powell/LDF is built for 3-D");
   if (p->precision != DG_FP64 && p->precision != DG_FP32) return fail(nullptr, DG_EINVAL, "unknown precision");
   if (p->rk_stages != 1 && p->rk_stages != 2 && p->rk_stages != 3 && p->rk_stages != 5)
     return fail(nullptr, DG_EUNSUPPORTED, "rk_stages must be 1, 2, 3 (SSP-RK of that order) or 5 (SSP-RK(5,4))");

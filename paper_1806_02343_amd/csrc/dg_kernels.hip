@@ -2613,7 +2613,8 @@ Launcher* make_launcher(int precision, int D, int d, int divb) {
   if (D == DD && d == DEG && divb == DIV) return new LauncherImpl<T, DD, DEG, DIV>();
 #define ALL(T)                                                                               \
   CASE(T, 2, 1, GLM) CASE(T, 2, 2, GLM) CASE(T, 2, 3, GLM) CASE(T, 3, 1, GLM) CASE(T, 3, 2, GLM) \
-  CASE(T, 3, 3, GLM) CASE(T, 3, 1, POWELL) CASE(T, 3, 2, POWELL) CASE(T, 3, 3, POWELL)
+  CASE(T, 3, 3, GLM) CASE(T, 2, 1, POWELL) CASE(T, 2, 2, POWELL) CASE(T, 2, 3, POWELL) CASE(T, 3, 1, POWELL)     \
+  CASE(T, 3, 2, POWELL) CASE(T, 3, 3, POWELL)
   if (precision == 0) { ALL(double) }
   else { ALL(float) }
 #undef ALL

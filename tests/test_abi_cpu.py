@@ -50,7 +50,7 @@ def _mesh(n=(4, 4, 4), box=(1.0, 1.0, 1.0), kind=B.DG_MESH_UNIFORM):
     (dict(rk_stages=6), {}, B.DG_EUNSUPPORTED),
     (dict(cfl=1.5), {}, B.DG_EINVAL),
     (dict(gamma=1.0), {}, B.DG_EINVAL),
-    (dict(dim=2, divb=B.DG_POWELL), {}, B.DG_EUNSUPPORTED),
+    (dict(dim=4), {}, B.DG_EINVAL),
     (dict(powell_q=2, divb=B.DG_POWELL), {}, B.DG_EINVAL),
     (dict(powell_q=1), {}, B.DG_EINVAL),
     ({}, dict(n=(4, 0, 4)), B.DG_EINVAL),

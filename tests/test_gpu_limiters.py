@@ -83,13 +83,23 @@ def test_limited_steps_fp32_error_stated():
     assert np.all(err < 1e-5), err
 
 
-@pytest.mark.parametrize("d,n,lim", [(2, 8, 7), (2, 8, 5), (1, 8, 7), (3, 6, 7), (2, 8, 1)])
-def test_powell_limit_matches_oracle(d, n, lim):
+def _blast(D):
+    """The 3-D blast input, or its z = 0.5 slice in 2-D."""
+    if D == 3:
+        return wl.Blast(2000)
+    base = wl.Blast(2001)
+    return lambda x: base(np.concatenate([x, np.full((x.shape[0], 1), 0.5)], 1) if isinstance(x, np.ndarray) else
+                          torch.cat([x, torch.full_like(x[:, :1], 0.5)], 1))
+
+
+@pytest.mark.parametrize("D,d,n,lim", [(3, 2, 8, 7), (3, 2, 8, 5), (3, 1, 8, 7), (3, 3, 6, 7), (3, 2, 8, 1),
+                                       (2, 2, 20, 7), (2, 3, 16, 7), (2, 1, 24, 5)])
+def test_powell_limit_matches_oracle(D, d, n, lim):
     """Powell scheme with the LDF field (Sec. 4.2.4): 8-wave characteristic
     (or componentwise) TVB decisions, limited Legendre slopes, the
     divergence-free re-projected field and positivity against the oracle."""
-    _announce("powell limit", d, n, lim)
-    gpu, wg, orc, wo = make_pair(3, d, n, dg.POWELL, field=wl.Blast(2000), limiter=lim)
+    _announce("powell limit", D, d, n, lim)
+    gpu, wg, orc, wo = make_pair(D, d, n, dg.POWELL, field=_blast(D), limiter=lim)
     st_o = {}
     wo2 = limiters.make_stage_limiter(orc, lim, stats=st_o)(wo)
     st_g = gpu.limit(wg, stats=True)
@@ -109,9 +119,10 @@ def test_powell_limit_matches_oracle(d, n, lim):
     assert np.all(tr < 1e-12 * np.maximum(1.0, np.abs(S).max(axis=(1, 2)))), tr.max()
 
 
-def test_powell_limited_steps_match_oracle():
-    _announce("powell limited steps")
-    gpu, wg, orc, wo = make_pair(3, 2, 8, dg.POWELL, field=wl.Blast(2000), limiter=7)
+@pytest.mark.parametrize("D,d,n", [(3, 2, 8), (2, 2, 20)])
+def test_powell_limited_steps_match_oracle(D, d, n):
+    _announce("powell limited steps", D, d, n)
+    gpu, wg, orc, wo = make_pair(D, d, n, dg.POWELL, field=_blast(D), limiter=7)
     olim = limiters.make_stage_limiter(orc, 7)
     wo = olim(wo)
     gpu.limit(wg)

@@ -23,6 +23,9 @@ CASES = [
     (3, 3, 5, dg.GLM),
     (3, 1, 5, dg.POWELL),
     (3, 2, 6, dg.POWELL),
+    (2, 1, 16, dg.POWELL),
+    (2, 2, 12, dg.POWELL),
+    (2, 3, 9, dg.POWELL),
 ]
 
 
@@ -147,7 +150,7 @@ def test_step_is_deterministic():
 
 
 VARIANT_CASES = [(3, 2, 6, dg.GLM), (3, 3, 5, dg.GLM), (3, 1, 7, dg.GLM), (3, 2, 6, dg.POWELL), (2, 2, 12, dg.GLM),
-                 (2, 3, 9, dg.GLM), (2, 1, 11, dg.GLM)]
+                 (2, 3, 9, dg.GLM), (2, 1, 11, dg.GLM), (2, 2, 12, dg.POWELL), (2, 3, 9, dg.POWELL)]
 
 
 @pytest.mark.parametrize("case", VARIANT_CASES, ids=ids)
@@ -240,18 +243,19 @@ def test_schedule_pairs_face_flux_layouts():
     assert ((chosen >> 4) >= 1) == ((chosen & 15) >= 4), chosen
 
 
-def test_powell_dt_cap_binds_matches_oracle():
+@pytest.mark.parametrize("D,d,n", [(3, 2, 6), (2, 2, 12)])
+def test_powell_dt_cap_binds_matches_oracle(D, d, n):
     """Powell time-step cap (eq. powell_dt with |div B|_K from the face jumps of
     eq. divb-cell) on a state with O(0.1) normal-field jumps at every face and
     a small eta, so that the cap and not eq. cfl sets the step: dg_dt and two
     SSP-RK3 steps against the oracle."""
     from paper_1806_02343_amd import DG
-    _announce("powell cap")
-    D, d, n, eta = 3, 2, 6, 1e-6
+    _announce("powell cap", D, d, n)
+    eta = 1e-6
     orc = dg.DG(dg.Mesh.uniform(D, n), d, divb=dg.POWELL, powell_eta=eta)
     rng = np.random.default_rng(77)
     wo = orc.project(dg.conserved_field(wl.Smooth(1000 * D + d, D), 5.0 / 3.0, orc.nvar))
-    nl = 5 * orc.n
+    nl = len(orc.leg_vars) * orc.n
     wo[:, :nl] += 0.02 * rng.normal(size=(orc.mesh.ncells, nl)) * (np.arange(nl) % orc.n != 0)
     wo[:, nl:] += 0.05 * rng.normal(size=(orc.mesh.ncells, orc.nldf))
     gpu = DG(D, d, n, divb=dg.POWELL, powell_eta=eta)
@@ -347,7 +351,8 @@ def test_ssp_rk4_fp32_matches_oracle():
     assert np.all(err < 1e-5), err
 
 
-@pytest.mark.parametrize("case", [(3, 1, 5, dg.POWELL), (3, 2, 6, dg.POWELL), (3, 3, 4, dg.POWELL)], ids=ids)
+@pytest.mark.parametrize("case", [(3, 1, 5, dg.POWELL), (3, 2, 6, dg.POWELL), (3, 3, 4, dg.POWELL),
+                                  (2, 2, 10, dg.POWELL)], ids=ids)
 def test_powell_interpolated_q_matches_oracle(case):
     """Powell face term with the interpolated q-dagger (eq. powellq-interp,
     HLLD interface state) on a state with normal-field jumps at every face:
@@ -359,7 +364,7 @@ def test_powell_interpolated_q_matches_oracle(case):
     orc = dg.DG(dg.Mesh.uniform(D, n), d, divb=dg.POWELL, powell_q="interp")
     rng = np.random.default_rng(88 + d)
     wo = orc.project(dg.conserved_field(wl.Smooth(1000 * D + d, D), 5.0 / 3.0, orc.nvar))
-    nl = 5 * orc.n
+    nl = len(orc.leg_vars) * orc.n
     wo[:, :nl] += 0.01 * rng.normal(size=(orc.mesh.ncells, nl)) * (np.arange(nl) % orc.n != 0)
     wo[:, nl:] += 0.03 * rng.normal(size=(orc.mesh.ncells, orc.nldf))
     gpu = DG(D, d, n, divb=dg.POWELL, powell_q=1)
