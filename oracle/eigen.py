@@ -37,15 +37,29 @@ def primitive_right_eigenvectors(rho, u, p, bn, bt1, bt2, gamma):
     """7x7 right eigenvectors (columns) in primitive variables and eigenvalues."""
     a2 = gamma * p / rho
     bt2sq = bt1 * bt1 + bt2 * bt2
-    b2 = (bn * bn + bt2sq) / rho
     ca2 = bn * bn / rho
-    disc = max((a2 + b2) ** 2 - 4.0 * a2 * ca2, 0.0)
-    cf2 = 0.5 * (a2 + b2 + np.sqrt(disc))
-    cs2 = max(0.5 * (a2 + b2 - np.sqrt(disc)), 0.0)
+    tt = bt2sq / rho                       # tangential Alfven term, b^2 = c_a^2 + tt
+    b2 = ca2 + tt
+    # every quantity below is formed without cancellation, so that states
+    # near the degenerate points (B_t -> 0, c_a -> 0) give eigenvectors that
+    # are continuous at rounding level, not at the square root of it:
+    #   (c_f^2 - c_s^2)^2 = (a^2 - c_a^2)^2 + tt (2 (a^2 + c_a^2) + tt)
+    #   c_f^2 c_s^2 = a^2 c_a^2
+    #   x = c_f^2 - a^2 and y = a^2 - c_s^2 have x + y = c_f^2 - c_s^2 and
+    #   x y = a^2 tt; the larger of the two is a sum of non-negative terms
+    dd = np.sqrt((a2 - ca2) ** 2 + tt * (2.0 * (a2 + ca2) + tt))
+    cf2 = 0.5 * (a2 + b2 + dd)
+    cs2 = a2 * ca2 / cf2
     cf, cs, ca, a = np.sqrt(cf2), np.sqrt(cs2), np.sqrt(ca2), np.sqrt(a2)
-    if cf2 - cs2 > 1e-12 * cf2:
-        af = np.sqrt(min(max((a2 - cs2) / (cf2 - cs2), 0.0), 1.0))
-        as_ = np.sqrt(min(max((cf2 - a2) / (cf2 - cs2), 0.0), 1.0))
+    if dd > 1e-12 * cf2:
+        if b2 >= a2:
+            x = 0.5 * (b2 - a2 + dd)
+            y = a2 * tt / x
+        else:
+            y = 0.5 * (a2 - b2 + dd)
+            x = a2 * tt / y
+        af = np.sqrt(min(max(y / dd, 0.0), 1.0))
+        as_ = np.sqrt(min(max(x / dd, 0.0), 1.0))
     else:
         af, as_ = 1.0, 0.0
     bt = np.sqrt(bt2sq)

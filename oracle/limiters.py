@@ -19,9 +19,11 @@ on the cell averages (tallied), then w <- tau w + (1 - tau) w_mean with tau
 the smallest of (rho_bar - eps)/(rho_bar - rho_q) over points with
 rho_q < eps and (p_bar - eps)/(p_bar - p_q) over points with p_q < eps,
 over all volume and face quadrature points.  Reading: p_q only counts where
-rho_q > 0; a second pass is made if the first one leaves any point below
-half the floors (rounding at the floor level after the first pass is not
-re-limited).
+rho_q > 0; a point counts only where it lies below the mean (the ratio is
+taken where its denominator is positive) and tau is clipped to [0, 1], so a
+cell whose mean sits at the floor collapses to its mean; a second pass is
+made if the first one leaves any point below half the floors (rounding at
+the floor level after the first pass is not re-limited).
 """
 import numpy as np
 
@@ -42,6 +44,19 @@ def minmod(a, b, c):
 def tvb_sigma(a, dl, dr, Mtilde, h, beta):
     """Limited slope of eq. tvb-limiter with M = M~/h."""
     return np.where(np.abs(a) <= Mtilde * h, a, minmod(a, beta * dl, beta * dr))
+
+
+def char_usable(ubar, gamma, rel=1e-8):
+    """Whether the characteristic matrices at the cell mean ubar are used
+    (Sec. 4.2.2).  Their condition number grows like b^2/a^2 (Alfven over
+    sound speed squared), so near the positivity floor in a strong field the
+    projection carries no accurate digit; the paper does not treat this
+    case.  Reading: such a cell (gamma p < rel (gamma p + |B|^2), or a
+    non-positive density or pressure) is limited componentwise."""
+    rho = ubar[ph.RHO]
+    gp = gamma * ph.pressure(ubar, gamma)
+    B2 = ubar[ph.B1] ** 2 + ubar[ph.B2] ** 2 + ubar[ph.B3] ** 2
+    return bool(rho > 0.0 and gp > 0.0 and gp >= rel * (gp + B2))
 
 
 def slope_limit(s, w, Mtilde=5.0, beta=2.0, eps=1e-8, characteristic=True, ch=1.0):
@@ -68,7 +83,7 @@ def slope_limit(s, w, Mtilde=5.0, beta=2.0, eps=1e-8, characteristic=True, ch=1.
         sig_cons = np.empty_like(slope)
         trig = np.zeros(C, dtype=bool)
         for c in range(C):
-            if characteristic:
+            if characteristic and char_usable(means[:, c], s.gamma):
                 L, R = eigen.char_matrices(means[:, c], a, s.gamma, ch)
             else:
                 L = R = np.eye(9)
@@ -138,7 +153,7 @@ def slope_limit_powell(s, w, Mtilde=5.0, beta=2.0, eps=1e-8, characteristic=True
         sig_cons = np.empty_like(slope)
         trig = np.zeros(C, dtype=bool)
         for k in range(C):
-            if characteristic:
+            if characteristic and char_usable(means[:, k], s.gamma):
                 L, R = eigen.char_matrices(means[:, k], a, s.gamma, None, nvar=8)
             else:
                 L = R = np.eye(8)
@@ -242,17 +257,27 @@ def positivity(s, w, eps_rho=1e-12, eps_p=1e-12):
         # in E - m^2/(2 rho) - B^2/2 and must not decide anything
         f = 1.0 if npass == 0 else 0.5
         m = rq < eps_rho * f
-        with np.errstate(divide="ignore", invalid="ignore"):
-            tr = np.where(m, (rb - eps_rho) / (rb - rq), 1.0)
-            mp = (rq > 0) & (pq < eps_p * f)
-            tp = np.where(mp, (pb[:, None] - eps_p) / (pb[:, None] - pq), 1.0)
-        tau = np.minimum(tau, np.minimum(tr.min(axis=1), tp.min(axis=1)))
+        # a point counts only where it lies below the mean (scaling toward the
+        # mean cannot raise a point that is not); tau is clipped to [0, 1], so
+        # a cell whose mean pressure sits at the floor collapses to its mean
+        tr = point_tau(rb, rq, eps_rho, m)
+        tp = point_tau(pb[:, None], pq, eps_p, (rq > 0) & (pq < eps_p * f))
+        tau = np.clip(np.minimum(tau, np.minimum(tr.min(axis=1), tp.min(axis=1))), 0.0, 1.0)
         sel = tau < 1.0
         if not sel.any():
             break
         stats["n_pos_scaled"] += int(sel.sum())
         out[np.ix_(sel, ~keep)] *= tau[sel][:, None]
     return out, stats
+
+
+def point_tau(mean, q, floor, mask):
+    """Per-point factor of eq. tau_rho / eq. tau_press: (mean - floor) /
+    (mean - q) at the masked points that lie below the mean, 1 elsewhere (a
+    point not below the mean cannot be raised by scaling toward it)."""
+    d = mean - q
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return np.where(mask & (d > 0), (mean - floor) / np.where(d > 0, d, 1.0), 1.0)
 
 
 def make_stage_limiter(s, limiter, Mtilde=5.0, beta=2.0, eps=1e-8, eps_rho=1e-12, eps_p=1e-12, stats=None):

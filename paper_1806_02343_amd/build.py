@@ -7,7 +7,10 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdgmhd.so")
-SOURCES = ["dg_tables.cpp", "dg_kernels.hip", "dg_mlp.hip", "dg_api.hip"]
+# (source, object, extra flags): the kernel file is built as four objects, one
+# per (precision, divergence scheme), compiled in parallel
+SOURCES = [("dg_tables.cpp", "dg_tables", []), ("dg_mlp.hip", "dg_mlp", []), ("dg_api.hip", "dg_api", [])] + [
+    ("dg_kernels.hip", f"dg_kernels_{k}", [f"-DDG_PART={k}"]) for k in range(4)]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
          # packed FP32 instructions are kept out of the device code
@@ -26,11 +29,11 @@ def build(verbose=False, jobs=4):
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     objs, procs = [], []
-    for src in SOURCES:
-        obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
-        cmd = [cc, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    for src, name, extra in SOURCES:
+        obj = os.path.join(bdir, name + ".o")
+        cmd = [cc, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
-            cmd = [cc, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+            cmd = [cc, *FLAGS, *extra, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

@@ -28,6 +28,16 @@
 #include "dg_kernels.h"
 #include "dg_physics.h"
 
+// The file is compiled as four objects in parallel, one per (precision,
+// divergence scheme): DG_PART 0 = FP64 GLM, 1 = FP64 Powell, 2 = FP32 GLM,
+// 3 = FP32 Powell.  Part 0 also holds the scalar kernels and host helpers
+// shared by all parts and the launcher factory.  Without DG_PART everything
+// is built into one object.
+#ifndef DG_PART
+#define DG_PART -1
+#endif
+#define DG_SHARED (DG_PART <= 0)
+
 namespace dgmhd {
 
 template <int D, int DEG, int DIVB>
@@ -2053,6 +2063,7 @@ __global__ void __launch_bounds__(256) k_project(const double* __restrict__ prim
   }
 }
 
+#if DG_SHARED
 // ---------------------------------------------------------------------------
 // scalar kernels
 
@@ -2181,6 +2192,7 @@ void launch_lincomb(void* out, const void* const x[4], const double c[4], size_t
     k_lincomb<float><<<grid, 256, 0, s>>>((float*)out, (const float*)X(0), (const float*)X(1), (const float*)X(2),
                                           (const float*)X(3), c[0], c[1], c[2], c[3], nmodes, ld, C);
 }
+#endif  // DG_SHARED
 
 }  // namespace dgmhd
 
@@ -2608,18 +2620,38 @@ struct LauncherImpl : Launcher {
   ~LauncherImpl() override { free_tables(); }
 };
 
-Launcher* make_launcher(int precision, int D, int d, int divb) {
 #define CASE(T, DD, DEG, DIV) \
-  if (D == DD && d == DEG && divb == DIV) return new LauncherImpl<T, DD, DEG, DIV>();
-#define ALL(T)                                                                               \
-  CASE(T, 2, 1, GLM) CASE(T, 2, 2, GLM) CASE(T, 2, 3, GLM) CASE(T, 3, 1, GLM) CASE(T, 3, 2, GLM) \
-  CASE(T, 3, 3, GLM) CASE(T, 2, 1, POWELL) CASE(T, 2, 2, POWELL) CASE(T, 2, 3, POWELL) CASE(T, 3, 1, POWELL)     \
-  CASE(T, 3, 2, POWELL) CASE(T, 3, 3, POWELL)
-  if (precision == 0) { ALL(double) }
-  else { ALL(float) }
-#undef ALL
+  if (D == DD && d == DEG) return new LauncherImpl<T, DD, DEG, DIV>();
+#define PART(NAME, T, DIV)                                                                            \
+  Launcher* NAME(int D, int d) {                                                                      \
+    CASE(T, 2, 1, DIV) CASE(T, 2, 2, DIV) CASE(T, 2, 3, DIV) CASE(T, 3, 1, DIV) CASE(T, 3, 2, DIV) \
+    CASE(T, 3, 3, DIV) return nullptr;                                                                \
+  }
+#if DG_PART == -1 || DG_PART == 0
+PART(make_launcher_f64_glm, double, GLM)
+#endif
+#if DG_PART == -1 || DG_PART == 1
+PART(make_launcher_f64_powell, double, POWELL)
+#endif
+#if DG_PART == -1 || DG_PART == 2
+PART(make_launcher_f32_glm, float, GLM)
+#endif
+#if DG_PART == -1 || DG_PART == 3
+PART(make_launcher_f32_powell, float, POWELL)
+#endif
+#undef PART
 #undef CASE
-  return nullptr;
+
+#if DG_SHARED
+Launcher* make_launcher_f64_glm(int D, int d);
+Launcher* make_launcher_f64_powell(int D, int d);
+Launcher* make_launcher_f32_glm(int D, int d);
+Launcher* make_launcher_f32_powell(int D, int d);
+
+Launcher* make_launcher(int precision, int D, int d, int divb) {
+  if (precision == 0) return divb == GLM ? make_launcher_f64_glm(D, d) : make_launcher_f64_powell(D, d);
+  return divb == GLM ? make_launcher_f32_glm(D, d) : make_launcher_f32_powell(D, d);
 }
+#endif
 
 }  // namespace dgmhd

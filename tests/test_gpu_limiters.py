@@ -133,6 +133,47 @@ def test_powell_limited_steps_match_oracle(D, d, n):
     assert np.all(err < 1e-12), err
 
 
+@pytest.mark.parametrize("D,divb", [(2, dg.GLM), (2, dg.POWELL), (3, dg.GLM), (3, dg.POWELL)])
+def test_limit_at_the_pressure_floor_in_a_strong_field_matches_oracle(D, divb):
+    """Cells whose mean pressure is ten times the floor in a field of
+    |B|^2/p ~ 1e14: the characteristic matrices there are not used
+    (componentwise limiting; the cells' condition number would exceed 1e13);
+    decisions, states and counts match the oracle, and every weight stays
+    finite.  (Exactly at the floor the floor decision itself would rest on
+    the rounding of E - |B|^2/2 ~ 4e-14.)"""
+    from paper_1806_02343_amd import DG
+    _announce("floor strong field", D, divb)
+    n = 12 if D == 2 else 10
+    b = 100.0 / np.sqrt(3.0) / np.sqrt(4.0 * np.pi)
+
+    def prim(x):
+        # pressure constant per cell (by the cell centre's radius), so that a
+        # cell mean is either at the floor or well conditioned (|B|^2/p of
+        # about 8e2 and 1e-1); density varies smoothly, v = 0
+        rc = np.sqrt((((np.floor(x * n) + 0.5) / n - 0.5) ** 2).sum(axis=1))
+        one = np.ones(x.shape[0])
+        p = np.where(rc < 0.15, 1000.0, np.where(rc < 0.4, 1e-11, 1.0)) * one
+        rho = 1.0 + 0.9 * np.sin(6 * np.pi * x[:, 0]) * np.cos(2 * np.pi * x[:, 1])
+        return dict(rho=rho, v=[0 * one, 0 * one, 0 * one], p=p, B=[b * one, b * one, b * one], psi=0 * one)
+    orc = dg.DG(dg.Mesh.uniform(D, n), 2, divb=divb, gamma=1.4)
+    wo = orc.project(dg.conserved_field(prim, 1.4, orc.nvar))
+    means = orc.cell_means(wo)
+    low = [not limiters.char_usable(means[:, k], 1.4) for k in range(orc.mesh.ncells)]
+    assert any(low) and not all(low)
+    for lim in (3, 7):
+        gpu = DG(D, 2, n, divb=divb, limiter=lim, gamma=1.4)
+        wg = torch.as_tensor(orc.to_abi(wo, gpu.ld), device="cuda")
+        st_o = {}
+        wo2 = limiters.make_stage_limiter(orc, lim, stats=st_o)(wo)
+        st_g = gpu.limit(wg, stats=True)
+        wg2 = to_cells(wg, orc.mesh.ncells)
+        assert np.all(np.isfinite(wg2))
+        assert st_g["n_tvb_triggered"] == st_o["n_tvb"] > 0
+        assert st_g["n_pos_scaled"] == st_o.get("n_pos_scaled", 0)
+        err = block_rel_max(wg2, wo2, orc)
+        assert np.all(err < 1e-12), (lim, err)
+
+
 @pytest.mark.parametrize("D,d,precision", [(3, 3, 0), (3, 2, 0), (3, 3, 1), (2, 3, 0)])
 def test_positivity_near_floors_matches_oracle(D, d, precision):
     """Positivity limiter on states built around the floors, in tiles of 16

@@ -84,6 +84,148 @@ def test_eigensystem_diagonalises_flux_jacobian(kind):
             assert np.allclose(Dg, np.diag([1.7, -1.7]), atol=1e-14)
 
 
+@pytest.mark.parametrize("a2_over_ca2", [0.5, 2.0])
+def test_eigenvectors_are_continuous_at_rounding_level_near_degenerate_states(a2_over_ca2):
+    """At B_t = 0 (and at B_n = 0) the characteristic matrices move by no
+    more than the state does: a relative change of 1e-15 in p, rho or the
+    field must not shift them by the square root of rounding (~1e-8), which a
+    fast/slow normalisation formed by cancellation does."""
+    rho, p = 1.3, 0.7
+    bn = np.sqrt(G * p / a2_over_ca2 * rho)      # c_a^2 = a^2 / ratio
+    v = np.array([0.1, -0.2, 0.3])
+    for a in range(3):
+        n, t1, t2 = ph.face_frame(a)
+        for kind in ("bt_zero", "bn_zero"):
+            B0 = np.zeros(3)
+            B0[n if kind == "bt_zero" else t1] = bn
+            base = ph.prim_to_cons(np.array(rho), v, np.array(p), B0, G, np.array(0.0))
+            L0, R0 = eigen.char_matrices(base, a, G, 1.0)
+            for k in range(6):
+                r, pp, B1 = rho, p, B0.copy()
+                pert = 1e-15 * (k + 1)
+                if k % 3 == 0:
+                    pp = p * (1 + pert)
+                elif k % 3 == 1:
+                    r = rho * (1 + pert)
+                else:
+                    B1[t1 if kind == "bt_zero" else n] += pert
+                u1 = ph.prim_to_cons(np.array(r), v, np.array(pp), B1, G, np.array(0.0))
+                L1, R1 = eigen.char_matrices(u1, a, G, 1.0)
+                assert np.abs(R1 - R0).max() < 1e-11, (a, kind, k, np.abs(R1 - R0).max())
+                assert np.abs(L1 - L0).max() < 1e-11, (a, kind, k, np.abs(L1 - L0).max())
+
+
+def test_characteristic_matrices_are_used_only_where_they_are_well_conditioned():
+    """char_usable accepts a mean state exactly when gamma p >= 1e-8 (gamma p
+    + |B|^2); on the accepted side the condition number of R stays below
+    ~1e9 (it grows like |B|^2 / (gamma p)), on the rejected side it exceeds
+    ~1e8 and L R = I fails at low pressures; NaN and non-positive states are
+    rejected."""
+    b = 100.0 / np.sqrt(3.0) / np.sqrt(4.0 * np.pi)
+    B = np.array([b, 1.01 * b, 0.99 * b])
+    g = 1.4
+    for p in (1e-1, 1e-3, 1e-5, 2e-6, 1e-7, 1e-9, 1e-12):
+        u = ph.prim_to_cons(np.array(1.0), np.array([0.3, -0.2, 0.1]), np.array(p), B, g, np.array(0.0))
+        ok = limiters.char_usable(u, g)
+        assert ok == (g * p >= 1e-8 * (g * p + (B ** 2).sum()))
+        L, R = eigen.char_matrices(u, 0, g, 50.0)
+        cond = np.linalg.cond(R)
+        assert (cond < 1e9) if ok else (cond > 1e8)
+    bad = ph.prim_to_cons(np.array(1.0), np.zeros(3), np.array(0.1), B, g, np.array(0.0))
+    for k, val in ((0, -1.0), (4, 0.0), (4, np.nan)):
+        v = bad.copy()
+        v[k] = val
+        assert not limiters.char_usable(v, g)
+
+
+def test_floor_level_cells_are_limited_componentwise():
+    """A strong-field state whose pressure sits at the floor in some cells:
+    the characteristic limiter returns finite weights, and in those cells the
+    limited slopes equal the componentwise limiter's."""
+    s = dg.DG(dg.Mesh.uniform(2, 12), 2, gamma=1.4)
+    b = 100.0 / np.sqrt(3.0) / np.sqrt(4.0 * np.pi)
+
+    def prim(x):
+        r = np.hypot(x[:, 0] - 0.5, x[:, 1] - 0.5)
+        one = np.ones(x.shape[0])
+        p = np.where(r < 0.15, 1000.0, np.where(r < 0.4, 1e-12, 0.1)) * one
+        return dict(rho=1.0 + 0.5 * (r < 0.15), v=[0.3 * one, 0 * one, 0 * one], p=p, B=[b * one, b * one, b * one],
+                    psi=0 * one)
+    w = s.project(dg.conserved_field(prim, 1.4, 9))
+    means = s.cell_means(w)
+    low = np.array([not limiters.char_usable(means[:, k], 1.4) for k in range(w.shape[0])])
+    assert low.any() and not low.all()
+    wc, tc = limiters.slope_limit(s, w, characteristic=True, ch=30.0)
+    wp, tp = limiters.slope_limit(s, w, characteristic=False, ch=30.0)
+    assert np.all(np.isfinite(wc))
+    assert np.array_equal(wc[low], wp[low]) and np.array_equal(tc[low], tp[low])
+
+
+def _at_floor_state(divb=dg.GLM, seed=5):
+    """Strong-field state whose cells have their mean pressure set exactly at
+    the floor (the energy mode written from the means) while their slopes
+    stay, so that points lie on both sides of the mean and of the floor."""
+    s = dg.DG(dg.Mesh.uniform(2, 8), 2, divb=divb, gamma=1.4)
+    rng = np.random.default_rng(seed)
+    b = 16.0
+
+    def prim(x):
+        one = np.ones(x.shape[0])
+        return dict(rho=1.0 + 0.3 * np.sin(2 * np.pi * x[:, 0]), v=[0.2 * np.cos(2 * np.pi * x[:, 1]), 0 * one, 0 * one],
+                    p=0.1 * one, B=[b * one, b * one, b * one], psi=0 * one)
+    w = s.project(dg.conserved_field(prim, 1.4, s.nvar))
+    C, n = w.shape[0], s.n
+    eidx = s.leg_vars.index(ph.EN) * n
+    cells = rng.permutation(C)[:C // 2]
+    w[cells, eidx + 1:eidx + n] += 1e-12 * rng.normal(size=(cells.size, n - 1))
+    Ub = s.cell_means(w)
+    ke = 0.5 * (Ub[1] ** 2 + Ub[2] ** 2 + Ub[3] ** 2) / Ub[0]
+    me = 0.5 * (Ub[5] ** 2 + Ub[6] ** 2 + Ub[7] ** 2)
+    w[cells, eidx] = 1e-12 / 0.4 + ke[cells] + me[cells]
+    return s, w, cells
+
+
+def test_point_tau_rule():
+    """The per-point factor: the closed form (mean - floor)/(mean - q) for a
+    point below both; 1 for a point at or above the mean (including a point
+    equal to the mean, where the ratio would be 0/0 or +-inf) and for
+    unmasked points; a mean below the floor gives a negative factor, which
+    the cell's tau clips to 0."""
+    mean = np.array([1.0, 1.0, 1e-12, 1e-12, 0.9e-12, 0.5])
+    q = np.array([-0.5, 2.0, 1e-12, 0.5e-12, 0.5e-12, -1.0])
+    mask = np.array([True, True, True, True, True, False])
+    t = limiters.point_tau(mean, q, 1e-12, mask)
+    assert np.isclose(t[0], (1.0 - 1e-12) / 1.5, rtol=1e-15)
+    assert t[1] == 1.0 and t[2] == 1.0 and t[5] == 1.0
+    assert t[3] == 0.0
+    assert t[4] < 0.0 and np.isfinite(t).all()
+
+
+@pytest.mark.parametrize("divb", [dg.GLM, dg.POWELL])
+def test_positivity_with_means_at_the_floor_is_finite_and_convex(divb):
+    """Eq. tau_press with the mean pressure at the floor (up to the rounding
+    of E - |m|^2/2rho - |B|^2/2 ~ 5e-14): every cell's new weights are its
+    mean plus tau times its deviation with tau in [0, 1] (no sign flip, no
+    infinity from a point equal to the mean), and all are finite."""
+    s, w, cells = _at_floor_state(divb)
+    w2, st = limiters.positivity(s, w)
+    assert np.all(np.isfinite(w2))
+    assert st["n_pos_scaled"] > 0
+    n = s.n
+    keep = np.zeros(w.shape[1], dtype=bool)
+    keep[[j * n for j in range(len(s.leg_vars))]] = True
+    if s.nldf:
+        keep[len(s.leg_vars) * n:len(s.leg_vars) * n + s.D] = True
+    for k in range(w.shape[0]):
+        dv, dv2 = w[k, ~keep], w2[k, ~keep]
+        big = np.abs(dv) > 0
+        if not big.any():
+            continue
+        r = dv2[big] / dv[big]
+        assert np.all(r >= -1e-15) and np.all(r <= 1 + 1e-15), (k, r.min(), r.max())
+        assert np.ptp(r) < 1e-12                           # one tau per cell
+
+
 def _blast_state(n=6, d=2, seed=2000):
     s = dg.DG(dg.Mesh.uniform(3, n), d)
     w = s.project(dg.conserved_field(wl.Blast(seed), G, 9))

@@ -24,6 +24,24 @@ Recipes (one per workload):
   alfven2d    circularly polarised Alfven wave of the paper's 2-D convergence
               test (box sqrt(5), eps = 0.1, p = 0.1), exact at any time.
   alfven3d    the 3-D variant along the cube diagonal (p = 100, eps = 0.02).
+
+Shock problems of the paper's test section (deterministic, no random draws):
+  orszag_tang [0,1]^2, rho = 25/(36 pi), p = 5/(12 pi), v = (-sin 2pi y,
+              sin 2pi x, 0), B = B0 (-sin 2pi y, sin 4pi x, 0), B0 = 1/sqrt(4 pi).
+  rotor       [0,1]^2, p = 1, B = (5/sqrt(4 pi), 0, 0); disk r < 0.1 with
+              rho = 10 rotating at v = (0.5 - y, x - 0.5) v0/r0 (v0 = 2),
+              linear taper f = (r1 - r)/(r1 - r0) to r1 = 0.115 (rho = 1 + 9f,
+              v scaled by f), rho = 1 at rest outside.
+  blast2d     [0,1]^2, rho = 1, p = 0.1, v = 0, B = B0 (cos 45, sin 45, 0),
+              B0 = 1; p = 10 within r0 = 0.1 of the box centre.
+  blast3d     [0,1]^3, rho = 1, p = 0.1, v = 0, B = (B0, B0, B0),
+              B0 = 100/(sqrt 3 sqrt(4 pi)), gamma 1.4 (2p/|B|^2 = 2.5e-4;
+              the plasma beta of 7.5e-4 the paper quotes is 2p/B0^2);
+              p = 1000 within r0 = 0.1 of the centre, which sits half a cell
+              off the box centre (at a cell centre).
+  loop        [-1,1]^2 (mesh box 2, coordinates shifted by -1), rho = 1, p = 1,
+              v = (2, 1, 0), B = curl (0, 0, A_z) with A_z = A0 max(0, r0 - r),
+              A0 = 1e-3, r0 = 0.3: B = A0 (-y, x, 0)/r inside the loop.
 """
 import math
 
@@ -229,6 +247,96 @@ class Alfven3D:
         v = [sum(vprime[i] * float(self.E[i, c]) for i in range(3)) for c in range(3)]
         B = [sum(bprime[i] * float(self.E[i, c]) for i in range(3)) for c in range(3)]
         return dict(rho=one, v=v, p=self.p0 * one, B=B, psi=0.0 * one)
+
+
+def _radius(x, c):
+    """Euclidean distance of the points x[P, D] from the point c (no periodic wrap)."""
+    xp = _xp(x)
+    d = x - (c if xp is np else torch.as_tensor(c, dtype=x.dtype, device=x.device))
+    return xp.sqrt((d * d).sum(axis=-1) if xp is np else (d * d).sum(dim=-1))
+
+
+class OrszagTang:
+    """Orszag-Tang vortex (2-D, gamma 5/3)."""
+
+    def __call__(self, x):
+        xp = _xp(x)
+        tp = 2.0 * math.pi
+        b0 = 1.0 / math.sqrt(4.0 * math.pi)
+        X, Y = x[:, 0], x[:, 1]
+        z = _const(xp, X, 0.0)
+        return dict(rho=_const(xp, X, 25.0 / (36.0 * math.pi)), p=_const(xp, X, 5.0 / (12.0 * math.pi)),
+                    v=[-xp.sin(tp * Y), xp.sin(tp * X), z], B=[-b0 * xp.sin(tp * Y), b0 * xp.sin(2 * tp * X), z],
+                    psi=z)
+
+
+class Rotor:
+    """First rotor problem (2-D; the paper states no gamma for it, the runs
+    here take 1.4, that of the problem's original definition)."""
+
+    r0, r1, v0 = 0.1, 0.115, 2.0
+
+    def __call__(self, x):
+        xp = _xp(x)
+        X, Y = x[:, 0], x[:, 1]
+        r = _radius(x, np.array([0.5, 0.5]))
+        one = _const(xp, X, 1.0)
+        f = xp.where(r < self.r0, one, xp.where(r > self.r1, 0.0 * one, (self.r1 - r) / (self.r1 - self.r0)))
+        w = self.v0 / self.r0 * f
+        z = 0.0 * one
+        return dict(rho=1.0 + 9.0 * f, p=one, v=[(0.5 - Y) * w, (X - 0.5) * w, z],
+                    B=[5.0 / math.sqrt(4.0 * math.pi) * one, z, z], psi=z)
+
+
+class Blast2D:
+    """Strongly magnetised blast wave in 2-D (B at 45 degrees to the grid)."""
+
+    def __init__(self, B0=1.0):
+        self.B0 = B0
+
+    def __call__(self, x):
+        xp = _xp(x)
+        one = _const(xp, x[:, 0], 1.0)
+        r = _radius(x, np.array([0.5, 0.5]))
+        b = self.B0 / math.sqrt(2.0)
+        z = 0.0 * one
+        return dict(rho=one, p=xp.where(r < 0.1, 10.0 * one, 0.1 * one), v=[z, z, z], B=[b * one, b * one, z],
+                    psi=z)
+
+
+class Blast3D:
+    """Blast wave with pressure ratio 1e4 in a strong field (gamma 1.4); the
+    centre is moved half a cell of an n^3 grid off the box centre."""
+
+    def __init__(self, n):
+        self.c = np.full(3, 0.5 + 0.5 / n)
+
+    def __call__(self, x):
+        xp = _xp(x)
+        one = _const(xp, x[:, 0], 1.0)
+        r = _radius(x, self.c)
+        b = 100.0 / (math.sqrt(3.0) * math.sqrt(4.0 * math.pi))
+        z = 0.0 * one
+        return dict(rho=one, p=xp.where(r < 0.1, 1000.0 * one, 0.1 * one), v=[z, z, z], B=[b * one, b * one, b * one],
+                    psi=z)
+
+
+class Loop:
+    """Field-loop advection on [-1,1]^2 (mesh box 2, points shifted by -1)."""
+
+    A0, R0 = 1e-3, 0.3
+
+    def __call__(self, x):
+        xp = _xp(x)
+        xs = x - 1.0
+        one = _const(xp, x[:, 0], 1.0)
+        r = _radius(xs, np.array([0.0, 0.0]))
+        inside = r < self.R0
+        rs = xp.where(inside, r, one)
+        z = 0.0 * one
+        bx = xp.where(inside, -self.A0 * xs[:, 1] / rs, z)
+        by = xp.where(inside, self.A0 * xs[:, 0] / rs, z)
+        return dict(rho=one, p=one, v=[2.0 * one, one, z], B=[bx, by, z], psi=z)
 
 
 def config_field(cfg, replicate=0):
