@@ -143,6 +143,14 @@ int dg_proj_points(dg_handle h, double* xi /*[host] or NULL*/, int64_t* npts /*[
  * columns of w.  Async. */
 int dg_project(dg_handle h, const double* prim, int64_t cell0, int64_t ncell, void* w);
 
+/* Conserved state at the points of dg_proj_points (the (d+3)^dim Gauss
+ * rule with which eq. lp_norm measures errors) for cells cell0 ..
+ * cell0+ncell-1: out is a device FP64 array [nvar][npts][ncell] (nvar = 9
+ * for GLM, 8 for Powell; variables rho, m1, m2, m3, E, B1, B2, B3, psi),
+ * evaluated in FP64 from the weights of w (of either precision).  DG_EINVAL
+ * for a null pointer or a cell range outside the grid.  Async. */
+int dg_nodal(dg_handle h, const void* w, int64_t cell0, int64_t ncell, double* out);
+
 /* Time step of the state w (eq. cfl; Powell cap eq. powell_dt; GLM c_h and
  * kappa = c_h^2 / c_p^2 of Sec. 4.1.5).  Synchronous; outputs on the host.
  * DG_ENONFINITE if the state's signal speed is not finite; DG_ECH (outputs

@@ -12,7 +12,7 @@ DG_LIM_TVB, DG_LIM_CHAR, DG_LIM_POS, DG_LIM_LEARNED = 1, 2, 4, 8
 DG_MESH_UNIFORM, DG_MESH_OCTREE = 0, 1
 DG_POWELL_Q_MEAN, DG_POWELL_Q_INTERP = 0, 1
 
-EXPORTS = ["dg_init", "dg_layout", "dg_proj_points", "dg_project", "dg_dt", "dg_rhs", "dg_rhs_noalloc", "dg_limit",
+EXPORTS = ["dg_init", "dg_layout", "dg_proj_points", "dg_project", "dg_nodal", "dg_dt", "dg_rhs", "dg_rhs_noalloc", "dg_limit",
            "dg_step",
            "dg_mlp_scale", "dg_mlp_set", "dg_mlp_get", "dg_mlp_features", "dg_mlp_labels", "dg_mlp_record", "dg_mlp_forward",
            "dg_mlp_grad", "dg_mlp_train", "dg_time_kernel", "dg_autotune", "dg_last_error", "dg_destroy"]
@@ -70,6 +70,7 @@ def load_library(path=LIB_PATH):
     lib.dg_layout.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64)]
     lib.dg_proj_points.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(I64)]
     lib.dg_project.argtypes = [P, P, I64, I64, P]
+    lib.dg_nodal.argtypes = [P, P, I64, I64, P]
     lib.dg_dt.argtypes = [P, P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)]
     lib.dg_rhs.argtypes = [P, P, P, D, D]
     lib.dg_rhs_noalloc.argtypes = [P, P, P, D, D]
@@ -184,6 +185,19 @@ class DG:
         """prim: device float64 tensor [9][ncell][npts] of primitive values."""
         assert prim.dtype == self.torch.float64 and prim.is_contiguous()
         self._check(self.lib.dg_project(self.h, _ptr(prim), cell0, ncell, _ptr(w)))
+
+    def nodal(self, w, cell0=0, ncell=None, out=None):
+        """Conserved state at the projection points: device float64 tensor
+        [nvar][npts][ncell] (nvar 9 for GLM, 8 for Powell)."""
+        torch = self.torch
+        ncell = self.ncells - cell0 if ncell is None else ncell
+        nvar = 9 if self.divb == DG_GLM else 8
+        npts = self.proj_points().shape[0]
+        if out is None:
+            out = torch.empty((nvar, npts, ncell), dtype=torch.float64, device="cuda")
+        assert out.dtype == torch.float64 and out.is_contiguous() and out.numel() >= nvar * npts * ncell
+        self._check(self.lib.dg_nodal(self.h, _ptr(w), cell0, ncell, _ptr(out)))
+        return out
 
     def dt(self, w):
         dt, ch, k = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()

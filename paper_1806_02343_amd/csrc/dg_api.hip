@@ -397,6 +397,15 @@ int dg_project(dg_handle h, const double* prim, int64_t cell0, int64_t ncell, vo
   return check_launch(h, "project");
 }
 
+int dg_nodal(dg_handle h, const void* w, int64_t cell0, int64_t ncell, double* out) {
+  if (int r = valid_state(h, w)) return r;
+  if (!out) return fail(h, DG_EINVAL, "null out");
+  if (cell0 < 0 || ncell < 0 || cell0 + ncell > h->g.C) return fail(h, DG_EINVAL, "cell range");
+  if (ncell == 0) return DG_OK;
+  h->L->nodal(w, cell0, ncell, out, h->g, h->stream);
+  return check_launch(h, "nodal");
+}
+
 static int dt_sequence(dg_handle h, const void* w) {
   launch_reset_step(h->sc, h->stream);
   h->L->maxsig(w, h->g, h->sc, h->sp, h->stream);

@@ -92,6 +92,8 @@ struct Launcher {
   // Powell dt cap: per-face normal-field jumps then per-cell rate
   virtual void powell_cap(const void* w, void* jsum, const Grid& g, Scal* sc, const SchemeParams& sp,
                           hipStream_t s) = 0;
+  // conserved state at the points of the projection rule: out[var][point][cell - cell0]
+  virtual void nodal(const void* w, int64_t cell0, int64_t ncell, double* out, const Grid& g, hipStream_t s) = 0;
   virtual void project(const double* prim, int64_t cell0, int64_t ncell, void* w, const Grid& g,
                        const SchemeParams& sp, hipStream_t s) = 0;
   // limiters in place

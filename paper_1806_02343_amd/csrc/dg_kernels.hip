@@ -2022,6 +2022,33 @@ struct ProjTile {
   static constexpr int TC = TC0 > 16 ? 16 : (TC0 < 1 ? 1 : TC0);
 };
 
+// Conserved state at the points of the projection rule, one thread per
+// (cell, point); consecutive threads take consecutive cells of one point.
+template <typename T, int D, int DEG, int DIVB>
+__global__ void __launch_bounds__(256) k_nodal(const T* __restrict__ w, int64_t cell0, int64_t ncell,
+                                               double* __restrict__ out, const double* __restrict__ vp,
+                                               const double* __restrict__ pvp, int64_t ld) {
+  using C = Cfg<D, DEG, DIVB>;
+  constexpr int NP = ProjTile<D, DEG>::NP;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ncell * NP) return;
+  const int p = (int)(i / ncell);
+  const int64_t c = i - (int64_t)p * ncell, K = cell0 + c;
+  for (int j = 0; j < C::NLEG; ++j) {
+    double s = 0.0;
+    for (int l = 0; l < C::N; ++l) s += vp[p * C::N + l] * (double)w[(int64_t)(j * C::N + l) * ld + K];
+    out[((int64_t)C::legvar(j) * NP + p) * ncell + c] = s;
+  }
+  if constexpr (C::NLDF > 0) {
+    for (int cc = 0; cc < D; ++cc) {
+      double s = 0.0;
+      for (int l = 0; l < C::NLDF; ++l)
+        s += pvp[(cc * NP + p) * C::NLDF + l] * (double)w[(int64_t)(C::NLEG * C::N + l) * ld + K];
+      out[((int64_t)(5 + cc) * NP + p) * ncell + c] = s;
+    }
+  }
+}
+
 template <typename T, int D, int DEG, int DIVB>
 __global__ void __launch_bounds__(256) k_project(const double* __restrict__ prim, int64_t cell0, int64_t ncell,
                                                  T* __restrict__ w, const double* __restrict__ vpw,
@@ -2209,7 +2236,7 @@ struct LauncherImpl : Launcher {
   using TL = Tile<T, D, DEG, DIVB>;
   std::vector<void*> bufs;
   DevTab<T> tb{};
-  double *vpw = nullptr, *pvpw = nullptr, *minv64 = nullptr;
+  double *vpw = nullptr, *pvpw = nullptr, *minv64 = nullptr, *vp64 = nullptr, *pvp64 = nullptr;
   const T *mfv = nullptr, *mfg = nullptr, *mfl = nullptr;  // fragment-order tables of the matrix-core cell kernel
   const T *mgx = nullptr, *mlx = nullptr;                   // and its vector-ALU rows (modes 16..19)
   const T* ml1 = nullptr;                                   // lift of a constant over each -a face
@@ -2248,6 +2275,10 @@ struct LauncherImpl : Launcher {
     pvpw = (double*)d1;
     if ((e = up<double>(t.Minv, d1)) != hipSuccess) return e;
     minv64 = (double*)d1;
+    if ((e = up<double>(t.VP, d1)) != hipSuccess) return e;
+    vp64 = (double*)d1;
+    if ((e = up<double>(t.PVP, d1)) != hipSuccess) return e;
+    pvp64 = (double*)d1;
     if constexpr (DIVB == POWELL) {
       std::vector<double> fv, fg, fl, pv, pg, pl, gx, lx;
       mfma_tables<T, D, DEG>(t, fv, fg, fl, gx, lx);
@@ -2559,6 +2590,13 @@ struct LauncherImpl : Launcher {
       k_face_jump<T, D, DEG, DIVB><<<(int)((nf + 255) / 256), 256, 0, s>>>((const T*)w, (double*)jsum, tb, g, sp.gamma);
       k_powell_rate<T, D, DEG, DIVB><<<(int)((g.C + 255) / 256), 256, 0, s>>>((const T*)w, (const double*)jsum, tb, g, sc);
     }
+  }
+  void nodal(const void* w, int64_t cell0, int64_t ncell, double* out, const Grid& g, hipStream_t s) override {
+    constexpr int NP = ProjTile<D, DEG>::NP;
+    if (ncell <= 0) return;
+    const int64_t n = ncell * NP;
+    k_nodal<T, D, DEG, DIVB><<<(unsigned)((n + 255) / 256), 256, 0, s>>>((const T*)w, cell0, ncell, out, vp64, pvp64,
+                                                                         g.ld);
   }
   void project(const double* prim, int64_t cell0, int64_t ncell, void* w, const Grid& g, const SchemeParams& sp,
                hipStream_t s) override {

@@ -352,9 +352,14 @@ bool build_tables(int D, int d, int divb, Tables& t, std::string& err) {
     wpj[p] = wp[p0] * wp[p1];
     if (D == 3) { t.xproj[p * D + 2] = xp[p2]; wpj[p] *= wp[p2]; }
   }
+  t.wproj = wpj;
   t.VPW.assign(t.NPROJ * N, 0.0);
+  t.VP.assign(t.NPROJ * N, 0.0);
   for (int p = 0; p < t.NPROJ; ++p)
-    for (int l = 0; l < N; ++l) t.VPW[p * N + l] = wpj[p] * Pl(l, &t.xproj[p * D]);
+    for (int l = 0; l < N; ++l) {
+      t.VP[p * N + l] = Pl(l, &t.xproj[p * D]);
+      t.VPW[p * N + l] = wpj[p] * t.VP[p * N + l];
+    }
   if (t.NLDF) {
     std::vector<Vec> basis;
     if (!build_ldf(D, d, basis, t.ldf_deg, err)) return false;
@@ -366,6 +371,7 @@ bool build_tables(int D, int d, int divb, Tables& t, std::string& err) {
     t.Pmean.assign(D * L, 0.0);
     t.Plin.assign(D * D * L, 0.0);
     t.PVPW.assign(D * t.NPROJ * L, 0.0);
+    t.PVP.assign(D * t.NPROJ * L, 0.0);
     for (int l = 0; l < L; ++l) {
       double nrm = vinner(basis[l], basis[l], D);
       t.Mass[t.NLEG * N + l] = nrm;
@@ -391,8 +397,10 @@ bool build_tables(int D, int d, int divb, Tables& t, std::string& err) {
           if (b == 0) xb.at(1, 0, 0) = 1.0; else if (b == 1) xb.at(0, 1, 0) = 1.0; else xb.at(0, 0, 1) = 1.0;
           t.Plin[(c * D + b) * L + l] = pinner(pc, xb, D) / pinner(xb, xb, D);
         }
-        for (int p = 0; p < t.NPROJ; ++p)
-          t.PVPW[(c * t.NPROJ + p) * L + l] = wpj[p] * pc.eval(&t.xproj[p * D], D);
+        for (int p = 0; p < t.NPROJ; ++p) {
+          t.PVP[(c * t.NPROJ + p) * L + l] = pc.eval(&t.xproj[p * D], D);
+          t.PVPW[(c * t.NPROJ + p) * L + l] = wpj[p] * t.PVP[(c * t.NPROJ + p) * L + l];
+        }
       }
     }
   }

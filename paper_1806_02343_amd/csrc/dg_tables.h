@@ -43,6 +43,9 @@ struct Tables {
   std::vector<double> xproj;           // [NPROJ][D]
   std::vector<double> VPW;             // [NPROJ][N]         w_p P_l(xi_p)
   std::vector<double> PVPW;            // [D(c)][NPROJ][NLDF] w_p Phi_c(xi_p)
+  std::vector<double> wproj;           // [NPROJ] weights of the rule (sum 2^D)
+  std::vector<double> VP;              // [NPROJ][N]         P_l(xi_p)
+  std::vector<double> PVP;             // [D(c)][NPROJ][NLDF] Phi_c(xi_p)
 };
 
 // Gauss-Legendre nodes (ascending) and weights on [-1, 1].

@@ -69,6 +69,29 @@ def test_rhs_matches_oracle(case):
     assert np.all(err < 1e-12), err
 
 
+@pytest.mark.parametrize("case", [(2, 1, 32, dg.GLM), (3, 3, 5, dg.GLM), (3, 2, 6, dg.POWELL), (2, 3, 9, dg.POWELL)],
+                         ids=ids)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_nodal_values_match_oracle(case, prec):
+    """dg_nodal: the state at the (d+3)^D points of the projection rule
+    against the oracle's evaluation of the same weights, all cells and a
+    sub-range."""
+    D, d, n, divb = case
+    _announce("nodal", case, prec)
+    gpu, wg, orc, wo = make_pair(D, d, n, divb, precision=prec)
+    wc = to_cells(wg, orc.mesh.ncells)
+    xi = gpu.proj_points()
+    U = orc.nodal(wc, xi=xi)                                # [var, cell, point]
+    out = gpu.nodal(wg).cpu().numpy()                       # [var, point, cell]
+    assert out.shape == (orc.nvar, xi.shape[0], orc.mesh.ncells)
+    scale = np.abs(U).max(axis=(1, 2))
+    err = np.abs(out.transpose(0, 2, 1) - U).max(axis=(1, 2)) / np.maximum(scale, 1e-3 * scale.max())
+    assert np.all(err < 1e-13), err
+    c0, nc = 7, orc.mesh.ncells // 3
+    sub = gpu.nodal(wg, c0, nc).cpu().numpy()
+    assert np.array_equal(sub, out[:, :, c0:c0 + nc])
+
+
 @pytest.mark.parametrize("case", CASES, ids=ids)
 def test_timestep_matches_oracle(case):
     D, d, n, divb = case
