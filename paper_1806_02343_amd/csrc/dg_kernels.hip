@@ -1346,8 +1346,14 @@ __device__ __forceinline__ void cell_tile_mfma_powell(int64_t c0, int lane, cons
   }
 }
 
+// two waves per SIMD where the tile fits 256 registers without spilling
+template <typename T, int D, int DEG>
+constexpr int powell_cell_waves_per_eu() {
+  return (D == 3 && DEG >= 3) ? 1 : 2;
+}
+
 template <typename T, int D, int DEG, int NW>
-__global__ void __launch_bounds__(64 * NW)
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(powell_cell_waves_per_eu<T, D, DEG>())))
     k_cell_mfma_powell(const T* w, const T* w0, T* out, const T* __restrict__ ff, const T* __restrict__ jp,
                        const T* __restrict__ FV, const T* __restrict__ FG, const T* __restrict__ FL,
                        const T* __restrict__ PVt, const T* __restrict__ PGt, const T* __restrict__ PLt,
