@@ -60,6 +60,47 @@ def test_forward_and_gradients_match_oracle():
     torch.cuda.synchronize()
     po, _ = mlp.forward(Pq, X, bf16=True)
     assert np.abs(prob.cpu().numpy() - po).max() < 5e-3
+    # against the FP64 network (no BF16 rounding anywhere): the BF16 operands
+    # (8 significant bits) leave a few per cent per element, ~1e-2 of each
+    # layer's largest gradient
+    loss_64, G64 = mlp.backward(Pq, X, y, bf16=False)
+    assert abs(loss_g - loss_64) <= 1e-2 * loss_64
+    rel = [np.abs(a - b).max() / np.abs(b).max() for a, b in zip(Gg, G64)]
+    print("gradient error vs the FP64 network, per parameter block:", ["%.1e" % r for r in rel], flush=True)
+    assert max(rel) < 1e-2, rel                       # measured <= 4.1e-3
+    p64, _ = mlp.forward(Pq, X, bf16=False)
+    assert np.abs(prob.cpu().numpy() - p64).max() < 2e-2
+
+
+def test_adam_steps_match_oracle():
+    """Three Adam steps on one full batch (dg_mlp_train with batch = rows)
+    against the oracle's BF16-rounding gradients and adam_update: the update
+    of an element is lr times a ratio of moments that the gradients' BF16
+    noise moves by a few per cent, so the parameters agree to a small
+    fraction of lr (and within the 3 lr an element can move at all)."""
+    print("case mlp adam", flush=True)
+    rng = np.random.default_rng(4)
+    P = mlp.init_params(6)
+    B, lr, k = 256, 1e-3, 3
+    X = rng.normal(size=(B, 256))
+    y = (rng.uniform(size=B) > 0.5).astype(np.float64)
+    gpu = _gpu_handle()
+    gpu.mlp_set(_pub(P), np.ones(9))
+    Pq = _unpub(_pub(P))
+    Xq = mlp.bf16_round(X)
+    gpu.mlp_train(_bf16_tensor(X), torch.as_tensor(y.astype(np.float32), device="cuda"), B, batch=B, epochs=k, lr=lr,
+                  seed=3)
+    Pg = _unpub(gpu.mlp_get())
+    Po = [p.copy() for p in Pq]
+    M = [np.zeros_like(p) for p in Po]
+    V = [np.zeros_like(p) for p in Po]
+    for t in range(1, k + 1):
+        _, G = mlp.backward([mlp.bf16_round(p) if p.ndim == 2 else p for p in Po], Xq, y, bf16=True)
+        mlp.adam_update(Po, G, M, V, t, lr)
+    d = np.concatenate([np.abs(a - b).ravel() for a, b in zip(Pg, Po)])
+    moved = np.concatenate([np.abs(a - b).ravel() for a, b in zip(Po, Pq)])
+    assert np.median(moved) > 0.5 * lr                      # the steps did move the parameters
+    assert np.median(d) < 0.02 * lr and d.max() < 2 * k * lr, (np.median(d) / lr, d.max() / lr)
 
 
 def _blast_state(n=6, d=3):
@@ -109,6 +150,43 @@ def test_gate_counts_match_features_and_forward():
     st = gpu.limit(wg, stats=True)
     assert st["n_mlp_flagged"] == int((p >= 0.55).sum())
     assert st["n_fallback"] == int(((p >= 0.45) & (p < 0.55)).sum())
+
+
+def test_gated_limit_matches_oracle():
+    """The learned gate inside dg_limit (Sec. 4.2 detect-then-limit with the
+    network in front): cells whose probability (oracle features, oracle
+    forward with the GPU's parameters) is below mlp_lo skip the detector and
+    stay bitwise; every other cell is limited as the oracle limits it.  Cells
+    whose probability lies within 1e-2 of mlp_lo (the BF16 forward's spread)
+    are left out of the comparison."""
+    print("case mlp gated limit", flush=True)
+    from paper_1806_02343_amd import DG, DG_LIM_CHAR, DG_LIM_LEARNED, DG_LIM_POS, DG_LIM_TVB
+    gpu0, wg0, orc, wo = make_pair(3, 3, 6, dg.GLM, field=wl.Blast(2000), limiter=7)
+    sigma = mlp.feature_scale(orc, wo)
+    gpu0.mlp_set(None, sigma, seed=5)
+    Pq = _unpub(gpu0.mlp_get())
+    # spread the logits so that the probabilities cover (0, 1)
+    Pq[6] = Pq[6] * 40.0
+    p, _ = mlp.forward(Pq, mlp.bf16_round(mlp.features(orc, wo, sigma)), bf16=True)
+    lo = float(np.quantile(p, 0.5))
+    lim = DG_LIM_TVB | DG_LIM_CHAR | DG_LIM_POS | DG_LIM_LEARNED
+    gpu = DG(3, 3, 6, limiter=lim, mlp_lo=lo, mlp_hi=1.5)
+    gpu.mlp_set(_pub(Pq), sigma)
+    wg = torch.as_tensor(orc.to_abi(wo, gpu.ld), device="cuda")
+    st = gpu.limit(wg, stats=True)
+    wgc = to_cells(wg, orc.mesh.ncells)
+    skip = p < lo
+    sure = np.abs(p - lo) > 1e-2
+    ch = orc.timestep(wo)[1]
+    wl_, tr = limiters.slope_limit(orc, wo, ch=ch)
+    wl_[skip] = wo[skip]
+    wo2, _ = limiters.positivity(orc, wl_)
+    assert skip[sure].any() and (~skip[sure]).any() and (tr & ~skip & sure).any()
+    ref_trig = int((tr & ~skip)[sure].sum())
+    gpu_trig_bound = st["n_tvb_triggered"]
+    assert abs(gpu_trig_bound - ref_trig) <= int((~sure).sum())
+    err = np.abs(wgc[sure] - wo2[sure]).max(axis=1) / np.abs(wo2).max()
+    assert np.all(err < 1e-12), err.max()
 
 
 def test_training_learns_a_separable_rule():
