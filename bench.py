@@ -83,8 +83,13 @@ def rel_l1_nodal(ga, wa, gb, wb, nvar_cmp=8, chunk=1 << 15):
     ref = torch.zeros_like(err)
     for c0 in range(0, ga.ncells, chunk):
         nc = min(chunk, ga.ncells - c0)
+        # the handles may write on streams of their own: the previous chunk's
+        # reductions must be done before the buffers are rewritten, and the
+        # values must be written before they are read
+        torch.cuda.synchronize()
         A = ga.nodal(wa, c0, nc)[:nvar_cmp]
         B = gb.nodal(wb, c0, nc)[:nvar_cmp]
+        torch.cuda.synchronize()
         _, h = ga.cell_centers(c0, nc)        # octree cells carry their own size
         vol = h.reshape(1, 1, -1) ** ga.dim if isinstance(h, torch.Tensor) else 1.0
         err += ((A - B).abs() * wq * vol).sum(dim=(1, 2))
