@@ -163,3 +163,157 @@ class Octree:
 
     def coords(self):
         return np.array([list(c) + [0] * (3 - self.D) for _, c in self.leaves], dtype=np.int32)
+
+
+# ----------------------------------------------------------------------
+# Dynamic refinement (Sec. 4.4): smoothness indicator, L2 prolongation and
+# restriction of the modal weights, and the regrid of a leaf set.
+
+from functools import lru_cache  # noqa: E402
+
+from . import basis as B  # noqa: E402
+from . import physics as ph  # noqa: E402
+from .quadrature import tensor_rule  # noqa: E402
+
+
+@lru_cache(maxsize=None)
+def _scalar_polys(D, d):
+    """Exact polynomials of the Legendre modes (3-variable exponents)."""
+    return tuple(B._legendre_product_poly(tuple(e) + (0,) * (3 - D)) for e in B.mode_exponents(D, d))
+
+
+def _kth_derivative_values(p, a, k, xi):
+    for _ in range(k):
+        p = B._pderiv(p, a)
+    return B._peval(p, xi)
+
+
+def smoothness(s, w, fields=(ph.RHO, ph.B1, ph.B2, ph.B3)):
+    """S_alpha(u) = sum_{k=1}^{d} 2^(2k-1) int_{[-1,1]^D} (d^k u / d xi_alpha^k)^2
+    (the smoothness indicator of Sec. 4.4, on the reference cell) for each
+    cell, monitored field and direction: array [C, len(fields), D].  The
+    field's polynomial is its Legendre expansion, or for B under the Powell
+    scheme its component of the LDF expansion; the integrals are exact with
+    the (d+1)-point Gauss rule (integrands of degree <= 2(d - k))."""
+    D, d, n = s.D, s.d, s.n
+    xq, wq = tensor_rule(d + 1, D)
+    xq3 = np.concatenate([xq, np.zeros((xq.shape[0], 3 - D))], axis=1)
+    C = w.shape[0]
+    out = np.zeros((C, len(fields), D))
+    leg = _scalar_polys(D, d)
+    ldf = B.ldf_basis_exact(D, d)[0] if s.nldf else None
+    for i, v in enumerate(fields):
+        if v in s.leg_vars:
+            j = s.leg_vars.index(v)
+            polys = leg
+            wv = w[:, j * n:(j + 1) * n]
+        else:
+            c = v - ph.B1
+            polys = [V[c] for V in ldf]
+            wv = w[:, len(s.leg_vars) * n:]
+        for a in range(D):
+            for k in range(1, d + 1):
+                T = np.stack([_kth_derivative_values(p, a, k, xq3) for p in polys], axis=1)  # [Q, modes]
+                du = wv @ T.T                                                           # [C, Q]
+                out[:, i, a] += 2.0 ** (2 * k - 1) * (du ** 2 * wq).sum(axis=1)
+    return out
+
+
+def _octant_shift(o, D):
+    return np.array([2 * ((o >> a) & 1) - 1 for a in range(D)], dtype=np.float64)
+
+
+def prolong(s, wp, o):
+    """Weights of child o (bit a of o: upper half along axis a) of a cell with
+    weights wp: the L2 projection of the parent's polynomial restricted to
+    the octant onto the child's basis (exact: the same polynomial)."""
+    xq, wq = tensor_rule(s.d + 1, s.D)
+    xi_p = 0.5 * (xq + _octant_shift(o, s.D))
+    U = s.nodal(np.asarray(wp)[None, :], xi=xi_p)
+    return s.project_test(U, s._basis_at(xq), wq)[0] / s.M
+
+
+def restrict(s, wc):
+    """Weights of the parent of the 2^D children wc[o] (octant order): the L2
+    projection of the piecewise polynomial onto the parent's basis; each
+    octant contributes with the Jacobian 2^-D of the map to the parent's
+    reference cell."""
+    xq, wq = tensor_rule(s.d + 1, s.D)
+    acc = np.zeros(s.nmodes)
+    for o in range(1 << s.D):
+        U = s.nodal(np.asarray(wc[o])[None, :], xi=xq)
+        xi_p = 0.5 * (xq + _octant_shift(o, s.D))
+        acc += s.project_test(U, s._basis_at(xi_p), wq * 2.0 ** (-s.D))[0]
+    return acc / s.M
+
+
+def _octant_of(c, D):
+    return sum((c[a] & 1) << a for a in range(D))
+
+
+def regrid(tree, s, w, s_tilde=0.03, fields=(ph.RHO, ph.B1, ph.B2, ph.B3), max_level=8):
+    """One regrid of Sec. 4.4.  A leaf is refined when S_alpha(u) > 2 S~ for
+    any monitored field and direction (and its level is below max_level); a
+    complete group of 2^D sibling leaves, none of them marked for refinement,
+    is merged into its parent when the parent's polynomial (the restriction
+    of the children) has S_alpha(u) < S~/2 for every field and direction.
+    2:1 balance: a merge that would leave a face neighbour two levels finer
+    is dropped; remaining violations are removed by refinement.  Returns
+    (new tree, new weights, stats)."""
+    D = tree.D
+    Sv = smoothness(s, w, fields)
+    refine = (Sv > 2.0 * s_tilde).reshape(len(tree.leaves), -1).any(axis=1)
+    refine &= np.array([l < max_level for l, _ in tree.leaves])
+    # complete sibling groups
+    groups = {}
+    for i, (l, c) in enumerate(tree.leaves):
+        if l > 0:
+            groups.setdefault((l - 1, tuple(x // 2 for x in c)), []).append(i)
+    merge = {}
+    for par, kids in groups.items():
+        if len(kids) != (1 << D) or refine[kids].any():
+            continue
+        order = sorted(kids, key=lambda i: _octant_of(tree.leaves[i][1], D))
+        wpar = restrict(s, w[order])
+        Sp = smoothness(s, wpar[None, :], fields)
+        if (Sp < 0.5 * s_tilde).all():
+            merge[par] = order
+    # apply, dropping merges that break the 2:1 balance
+    while True:
+        leaves = []
+        for i, (l, c) in enumerate(tree.leaves):
+            if l > 0 and (l - 1, tuple(x // 2 for x in c)) in merge:
+                continue
+            if refine[i]:
+                for off in range(1 << D):
+                    leaves.append((l + 1, tuple(2 * c[a] + ((off >> a) & 1) for a in range(D))))
+            else:
+                leaves.append((l, c))
+        leaves += list(merge.keys())
+        t = Octree(D, tree.n0, leaves, tree.box)
+        bad = t.balance_violations()
+        drop = [t.leaves[i] for i in np.nonzero(bad)[0] if t.leaves[i] in merge]
+        if not drop:
+            break
+        for par in drop:
+            del merge[par]
+    t = t.balanced().morton_sorted()
+    # weights of the new leaves
+    old = tree.index
+    W = np.zeros((len(t.leaves), s.nmodes))
+    for i, (l, c) in enumerate(t.leaves):
+        if (l, c) in old:
+            W[i] = w[old[(l, c)]]
+        elif (l, c) in merge:
+            W[i] = restrict(s, w[merge[(l, c)]])
+        else:
+            path, cl, cc = [], l, c          # climb to the old leaf that covers this one
+            while (cl, cc) not in old:
+                path.append(_octant_of(cc, D))
+                cl, cc = cl - 1, tuple(x // 2 for x in cc)
+            wv = w[old[(cl, cc)]]
+            for o in reversed(path):
+                wv = prolong(s, wv, o)
+            W[i] = wv
+    stats = dict(refined=int(refine.sum()), merged=len(merge), leaves=len(t.leaves))
+    return t, W, stats
