@@ -151,6 +151,41 @@ int dg_project(dg_handle h, const double* prim, int64_t cell0, int64_t ncell, vo
  * for a null pointer or a cell range outside the grid.  Async. */
 int dg_nodal(dg_handle h, const void* w, int64_t cell0, int64_t ncell, double* out);
 
+/* Dynamic refinement (Sec. 4.4; GLM handles, Legendre basis; DG_EUNSUPPORTED
+ * for Powell).  fields: bit v set monitors conserved variable v (0 rho,
+ * 1-3 m, 4 E, 5-7 B, 8 psi); the paper refines on rho and B (0xE1).
+ *
+ * dg_amr_indicator: S[cell] (device FP64, ncells) = the largest smoothness
+ * indicator S_alpha(u) = sum_{k=1}^{d} 2^(2k-1) int (d^k u/dxi_alpha^k)^2 over
+ * the monitored fields and the directions.  Async. */
+int dg_amr_indicator(dg_handle h, const void* w, uint32_t fields, double* S);
+
+/* dg_amr_plan: one regrid decision for the state w.  A leaf is split when its
+ * indicator exceeds 2 s_tilde and its level is below max_level; a complete
+ * group of 2^dim sibling leaves none of which is split merges into its parent
+ * when the parent's polynomial (the L2 restriction of the children) has an
+ * indicator below s_tilde / 2.  A merge that would leave a face neighbour two
+ * levels finer is dropped; other 2:1 violations are removed by refinement.
+ * The handle keeps the plan (new leaves in Morton order and the transfer
+ * map); *n_new (host) receives the number of new leaves.  A uniform grid's
+ * leaves are its level-0 cells.  Synchronous. */
+int dg_amr_plan(dg_handle h, const void* w, uint32_t fields, double s_tilde, int32_t max_level, int64_t* n_new);
+
+/* dg_amr_leaves: the planned leaves, level[n_new] and ijk[n_new][3] (host,
+ * caller-allocated), the input of a new handle's dg_mesh (DG_MESH_OCTREE,
+ * same base grid). */
+int dg_amr_leaves(dg_handle h, int8_t* level /*[host]*/, int32_t* ijk /*[host]*/);
+
+/* dg_amr_transfer: weights of the new leaves from the old state w_old: kept
+ * leaves copied, split leaves prolongated (L2 projection of the parent's
+ * polynomial onto each child, through every level of a split), merged groups
+ * restricted (L2 projection of the children onto the parent); exact for the
+ * polynomial space and conservative.  h_new must have been created from
+ * dg_amr_leaves of h_old's plan with the same dimension, degree, scheme and
+ * precision (DG_EINVAL otherwise).  Waits for h_old's stream, runs on
+ * h_new's; synchronous. */
+int dg_amr_transfer(dg_handle h_old, const void* w_old, dg_handle h_new, void* w_new);
+
 /* Time step of the state w (eq. cfl; Powell cap eq. powell_dt; GLM c_h and
  * kappa = c_h^2 / c_p^2 of Sec. 4.1.5).  Synchronous; outputs on the host.
  * DG_ENONFINITE if the state's signal speed is not finite; DG_ECH (outputs

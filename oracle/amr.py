@@ -83,17 +83,18 @@ class Octree:
         return Octree(D, self.n0, out, self.box)
 
     def balance_violations(self):
-        """Leaves with a face neighbour more than one level finer (2:1 rule)."""
+        """Leaves with a face neighbour more than one level finer (2:1 rule).
+        A leaf whose neighbour is coarser (by any number of levels) is not in
+        violation itself: the coarser side is, and refining it is what
+        restores the rule."""
         bad = np.zeros(len(self.leaves), dtype=bool)
         for i, (l, c) in enumerate(self.leaves):
             for a in range(self.D):
                 for s in (-1, 1):
                     nc = list(c)
                     nc[a] += s
-                    nc = tuple(nc)
-                    if self.is_leaf(l, nc):
-                        continue
-                    if l > 0 and self.is_leaf(l - 1, tuple(x // 2 for x in self.wrap(l, nc))):
+                    nc = self.wrap(l, tuple(nc))
+                    if any(self.is_leaf(l - k, tuple(x >> k for x in nc)) for k in range(l + 1)):
                         continue
                     # finer region: all children adjacent to this face must be leaves
                     for ch in self._adjacent_children(l, nc, a, s):

@@ -12,11 +12,13 @@ DG_LIM_TVB, DG_LIM_CHAR, DG_LIM_POS, DG_LIM_LEARNED = 1, 2, 4, 8
 DG_MESH_UNIFORM, DG_MESH_OCTREE = 0, 1
 DG_POWELL_Q_MEAN, DG_POWELL_Q_INTERP = 0, 1
 
-EXPORTS = ["dg_init", "dg_layout", "dg_proj_points", "dg_project", "dg_nodal", "dg_dt", "dg_rhs", "dg_rhs_noalloc", "dg_limit",
+EXPORTS = ["dg_init", "dg_layout", "dg_proj_points", "dg_project", "dg_nodal", "dg_amr_indicator", "dg_amr_plan",
+           "dg_amr_leaves", "dg_amr_transfer", "dg_dt", "dg_rhs", "dg_rhs_noalloc", "dg_limit",
            "dg_step",
            "dg_mlp_scale", "dg_mlp_set", "dg_mlp_get", "dg_mlp_features", "dg_mlp_labels", "dg_mlp_record", "dg_mlp_forward",
            "dg_mlp_grad", "dg_mlp_train", "dg_time_kernel", "dg_autotune", "dg_last_error", "dg_destroy"]
 MLP_NPARAM = 24833
+AMR_FIELDS_RHO_B = (1 << 0) | (1 << 5) | (1 << 6) | (1 << 7)   # the paper's refinement fields
 
 
 class dg_params(ctypes.Structure):
@@ -71,6 +73,10 @@ def load_library(path=LIB_PATH):
     lib.dg_proj_points.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(I64)]
     lib.dg_project.argtypes = [P, P, I64, I64, P]
     lib.dg_nodal.argtypes = [P, P, I64, I64, P]
+    lib.dg_amr_indicator.argtypes = [P, P, ctypes.c_uint32, P]
+    lib.dg_amr_plan.argtypes = [P, P, ctypes.c_uint32, D, I32, ctypes.POINTER(I64)]
+    lib.dg_amr_leaves.argtypes = [P, ctypes.POINTER(ctypes.c_int8), ctypes.POINTER(I32)]
+    lib.dg_amr_transfer.argtypes = [P, P, P, P]
     lib.dg_dt.argtypes = [P, P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)]
     lib.dg_rhs.argtypes = [P, P, P, D, D]
     lib.dg_rhs_noalloc.argtypes = [P, P, P, D, D]
@@ -119,6 +125,11 @@ class DG:
         self.torch = torch
         self.lib = load_library()
         self.dim, self.degree, self.divb, self.precision = dim, degree, divb, precision
+        # the settings a regridded handle inherits
+        self._kwargs = dict(divb=divb, precision=precision, limiter=limiter, gamma=gamma, cfl=cfl, cfl_glm=cfl_glm,
+                            glm_cr=glm_cr, glm_ch_fixed=glm_ch_fixed, tvb_Mtilde=tvb_Mtilde, tvb_beta=tvb_beta,
+                            tvb_eps=tvb_eps, eps_rho=eps_rho, eps_p=eps_p, powell_eta=powell_eta, mlp_lo=mlp_lo,
+                            mlp_hi=mlp_hi, stream=stream, rk_stages=rk_stages, powell_q=powell_q)
         p = dg_params(dim, degree, divb, precision, rk_stages, limiter, powell_q, gamma, cfl, cfl_glm, glm_cr,
                       glm_ch_fixed,
                       tvb_Mtilde, tvb_beta, tvb_eps, eps_rho, eps_p, powell_eta, mlp_lo, mlp_hi)
@@ -140,6 +151,7 @@ class DG:
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         self.stream = stream
+        self._kwargs["stream"] = stream
         h = ctypes.c_void_p()
         rc = self.lib.dg_init(ctypes.byref(p), ctypes.byref(m), ctypes.c_void_p(stream), ctypes.byref(h))
         if rc != DG_OK:
@@ -198,6 +210,30 @@ class DG:
         assert out.dtype == torch.float64 and out.is_contiguous() and out.numel() >= nvar * npts * ncell
         self._check(self.lib.dg_nodal(self.h, _ptr(w), cell0, ncell, _ptr(out)))
         return out
+
+    # ---------------------------------------------------------------- dynamic refinement
+    def amr_indicator(self, w, fields=AMR_FIELDS_RHO_B):
+        S = self.torch.empty(self.ncells, dtype=self.torch.float64, device="cuda")
+        self._check(self.lib.dg_amr_indicator(self.h, _ptr(w), fields, _ptr(S)))
+        return S
+
+    def regrid(self, w, s_tilde=0.03, max_level=8, fields=AMR_FIELDS_RHO_B, **overrides):
+        """One regrid (dg_amr_plan, dg_amr_leaves, a new handle on the planned
+        leaves with this handle's settings updated by `overrides` (an octree
+        handle needs glm_ch_fixed), dg_amr_transfer).  Returns the new handle
+        and its state."""
+        import numpy as np
+        n = ctypes.c_int64()
+        self._check(self.lib.dg_amr_plan(self.h, _ptr(w), fields, s_tilde, max_level, ctypes.byref(n)))
+        level = np.zeros(n.value, dtype=np.int8)
+        ijk = np.zeros((n.value, 3), dtype=np.int32)
+        self._check(self.lib.dg_amr_leaves(self.h, level.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
+                                           ijk.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        new = DG(self.dim, self.degree, tuple(self.n), box=tuple(self.box), octree=(level, ijk),
+                 **{**self._kwargs, **overrides})
+        w_new = new.empty_state()
+        self._check(self.lib.dg_amr_transfer(self.h, _ptr(w), new.h, _ptr(w_new)))
+        return new, w_new
 
     def dt(self, w):
         dt, ch, k = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()

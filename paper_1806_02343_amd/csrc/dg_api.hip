@@ -3,6 +3,7 @@
 // face kernel -> cell kernel -> limiters), all ordered on one HIP stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -52,6 +53,12 @@ struct dg_handle_s {
   const void* graph_w = nullptr;
   std::vector<int8_t> h_level;   // octree: host copy of the leaf levels
   std::vector<int32_t> h_ijk;    // octree: host copy of the leaf coordinates
+  // last regrid plan (dg_amr_plan): new leaves in Morton order, and per new
+  // leaf (kind, source, depth, octant path); kids: old leaves of each merged
+  // group in octant order
+  std::vector<int8_t> amr_level;
+  std::vector<int32_t> amr_ijk, amr_map, amr_kids;
+  int64_t amr_nold = 0;
   double hmin = 0.0;
   size_t elem = 8;
   int device = 0;             // HIP device current at dg_init
@@ -980,6 +987,356 @@ int dg_mlp_train(dg_handle h, const void* X, const float* y, int64_t nrows, int3
 }
 
 const char* dg_last_error(dg_handle h) { return h ? h->err.c_str() : g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// Dynamic refinement (Sec. 4.4)
+
+namespace {
+
+using LeafKey = uint64_t;
+inline LeafKey leaf_key(int l, int64_t i, int64_t j, int64_t k) {
+  return ((uint64_t)l << 60) | ((uint64_t)i << 40) | ((uint64_t)j << 20) | (uint64_t)k;
+}
+
+struct LeafSet {
+  int D = 3;
+  int64_t n0[3] = {1, 1, 1};
+  std::vector<int8_t> lev;
+  std::vector<int32_t> ijk;  // [C][3]
+  std::unordered_map<LeafKey, int64_t> index;
+  void build_index() {
+    index.clear();
+    index.reserve(lev.size() * 2);
+    for (size_t c = 0; c < lev.size(); ++c) index.emplace(leaf_key(lev[c], ijk[3 * c], ijk[3 * c + 1], ijk[3 * c + 2]), (int64_t)c);
+  }
+  int64_t ncell(int l, int a) const { return a < D ? (n0[a] << l) : 1; }
+  bool is_leaf(int l, const int64_t* c) const {
+    if (l < 0) return false;
+    int64_t w[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) {
+      const int64_t n = ncell(l, a);
+      w[a] = ((c[a] % n) + n) % n;
+    }
+    return index.count(leaf_key(l, w[0], w[1], w[2])) > 0;
+  }
+  // leaves with a face neighbour more than one level finer (2:1 rule)
+  std::vector<char> balance_violations() const {
+    const int64_t C = (int64_t)lev.size();
+    std::vector<char> bad((size_t)C, 0);
+    for (int64_t i = 0; i < C; ++i) {
+      const int l = lev[i];
+      for (int a = 0; a < D; ++a)
+        for (int sg = -1; sg <= 1; sg += 2) {
+          int64_t nc[3] = {ijk[3 * i], ijk[3 * i + 1], ijk[3 * i + 2]};
+          nc[a] += sg;
+          // a coarser neighbour (any number of levels) is the coarse side's
+          // violation, not this leaf's
+          bool covered = false;
+          for (int k = 0; k <= l && !covered; ++k) {
+            int64_t pc[3] = {0, 0, 0};
+            for (int b = 0; b < D; ++b) {
+              const int64_t n = ncell(l, b);
+              pc[b] = (((nc[b] % n) + n) % n) >> k;
+            }
+            covered = is_leaf(l - k, pc);
+          }
+          if (covered) continue;
+          int tang[2], nt = 0;
+          for (int b = 0; b < D; ++b)
+            if (b != a) tang[nt++] = b;
+          for (int q = 0; q < (1 << (D - 1)); ++q) {
+            int64_t ch[3] = {0, 0, 0};
+            for (int b = 0; b < D; ++b) {
+              const int64_t n = ncell(l, b);
+              ch[b] = 2 * (((nc[b] % n) + n) % n);
+            }
+            ch[a] += sg > 0 ? 0 : 1;
+            for (int t = 0; t < nt; ++t) ch[tang[t]] += (q >> t) & 1;
+            if (!is_leaf(l + 1, ch)) bad[(size_t)i] = 1;
+          }
+        }
+    }
+    return bad;
+  }
+  void refine(const std::vector<char>& flag) {
+    std::vector<int8_t> nl;
+    std::vector<int32_t> nc;
+    for (size_t c = 0; c < lev.size(); ++c) {
+      if (!flag[c]) {
+        nl.push_back(lev[c]);
+        nc.insert(nc.end(), {ijk[3 * c], ijk[3 * c + 1], ijk[3 * c + 2]});
+        continue;
+      }
+      for (int off = 0; off < (1 << D); ++off) {
+        nl.push_back((int8_t)(lev[c] + 1));
+        for (int a = 0; a < 3; ++a) nc.push_back(a < D ? 2 * ijk[3 * c + a] + ((off >> a) & 1) : 0);
+      }
+    }
+    lev.swap(nl);
+    ijk.swap(nc);
+    build_index();
+  }
+  void morton_sort() {
+    int lmax = 0;
+    for (int8_t l : lev) lmax = std::max(lmax, (int)l);
+    const int64_t C = (int64_t)lev.size();
+    std::vector<std::pair<uint64_t, int64_t>> key((size_t)C);
+    for (int64_t c = 0; c < C; ++c) {
+      uint64_t k = 0;
+      const int sh = lmax - lev[c];
+      for (int b = 0; b < 21; ++b)
+        for (int a = 0; a < D; ++a) k |= (((uint64_t)ijk[3 * c + a] << sh) >> b & 1ull) << (b * D + a);
+      key[(size_t)c] = {k, c};
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<int8_t> nl((size_t)C);
+    std::vector<int32_t> nc((size_t)C * 3);
+    for (int64_t c = 0; c < C; ++c) {
+      const int64_t o = key[(size_t)c].second;
+      nl[(size_t)c] = lev[(size_t)o];
+      for (int a = 0; a < 3; ++a) nc[(size_t)c * 3 + a] = ijk[(size_t)o * 3 + a];
+    }
+    lev.swap(nl);
+    ijk.swap(nc);
+    build_index();
+  }
+};
+
+int octant_of(const int32_t* c, int D) {
+  int o = 0;
+  for (int a = 0; a < D; ++a) o |= (c[a] & 1) << a;
+  return o;
+}
+
+}  // namespace
+
+int dg_amr_indicator(dg_handle h, const void* w, uint32_t fields, double* S) {
+  if (int r = valid_state(h, w)) return r;
+  if (!S) return fail(h, DG_EINVAL, "null S");
+  if (h->p.divb != DG_GLM) return fail(h, DG_EUNSUPPORTED, "dynamic refinement is built for the Legendre basis (GLM)");
+  if (fields == 0 || fields >= (1u << 9)) return fail(h, DG_EINVAL, "fields: a non-empty mask of the 9 variables");
+  h->L->amr_smooth(w, h->g, fields, S, h->stream);
+  return check_launch(h, "amr indicator");
+}
+
+int dg_amr_plan(dg_handle h, const void* w, uint32_t fields, double s_tilde, int32_t max_level, int64_t* n_new) {
+  if (int r = valid_state(h, w)) return r;
+  if (!n_new) return fail(h, DG_EINVAL, "null n_new");
+  if (h->p.divb != DG_GLM) return fail(h, DG_EUNSUPPORTED, "dynamic refinement is built for the Legendre basis (GLM)");
+  if (fields == 0 || fields >= (1u << 9)) return fail(h, DG_EINVAL, "fields: a non-empty mask of the 9 variables");
+  if (!(s_tilde > 0.0) || !std::isfinite(s_tilde)) return fail(h, DG_EINVAL, "s_tilde must be positive");
+  if (max_level < 0 || max_level > 18) return fail(h, DG_EINVAL, "max_level must be 0..18");
+  const int D = h->p.dim, NO = 1 << D;
+  const int64_t C = h->g.C;
+  LeafSet old;
+  old.D = D;
+  old.n0[0] = h->g.n0; old.n0[1] = h->g.n1; old.n0[2] = h->g.n2;
+  if (!h->h_level.empty()) {
+    old.lev = h->h_level;
+    old.ijk = h->h_ijk;
+  } else {  // uniform grid: level-0 leaves, index i + n0 (j + n1 k)
+    old.lev.assign((size_t)C, 0);
+    old.ijk.resize((size_t)C * 3);
+    for (int64_t c = 0; c < C; ++c) {
+      old.ijk[3 * c] = (int32_t)(c % old.n0[0]);
+      old.ijk[3 * c + 1] = (int32_t)((c / old.n0[0]) % old.n0[1]);
+      old.ijk[3 * c + 2] = (int32_t)(c / (old.n0[0] * old.n0[1]));
+    }
+  }
+  old.build_index();
+  // indicators of the leaves
+  std::vector<double> S((size_t)C);
+  double* dS = nullptr;
+  if (int r = check_hip(h, hipMalloc(&dS, (size_t)C * sizeof(double)), "amr S")) return r;
+  h->L->amr_smooth(w, h->g, fields, dS, h->stream);
+  int rc = check_launch(h, "amr indicator");
+  if (!rc) rc = check_hip(h, hipMemcpyAsync(S.data(), dS, (size_t)C * 8, hipMemcpyDeviceToHost, h->stream), "S copy");
+  if (!rc) rc = check_hip(h, hipStreamSynchronize(h->stream), "sync");
+  (void)hipFree(dS);
+  if (rc) return rc;
+  std::vector<char> refine((size_t)C, 0);
+  for (int64_t c = 0; c < C; ++c) refine[(size_t)c] = (S[(size_t)c] > 2.0 * s_tilde) && old.lev[(size_t)c] < max_level;
+  // complete sibling groups with no member marked for refinement
+  std::unordered_map<LeafKey, std::vector<int32_t>> groups;
+  for (int64_t c = 0; c < C; ++c) {
+    const int l = old.lev[(size_t)c];
+    if (l == 0) continue;
+    const LeafKey pk = leaf_key(l - 1, old.ijk[3 * c] >> 1, old.ijk[3 * c + 1] >> 1, old.ijk[3 * c + 2] >> 1);
+    auto& gv = groups[pk];
+    if (gv.empty()) gv.assign((size_t)NO, -1);
+    gv[(size_t)octant_of(&old.ijk[3 * c], D)] = (int32_t)c;
+  }
+  std::vector<LeafKey> gkey;
+  std::vector<int32_t> gkids;
+  for (auto& kv : groups) {
+    bool ok = true;
+    for (int32_t k : kv.second) ok = ok && k >= 0 && !refine[(size_t)k];
+    if (!ok) continue;
+    gkey.push_back(kv.first);
+    gkids.insert(gkids.end(), kv.second.begin(), kv.second.end());
+  }
+  const int64_t NG = (int64_t)gkey.size();
+  std::vector<double> Sp((size_t)NG);
+  if (NG > 0) {
+    int32_t* dk = nullptr;
+    double* dSp = nullptr;
+    rc = check_hip(h, hipMalloc(&dk, gkids.size() * 4), "amr groups");
+    if (!rc) rc = check_hip(h, hipMalloc(&dSp, (size_t)NG * 8), "amr Sp");
+    if (!rc) rc = check_hip(h, hipMemcpyAsync(dk, gkids.data(), gkids.size() * 4, hipMemcpyHostToDevice, h->stream), "groups");
+    if (!rc) {
+      h->L->amr_parent_smooth(w, h->g, fields, dk, NG, dSp, h->stream);
+      rc = check_launch(h, "amr parent indicator");
+    }
+    if (!rc) rc = check_hip(h, hipMemcpyAsync(Sp.data(), dSp, (size_t)NG * 8, hipMemcpyDeviceToHost, h->stream), "Sp");
+    if (!rc) rc = check_hip(h, hipStreamSynchronize(h->stream), "sync");
+    (void)hipFree(dk);
+    (void)hipFree(dSp);
+    if (rc) return rc;
+  }
+  std::unordered_map<LeafKey, int64_t> merge;  // parent key -> group row
+  for (int64_t gi = 0; gi < NG; ++gi)
+    if (Sp[(size_t)gi] < 0.5 * s_tilde) merge.emplace(gkey[(size_t)gi], gi);
+  // new leaves; a merge that breaks the 2:1 balance is dropped, the rest is
+  // balanced by refinement
+  LeafSet nw;
+  for (;;) {
+    nw = LeafSet();
+    nw.D = D;
+    for (int a = 0; a < 3; ++a) nw.n0[a] = old.n0[a];
+    for (int64_t c = 0; c < C; ++c) {
+      const int l = old.lev[(size_t)c];
+      const int32_t* x = &old.ijk[3 * c];
+      if (l > 0 && merge.count(leaf_key(l - 1, x[0] >> 1, x[1] >> 1, x[2] >> 1))) continue;
+      if (refine[(size_t)c]) {
+        for (int off = 0; off < NO; ++off) {
+          nw.lev.push_back((int8_t)(l + 1));
+          for (int a = 0; a < 3; ++a) nw.ijk.push_back(a < D ? 2 * x[a] + ((off >> a) & 1) : 0);
+        }
+      } else {
+        nw.lev.push_back((int8_t)l);
+        nw.ijk.insert(nw.ijk.end(), {x[0], x[1], x[2]});
+      }
+    }
+    for (auto& kv : merge) {
+      const int32_t* x0 = &old.ijk[3 * (int64_t)gkids[(size_t)kv.second * NO]];
+      nw.lev.push_back((int8_t)(old.lev[(size_t)gkids[(size_t)kv.second * NO]] - 1));
+      nw.ijk.insert(nw.ijk.end(), {x0[0] >> 1, x0[1] >> 1, x0[2] >> 1});
+    }
+    nw.build_index();
+    const std::vector<char> bad = nw.balance_violations();
+    bool dropped = false;
+    for (size_t c = 0; c < bad.size(); ++c) {
+      if (!bad[c]) continue;
+      auto it = merge.find(leaf_key(nw.lev[c], nw.ijk[3 * c], nw.ijk[3 * c + 1], nw.ijk[3 * c + 2]));
+      if (it != merge.end()) {
+        merge.erase(it);
+        dropped = true;
+      }
+    }
+    if (!dropped) break;
+  }
+  for (int it = 0;; ++it) {
+    const std::vector<char> bad = nw.balance_violations();
+    bool any = false;
+    for (char b : bad) any = any || b;
+    if (!any) break;
+    if (it >= 20) return fail(h, DG_EINVAL, "amr: 2:1 balance did not converge");
+    nw.refine(bad);
+  }
+  nw.morton_sort();
+  // transfer map
+  const int64_t NN = (int64_t)nw.lev.size();
+  std::vector<int32_t> map((size_t)NN * 4, 0), kids;
+  std::unordered_map<int64_t, int32_t> krow;
+  for (int64_t i = 0; i < NN; ++i) {
+    int l = nw.lev[(size_t)i];
+    int64_t x[3] = {nw.ijk[3 * i], nw.ijk[3 * i + 1], nw.ijk[3 * i + 2]};
+    auto hit = old.index.find(leaf_key(l, x[0], x[1], x[2]));
+    if (hit != old.index.end()) {
+      map[4 * i] = 0;
+      map[4 * i + 1] = (int32_t)hit->second;
+      continue;
+    }
+    auto mg = merge.find(leaf_key(l, x[0], x[1], x[2]));
+    if (mg != merge.end()) {
+      auto kr = krow.find(mg->second);
+      int32_t row;
+      if (kr == krow.end()) {
+        row = (int32_t)(kids.size() / NO);
+        kids.insert(kids.end(), gkids.begin() + mg->second * NO, gkids.begin() + (mg->second + 1) * NO);
+        krow.emplace(mg->second, row);
+      } else {
+        row = kr->second;
+      }
+      map[4 * i] = 2;
+      map[4 * i + 1] = row;
+      continue;
+    }
+    uint32_t path = 0;
+    int depth = 0;
+    for (;;) {
+      const int32_t cx[3] = {(int32_t)x[0], (int32_t)x[1], (int32_t)x[2]};
+      path |= (uint32_t)octant_of(cx, D) << (3 * depth);
+      ++depth;
+      --l;
+      for (int a = 0; a < 3; ++a) x[a] >>= 1;
+      if (l < 0 || depth > 10) return fail(h, DG_EINVAL, "amr: a new leaf has no ancestor among the old leaves");
+      auto anc = old.index.find(leaf_key(l, x[0], x[1], x[2]));
+      if (anc != old.index.end()) {
+        map[4 * i] = 1;
+        map[4 * i + 1] = (int32_t)anc->second;
+        map[4 * i + 2] = depth;
+        map[4 * i + 3] = (int32_t)path;  // bits 3k: the octant k levels above the new leaf (top = highest)
+        break;
+      }
+    }
+  }
+  h->amr_level = nw.lev;
+  h->amr_ijk = nw.ijk;
+  h->amr_map = map;
+  h->amr_kids = kids;
+  h->amr_nold = C;
+  *n_new = NN;
+  return DG_OK;
+}
+
+int dg_amr_leaves(dg_handle h, int8_t* level, int32_t* ijk) {
+  if (!h) return DG_EINVAL;
+  if (h->amr_level.empty()) return fail(h, DG_EINVAL, "no regrid plan: call dg_amr_plan first");
+  if (!level || !ijk) return fail(h, DG_EINVAL, "null output");
+  std::memcpy(level, h->amr_level.data(), h->amr_level.size());
+  std::memcpy(ijk, h->amr_ijk.data(), h->amr_ijk.size() * 4);
+  return DG_OK;
+}
+
+int dg_amr_transfer(dg_handle h_old, const void* w_old, dg_handle h_new, void* w_new) {
+  if (int r = valid_state(h_old, w_old)) return r;
+  if (int r = valid_state(h_new, w_new)) return r;
+  if (h_old->amr_level.empty()) return fail(h_old, DG_EINVAL, "no regrid plan: call dg_amr_plan first");
+  if (h_old->amr_nold != h_old->g.C) return fail(h_old, DG_EINVAL, "the plan belongs to another leaf set");
+  if (h_new->p.dim != h_old->p.dim || h_new->p.degree != h_old->p.degree || h_new->p.divb != h_old->p.divb ||
+      h_new->p.precision != h_old->p.precision)
+    return fail(h_old, DG_EINVAL, "the new handle differs in dimension, degree, scheme or precision");
+  if (h_new->h_level != h_old->amr_level || h_new->h_ijk != h_old->amr_ijk)
+    return fail(h_old, DG_EINVAL, "the new handle's leaves are not the plan's (dg_amr_leaves)");
+  const int NO = 1 << h_old->p.dim;
+  const int64_t NN = (int64_t)h_old->amr_level.size();
+  int32_t *dmap = nullptr, *dk = nullptr;
+  int rc = check_hip(h_old, hipStreamSynchronize(h_old->stream), "sync old");
+  if (!rc) rc = check_hip(h_old, hipMalloc(&dmap, h_old->amr_map.size() * 4), "amr map");
+  if (!rc) rc = check_hip(h_old, hipMalloc(&dk, std::max<size_t>(h_old->amr_kids.size(), (size_t)NO) * 4), "amr kids");
+  if (!rc) rc = check_hip(h_old, hipMemcpy(dmap, h_old->amr_map.data(), h_old->amr_map.size() * 4, hipMemcpyHostToDevice), "map");
+  if (!rc && !h_old->amr_kids.empty())
+    rc = check_hip(h_old, hipMemcpy(dk, h_old->amr_kids.data(), h_old->amr_kids.size() * 4, hipMemcpyHostToDevice), "kids");
+  if (!rc) {
+    h_old->L->amr_transfer(w_old, h_old->g.ld, w_new, h_new->g.ld, dmap, dk, NN, h_new->stream);
+    rc = check_launch(h_old, "amr transfer");
+  }
+  if (!rc) rc = check_hip(h_old, hipStreamSynchronize(h_new->stream), "sync new");
+  (void)hipFree(dmap);
+  (void)hipFree(dk);
+  return rc;
+}
 
 void dg_destroy(dg_handle h) {
   if (!h) return;

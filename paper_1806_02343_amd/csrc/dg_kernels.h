@@ -92,6 +92,17 @@ struct Launcher {
   // Powell dt cap: per-face normal-field jumps then per-cell rate
   virtual void powell_cap(const void* w, void* jsum, const Grid& g, Scal* sc, const SchemeParams& sp,
                           hipStream_t s) = 0;
+  // dynamic refinement (Sec. 4.4), Legendre bases: largest smoothness
+  // indicator over the fields in the bit mask and the directions, per leaf
+  // (S) or per sibling group restricted to its parent (groups[g][2^D] leaf
+  // indices in octant order); transfer of the weights to a new leaf set
+  // (map[i] = kind (0 copy, 1 prolongation, 2 restriction), source (leaf, or
+  // group row of kids), depth, octant path 3 bits per level from the top)
+  virtual void amr_smooth(const void* w, const Grid& g, uint32_t fields, double* S, hipStream_t s) = 0;
+  virtual void amr_parent_smooth(const void* w, const Grid& g, uint32_t fields, const int32_t* groups,
+                                 int64_t ngroups, double* Sp, hipStream_t s) = 0;
+  virtual void amr_transfer(const void* w_old, int64_t ld_old, void* w_new, int64_t ld_new, const int32_t* map,
+                            const int32_t* kids, int64_t nnew, hipStream_t s) = 0;
   // conserved state at the points of the projection rule: out[var][point][cell - cell0]
   virtual void nodal(const void* w, int64_t cell0, int64_t ncell, double* out, const Grid& g, hipStream_t s) = 0;
   virtual void project(const double* prim, int64_t cell0, int64_t ncell, void* w, const Grid& g,

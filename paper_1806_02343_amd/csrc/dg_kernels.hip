@@ -2028,6 +2028,114 @@ struct ProjTile {
   static constexpr int TC = TC0 > 16 ? 16 : (TC0 < 1 ? 1 : TC0);
 };
 
+// Dynamic refinement (Sec. 4.4) on the Legendre basis, one thread per leaf
+// (or group).  The smoothness indicator of a field and direction is the
+// quadratic form w^T SQ_a w of its weights; the largest over the fields of
+// the mask and the directions is stored (NaN propagates).
+template <int N, int D>
+__device__ __forceinline__ double amr_smax(const double (&u)[N], const double* __restrict__ SQ, double smax) {
+  for (int a = 0; a < D; ++a) {
+    double q = 0.0;
+    for (int n = 0; n < N; ++n) {
+      double r = 0.0;
+      for (int m = 0; m < N; ++m) r += SQ[(a * N + n) * N + m] * u[m];
+      q += u[n] * r;
+    }
+    smax = (q > smax || q != q) ? q : smax;
+  }
+  return smax;
+}
+
+template <typename T, int D, int DEG>
+__global__ void __launch_bounds__(256) k_amr_smooth(const T* __restrict__ w, int64_t ld, int64_t C, uint32_t fields,
+                                                    const double* __restrict__ SQ, double* __restrict__ S) {
+  constexpr int N = Cfg<D, DEG, GLM>::N;
+  const int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (K >= C) return;
+  double smax = 0.0;
+  for (int v = 0; v < 9; ++v) {
+    if (!((fields >> v) & 1u)) continue;
+    double u[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) u[n] = (double)w[(int64_t)(v * N + n) * ld + K];
+    smax = amr_smax<N, D>(u, SQ, smax);
+  }
+  S[K] = smax;
+}
+
+template <typename T, int D, int DEG>
+__global__ void __launch_bounds__(256) k_amr_parent_smooth(const T* __restrict__ w, int64_t ld, uint32_t fields,
+                                                           const int32_t* __restrict__ groups, int64_t ngroups,
+                                                           const double* __restrict__ SQ,
+                                                           const double* __restrict__ RES, double* __restrict__ Sp) {
+  constexpr int N = Cfg<D, DEG, GLM>::N, NO = 1 << D;
+  const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi >= ngroups) return;
+  double smax = 0.0;
+  for (int v = 0; v < 9; ++v) {
+    if (!((fields >> v) & 1u)) continue;
+    double u[N];
+#pragma unroll
+    for (int m = 0; m < N; ++m) u[m] = 0.0;
+    for (int o = 0; o < NO; ++o) {
+      const int64_t K = groups[gi * NO + o];
+      for (int n = 0; n < N; ++n) {
+        const double x = (double)w[(int64_t)(v * N + n) * ld + K];
+#pragma unroll
+        for (int m = 0; m < N; ++m) u[m] += RES[(o * N + m) * N + n] * x;
+      }
+    }
+    smax = amr_smax<N, D>(u, SQ, smax);
+  }
+  Sp[gi] = smax;
+}
+
+template <typename T, int D, int DEG>
+__global__ void __launch_bounds__(256) k_amr_transfer(const T* __restrict__ wo, int64_t ldo, T* __restrict__ wn,
+                                                      int64_t ldn, const int32_t* __restrict__ map,
+                                                      const int32_t* __restrict__ kids, int64_t nnew,
+                                                      const double* __restrict__ PRO,
+                                                      const double* __restrict__ RES) {
+  constexpr int N = Cfg<D, DEG, GLM>::N, NO = 1 << D;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nnew) return;
+  const int kind = map[4 * i], depth = map[4 * i + 2];
+  const int64_t src = map[4 * i + 1];
+  const uint32_t path = (uint32_t)map[4 * i + 3];
+  for (int v = 0; v < 9; ++v) {
+    double u[N];
+    if (kind == 2) {
+#pragma unroll
+      for (int m = 0; m < N; ++m) u[m] = 0.0;
+      for (int o = 0; o < NO; ++o) {
+        const int64_t K = kids[src * NO + o];
+        for (int n = 0; n < N; ++n) {
+          const double x = (double)wo[(int64_t)(v * N + n) * ldo + K];
+#pragma unroll
+          for (int m = 0; m < N; ++m) u[m] += RES[(o * N + m) * N + n] * x;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int n = 0; n < N; ++n) u[n] = (double)wo[(int64_t)(v * N + n) * ldo + src];
+      for (int l = 0; l < (kind == 1 ? depth : 0); ++l) {
+        const int o = (int)((path >> (3 * (depth - 1 - l))) & 7u);
+        double t[N];
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+          double acc = 0.0;
+          for (int n = 0; n < N; ++n) acc += PRO[(o * N + m) * N + n] * u[n];
+          t[m] = acc;
+        }
+#pragma unroll
+        for (int m = 0; m < N; ++m) u[m] = t[m];
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < N; ++m) wn[(int64_t)(v * N + m) * ldn + i] = (T)u[m];
+  }
+}
+
 // Conserved state at the points of the projection rule, one thread per
 // (cell, point); consecutive threads take consecutive cells of one point.
 template <typename T, int D, int DEG, int DIVB>
@@ -2243,6 +2351,7 @@ struct LauncherImpl : Launcher {
   std::vector<void*> bufs;
   DevTab<T> tb{};
   double *vpw = nullptr, *pvpw = nullptr, *minv64 = nullptr, *vp64 = nullptr, *pvp64 = nullptr;
+  double *sq64 = nullptr, *pro64 = nullptr, *res64 = nullptr;
   const T *mfv = nullptr, *mfg = nullptr, *mfl = nullptr;  // fragment-order tables of the matrix-core cell kernel
   const T *mgx = nullptr, *mlx = nullptr;                   // and its vector-ALU rows (modes 16..19)
   const T* ml1 = nullptr;                                   // lift of a constant over each -a face
@@ -2285,6 +2394,12 @@ struct LauncherImpl : Launcher {
     vp64 = (double*)d1;
     if ((e = up<double>(t.PVP, d1)) != hipSuccess) return e;
     pvp64 = (double*)d1;
+    if ((e = up<double>(t.SQ, d1)) != hipSuccess) return e;
+    sq64 = (double*)d1;
+    if ((e = up<double>(t.PRO, d1)) != hipSuccess) return e;
+    pro64 = (double*)d1;
+    if ((e = up<double>(t.RES, d1)) != hipSuccess) return e;
+    res64 = (double*)d1;
     if constexpr (DIVB == POWELL) {
       std::vector<double> fv, fg, fl, pv, pg, pl, gx, lx;
       mfma_tables<T, D, DEG>(t, fv, fg, fl, gx, lx);
@@ -2595,6 +2710,28 @@ struct LauncherImpl : Launcher {
       const int64_t nf = (int64_t)D * g.C;
       k_face_jump<T, D, DEG, DIVB><<<(int)((nf + 255) / 256), 256, 0, s>>>((const T*)w, (double*)jsum, tb, g, sp.gamma);
       k_powell_rate<T, D, DEG, DIVB><<<(int)((g.C + 255) / 256), 256, 0, s>>>((const T*)w, (const double*)jsum, tb, g, sc);
+    }
+  }
+  void amr_smooth(const void* w, const Grid& g, uint32_t fields, double* S, hipStream_t s) override {
+    if constexpr (DIVB == GLM) {
+      if (g.C > 0)
+        k_amr_smooth<T, D, DEG><<<(unsigned)((g.C + 255) / 256), 256, 0, s>>>((const T*)w, g.ld, g.C, fields, sq64, S);
+    }
+  }
+  void amr_parent_smooth(const void* w, const Grid& g, uint32_t fields, const int32_t* groups, int64_t ngroups,
+                         double* Sp, hipStream_t s) override {
+    if constexpr (DIVB == GLM) {
+      if (ngroups > 0)
+        k_amr_parent_smooth<T, D, DEG><<<(unsigned)((ngroups + 255) / 256), 256, 0, s>>>(
+            (const T*)w, g.ld, fields, groups, ngroups, sq64, res64, Sp);
+    }
+  }
+  void amr_transfer(const void* w_old, int64_t ld_old, void* w_new, int64_t ld_new, const int32_t* map,
+                    const int32_t* kids, int64_t nnew, hipStream_t s) override {
+    if constexpr (DIVB == GLM) {
+      if (nnew > 0)
+        k_amr_transfer<T, D, DEG><<<(unsigned)((nnew + 255) / 256), 256, 0, s>>>(
+            (const T*)w_old, ld_old, (T*)w_new, ld_new, map, kids, nnew, pro64, res64);
     }
   }
   void nodal(const void* w, int64_t cell0, int64_t ncell, double* out, const Grid& g, hipStream_t s) override {

@@ -222,6 +222,94 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
   if (n % 2) x[n / 2] = 0.0;
 }
 
+namespace {
+
+double poly1(const std::vector<double>& c, double x) {
+  double s = 0.0;
+  for (size_t i = c.size(); i-- > 0;) s = s * x + c[i];
+  return s;
+}
+
+std::vector<double> deriv1(const std::vector<double>& c) {
+  std::vector<double> r(c.size() > 1 ? c.size() - 1 : 1, 0.0);
+  for (size_t i = 1; i < c.size(); ++i) r[i - 1] = (double)i * c[i];
+  return r;
+}
+
+// Tables of the dynamic refinement (Sec. 4.4) on the Legendre product basis
+// phi_n = prod_a l_{e_a}(xi_a), from exact 1-D integrals (Gauss rules with
+// d + 1 points, exact for the degrees involved):
+//  SQ_a[n][m] = sum_{k=1..d} 2^(2k-1) int d^k phi_n/dxi_a^k d^k phi_m/dxi_a^k
+//  PRO_o[m][n] = <phi_m(eta), phi_n((eta + s_o)/2)> / <phi_m, phi_m>
+//  RES_o[m][n] = 2^-D <phi_n(eta), phi_m((eta + s_o)/2)> / <phi_m, phi_m>
+// (s_o = +-1 per axis from the bits of the octant o).
+void amr_tables(Tables& t) {
+  const int D = t.D, d = t.d, N = t.N, NO = 1 << D;
+  std::vector<double> x, w;
+  gauss_legendre(d + 1, x, w);
+  std::vector<std::vector<double>> lc(d + 1);
+  for (int k = 0; k <= d; ++k) lc[k] = leg_coeffs(k);
+  // 1-D factors
+  auto mass1 = [&](int e) { return 2.0 / (2.0 * e + 1.0); };
+  // derivative products: I[k][e][f] = int l_e^(k) l_f^(k)
+  std::vector<double> Id((size_t)(d + 1) * (d + 1) * (d + 1), 0.0);
+  for (int e = 0; e <= d; ++e)
+    for (int f = 0; f <= d; ++f) {
+      std::vector<double> ce = lc[e], cf = lc[f];
+      for (int k = 1; k <= d; ++k) {
+        ce = deriv1(ce);
+        cf = deriv1(cf);
+        double sacc = 0.0;
+        for (size_t q = 0; q < x.size(); ++q) sacc += w[q] * poly1(ce, x[q]) * poly1(cf, x[q]);
+        Id[((size_t)k * (d + 1) + e) * (d + 1) + f] = sacc;
+      }
+    }
+  // half-interval products: H[s][f][e] = int l_f(eta) l_e((eta + s)/2), s = -1 (0) or +1 (1)
+  std::vector<double> H((size_t)2 * (d + 1) * (d + 1), 0.0);
+  for (int sd = 0; sd < 2; ++sd)
+    for (int f = 0; f <= d; ++f)
+      for (int e = 0; e <= d; ++e) {
+        double sacc = 0.0;
+        for (size_t q = 0; q < x.size(); ++q)
+          sacc += w[q] * poly1(lc[f], x[q]) * poly1(lc[e], 0.5 * (x[q] + (sd ? 1.0 : -1.0)));
+        H[((size_t)sd * (d + 1) + f) * (d + 1) + e] = sacc;
+      }
+  const int* ex = t.expo.data();
+  t.SQ.assign((size_t)D * N * N, 0.0);
+  for (int a = 0; a < D; ++a)
+    for (int n = 0; n < N; ++n)
+      for (int m = 0; m < N; ++m) {
+        bool same = true;
+        double other = 1.0;
+        for (int b = 0; b < D; ++b) {
+          if (b == a) continue;
+          if (ex[3 * n + b] != ex[3 * m + b]) same = false;
+          else other *= mass1(ex[3 * n + b]);
+        }
+        if (!same) continue;
+        double sacc = 0.0;
+        for (int k = 1; k <= d; ++k)
+          sacc += std::ldexp(1.0, 2 * k - 1) * Id[((size_t)k * (d + 1) + ex[3 * n + a]) * (d + 1) + ex[3 * m + a]];
+        t.SQ[((size_t)a * N + n) * N + m] = sacc * other;
+      }
+  t.PRO.assign((size_t)NO * N * N, 0.0);
+  t.RES.assign((size_t)NO * N * N, 0.0);
+  for (int o = 0; o < NO; ++o)
+    for (int m = 0; m < N; ++m)
+      for (int n = 0; n < N; ++n) {
+        double pr = 1.0, rs = 1.0;
+        for (int b = 0; b < D; ++b) {
+          const int sd = (o >> b) & 1, em = ex[3 * m + b], en = ex[3 * n + b];
+          pr *= H[((size_t)sd * (d + 1) + em) * (d + 1) + en] / mass1(em);
+          rs *= 0.5 * H[((size_t)sd * (d + 1) + en) * (d + 1) + em] / mass1(em);
+        }
+        t.PRO[((size_t)o * N + m) * N + n] = pr;
+        t.RES[((size_t)o * N + m) * N + n] = rs;
+      }
+}
+
+}  // namespace
+
 bool build_tables(int D, int d, int divb, Tables& t, std::string& err) {
   if (D != 2 && D != 3) { err = "dim must be 2 or 3"; return false; }
   if (d < 1 || d > 3) { err = "degree must be 1..3"; return false; }
@@ -405,6 +493,7 @@ bool build_tables(int D, int d, int divb, Tables& t, std::string& err) {
     }
   }
   for (int m = 0; m < t.NMODES; ++m) t.Minv[m] = 1.0 / t.Mass[m];
+  amr_tables(t);
   return true;
 }
 

@@ -44,6 +44,10 @@ struct Tables {
   std::vector<double> VPW;             // [NPROJ][N]         w_p P_l(xi_p)
   std::vector<double> PVPW;            // [D(c)][NPROJ][NLDF] w_p Phi_c(xi_p)
   std::vector<double> wproj;           // [NPROJ] weights of the rule (sum 2^D)
+  // dynamic refinement (Sec. 4.4), Legendre basis
+  std::vector<double> SQ;              // [D][N][N] smoothness quadratic forms: S_a(u) = w^T SQ_a w
+  std::vector<double> PRO;             // [2^D][N][N] child o weights = PRO_o . parent weights
+  std::vector<double> RES;             // [2^D][N][N] parent weights = sum_o RES_o . child o weights
   std::vector<double> VP;              // [NPROJ][N]         P_l(xi_p)
   std::vector<double> PVP;             // [D(c)][NPROJ][NLDF] Phi_c(xi_p)
 };

@@ -136,3 +136,20 @@ def test_regrid_orszag_tang(divb):
     back = {lf: i for i, lf in enumerate(t3.leaves)}
     for i, lf in enumerate(t.leaves):
         assert np.allclose(w3[back[lf]], w[i], atol=1e-12 * np.abs(w).max())
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_balance_refines_the_coarse_side_only(D):
+    """A cell refined twice inside a uniform level-0 grid: the leaves next to
+    its level-2 children get refined once, the level-2 leaves are left as
+    they are, and the result has no face neighbours two levels apart."""
+    t = amr.Octree.uniform(D, 4)
+    t = t.refine(np.array([c == (1,) * D for _, c in t.leaves]))
+    t = t.refine(np.array([l == 1 and c == (2,) * D for l, c in t.leaves]))
+    deep = {lf for lf in t.leaves if lf[0] == 2}
+    bad = t.balance_violations()
+    assert all(t.leaves[i][0] == 0 for i in np.nonzero(bad)[0])      # only coarse leaves are flagged
+    tb = t.balanced()
+    assert max(l for l, _ in tb.leaves) == 2 and deep <= set(tb.leaves)
+    assert not tb.balance_violations().any()
+    tb.mesh()                                                        # builds (raises on a 2:1 violation)
