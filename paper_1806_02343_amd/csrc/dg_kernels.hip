@@ -1365,6 +1365,45 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(po
                                    sc, gamma, a0, b0, cdt, mode);
 }
 
+// Persistent form: one workgroup per CU stages every fragment table in LDS
+// (157 KB at 3-D degree 2 FP64) and its waves walk a contiguous, XCD-dealt
+// range of 16-cell tiles.  Built where the tables fit the 160 KB of LDS.
+template <typename T, int D, int DEG>
+struct PowellLds {
+  using S = MfmaShape<D, DEG>;
+  using P = PowellShape<D, DEG>;
+  static constexpr size_t bytes = (size_t)(S::SZ_V + S::SZ_G + S::SZ_L + P::SZ_PV + P::SZ_PG + P::SZ_PL) * sizeof(T);
+  static constexpr bool fits = bytes <= 160 * 1024;
+};
+
+template <typename T, int D, int DEG, int NW>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(powell_cell_waves_per_eu<T, D, DEG>())))
+    k_cell_mfma_powell_p(const T* w, const T* w0, T* out, const T* __restrict__ ff, const T* __restrict__ jp,
+                         const T* __restrict__ FV, const T* __restrict__ FG, const T* __restrict__ FL,
+                         const T* __restrict__ PVt, const T* __restrict__ PGt, const T* __restrict__ PLt,
+                         const T* __restrict__ Pmean, const T* __restrict__ Minv, Grid g, const Scal* __restrict__ sc,
+                         double gamma, double a0, double b0, double cdt, int mode) {
+  if constexpr (PowellLds<T, D, DEG>::fits) {
+    using S = MfmaShape<D, DEG>;
+    using P = PowellShape<D, DEG>;
+    __shared__ T sV[S::SZ_V], sG[S::SZ_G], sL[S::SZ_L], sPV[P::SZ_PV], sPG[P::SZ_PG], sPL[P::SZ_PL];
+    for (int i = threadIdx.x; i < S::SZ_V; i += 64 * NW) sV[i] = FV[i];
+    for (int i = threadIdx.x; i < S::SZ_G; i += 64 * NW) sG[i] = FG[i];
+    for (int i = threadIdx.x; i < S::SZ_L; i += 64 * NW) sL[i] = FL[i];
+    for (int i = threadIdx.x; i < P::SZ_PV; i += 64 * NW) sPV[i] = PVt[i];
+    for (int i = threadIdx.x; i < P::SZ_PG; i += 64 * NW) sPG[i] = PGt[i];
+    for (int i = threadIdx.x; i < P::SZ_PL; i += 64 * NW) sPL[i] = PLt[i];
+    __syncthreads();
+    const int64_t ntiles = (g.C + 15) / 16;
+    const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+    const int64_t t0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * per;
+    const int64_t t1 = t0 + per < ntiles ? t0 + per : ntiles;
+    for (int64_t t = t0 + (threadIdx.x >> 6); t < t1; t += NW)
+      cell_tile_mfma_powell<T, D, DEG>(t * 16, threadIdx.x & 63, w, w0, out, ff, jp, sV, sG, sL, sPV, sPG, sPL, Pmean,
+                                       Minv, g, sc, gamma, a0, b0, cdt, mode);
+  }
+}
+
 // Face kernel on octree meshes on the matrix cores: one wave per tile of 16
 // faces of one class (axis, left sub-face, right sub-face), so that both
 // trace tables (the full face or the quarter of the coarse side, Sec. 4.4
@@ -2410,6 +2449,15 @@ struct LauncherImpl : Launcher {
       if ((e = up<T>(pv, mpv)) != hipSuccess) return e;
       if ((e = up<T>(pg, mpg)) != hipSuccess) return e;
       if ((e = up<T>(pl, mpl)) != hipSuccess) return e;
+      if constexpr (PowellLds<T, D, DEG>::fits) {
+        int dev = 0, ncu = 0, bp = 0;
+        if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+        if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bp, k_cell_mfma_powell_p<T, D, DEG, 8>, 512, 0)) !=
+            hipSuccess)
+          return e;
+        persist_powell = bp * ncu;
+      }
     }
     if constexpr (DIVB == GLM) {
       // uniform grids: the matrix-core face kernels store face moments and
@@ -2551,6 +2599,7 @@ struct LauncherImpl : Launcher {
   // 8, 9: batched and persistent, the tables in LDS
   static constexpr int NVAR = 10;
   int persist_blocks[2] = {0, 0};      // resident workgroups of the persistent kernels (4 and 2 waves)
+  int persist_powell = 0;              // resident workgroups of the persistent Powell cell kernel (8 waves)
   int persist_blocks_amr[2] = {0, 0};  // the same on octree grids
   int pos_blocks = 0, maxsig_blocks = 0;
   template <int NW>
@@ -2596,6 +2645,18 @@ struct LauncherImpl : Launcher {
                           hipStream_t s) {
     if constexpr (DIVB == POWELL) {
       if (g.level) return false;
+      if (nw == 8) {  // persistent, tables in LDS
+        if constexpr (PowellLds<T, D, DEG>::fits) {
+          if (persist_powell <= 0) return false;
+          const int64_t groups = ((g.C + 15) / 16 + 7) / 8;
+          const unsigned grid = (unsigned)(groups < persist_powell ? groups : persist_powell);
+          k_cell_mfma_powell_p<T, D, DEG, 8><<<grid, 512, 0, s>>>((const T*)w, (const T*)w0, (T*)out, (const T*)ff,
+                                                                  (const T*)jp, mfv, mfg, mfl, mpv, mpg, mpl, tb.Pmean,
+                                                                  tb.Minv, g, sc, sp.gamma, a0, b0, cdt, mode);
+          return true;
+        }
+        return false;
+      }
       const unsigned grid = (unsigned)(((g.C + 15) / 16 + nw - 1) / nw);
       if (nw == 4)
         k_cell_mfma_powell<T, D, DEG, 4><<<grid, 256, 0, s>>>((const T*)w, (const T*)w0, (T*)out, (const T*)ff,
@@ -2677,6 +2738,7 @@ struct LauncherImpl : Launcher {
     if (v == 8 && launch_cell_mfma_p<4>(w, w0, out, ff, g, sc, sp, a0, b0, cdt, mode, s)) return;
     if (v == 9 && launch_cell_mfma_p<2>(w, w0, out, ff, g, sc, sp, a0, b0, cdt, mode, s)) return;
     if ((v == 8 || v == 9) && launch_cell_powell(v == 8 ? 4 : 2, w, w0, out, ff, jp, g, sc, sp, a0, b0, cdt, mode, s)) return;
+    if (v == 6 && launch_cell_powell(8, w, w0, out, ff, jp, g, sc, sp, a0, b0, cdt, mode, s)) return;
     // GLM: a persistent form that cannot be resident runs the batched one
     // (same face-flux layout)
     if (v >= 8 && launch_cell_mfma<4, true>(w, w0, out, ff, g, sc, sp, a0, b0, cdt, mode, s)) return;
