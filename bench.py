@@ -224,16 +224,20 @@ def main():
                             eval_fn_rate=fn, gate_skip_frac=gate_skip, train_seconds=t_train)
 
     ncells = r64["gpu"].ncells
-    mfma = (r64["variant"] & 15) >= 4 and octree is None  # octree grids run the LDS-tiled cell kernel
     cv = r64["variant"] & 15
-    # the matrix-core GLM cell kernel on uniform grids lifts face moments
-    flops_launch = cell_flops(D, d, divb, moments=mfma and divb == 0) * ncells
+    mfma = cv >= 4
+    # the matrix-core GLM cell kernel on uniform grids lifts face moments; the
+    # octree form and the Powell kernels lift point fluxes
+    flops_launch = cell_flops(D, d, divb, moments=mfma and divb == 0 and octree is None) * ncells
     achieved = flops_launch / (r64["k_cell"] / 1e3)
-    kname = ("k_cell_mfma_powell" if divb else ("k_cell_mfma_p" if cv >= 8 else "k_cell_mfma")) if mfma else "k_cell"
+    if divb:
+        kname = ("k_cell_mfma_powell_p" if cv == 6 else "k_cell_mfma_powell") if mfma else "k_cell"
+    else:
+        kname = ("k_cell_mfma_p" if cv >= 8 else "k_cell_mfma") if mfma else "k_cell"
     roof = {"kernel": kname, "bound": "mfma" if mfma else "alu",
             "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
-            "traffic": measured_traffic(args.workload, r64["variant"]) if mfma else None,
+            "traffic": measured_traffic(args.workload, r64["variant"]) if mfma and octree is None else None,
             "ms_per_launch": r64["k_cell"], "flops_per_launch": flops_launch}
     line = {
         "metric": METRIC,

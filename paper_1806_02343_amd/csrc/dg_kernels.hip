@@ -523,8 +523,8 @@ struct Mfma<float> {
 
 // Matrix-core GLM kernels in FP32 on uniform grids: two waves per SIMD
 // (256 registers per lane)
-template <typename T, bool AMR>
-constexpr int cell_waves_per_eu() { return (sizeof(T) == 4 && !AMR) ? 2 : 1; }
+template <typename T, bool AMR, int DEG = 3>
+constexpr int cell_waves_per_eu() { return ((sizeof(T) == 4 && !AMR) || (AMR && DEG <= 2)) ? 2 : 1; }
 
 template <int D, int DEG>
 struct MfmaShape {
@@ -967,34 +967,41 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
       }
     }
   }
-  if (AMR && live) {
-    constexpr int NSUB = 1 + (1 << (D - 1)), NQ = 1 << (D - 1);
+  if constexpr (AMR) {
+    // Surface term on the matrix cores: for each side of the cell and each
+    // sub-face class (0 the full face, 1 + q quarter q of a side with finer
+    // neighbours) one 16x16x4 product chain of the signed lift table of that
+    // class (LFS, fragment order) with the point fluxes of the 16 cells' faces
+    // of that class (cells without such a face contribute zero).  A class no
+    // cell of the tile has is skipped.
+    constexpr int NSUB = 1 + (1 << (D - 1)), NQ = 1 << (D - 1), KS1 = (FP + 3) / 4;
+    const int64_t ldf = g.ldf;
     for (int a = 0; a < D; ++a)
       for (int sd = 0; sd < 2; ++sd) {
-        const int32_t* sl = g.slots + (((int64_t)K * D + a) * 2 + sd) * 4;
-        for (int qf = 0; qf < NQ; ++qf) {
-          const int32_t f = sl[qf];
-          if (f < 0) break;
-          const int sub = 1 + (sd ? g.subL[f] : g.subR[f]);
-          const T sign = sd ? T(-1) : T(1);
-#pragma unroll 1
-          for (int r = 0; r < FP; ++r) {
-            const T* lf = LFS + (((a * 2 + sd) * NSUB + sub) * FP + r) * N;
-            T lv[S::NMT][4];
+        int32_t fs[NQ], sb[NQ];
+        const int32_t* sl = g.slots + (((int64_t)Kc * D + a) * 2 + sd) * 4;
 #pragma unroll
-            for (int mt = 0; mt < S::NMT; ++mt)
+        for (int q = 0; q < NQ; ++q) {
+          const int32_t f = live ? sl[q] : -1;
+          fs[q] = f;
+          sb[q] = f >= 0 ? 1 + (sd ? g.subL[f] : g.subR[f]) : -1;
+        }
+        for (int sub = 0; sub < NSUB; ++sub) {
+          int32_t f = -1;
 #pragma unroll
-              for (int e = 0; e < 4; ++e) {
-                const int n = 16 * mt + M::row(kq, e);
-                lv[mt][e] = n < N ? lf[n] : T(0);
-              }
+          for (int q = 0; q < NQ; ++q) f = (sb[q] == sub) ? fs[q] : f;
+          if (!__any(f >= 0)) continue;
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-              const T fv = sign * ff[((int64_t)v * FP + r) * g.ldf + f];
+          for (int s = 0; s < KS1; ++s) {
+            const int r = 4 * s + kq;
+            T bv[NV];
 #pragma unroll
-              for (int mt = 0; mt < S::NMT; ++mt)
+            for (int v = 0; v < NV; ++v) bv[v] = (f >= 0 && r < FP) ? ff[((int64_t)v * FP + r) * ldf + f] : T(0);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) R[v][mt][e] += lv[mt][e] * fv;
+            for (int mt = 0; mt < S::NMT; ++mt) {
+              const T la = LFS[(((((a * 2 + sd) * NSUB + sub) * KS1 + s) * S::NMT + mt) * 64) + lane];
+#pragma unroll
+              for (int v = 0; v < NV; ++v) R[v][mt] = M::mma(la, bv[v], R[v][mt]);
             }
           }
         }
@@ -1059,7 +1066,7 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
 }
 
 template <typename T, int D, int DEG, int NW, bool PF, bool AMR>
-__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(cell_waves_per_eu<T, AMR>())))
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(cell_waves_per_eu<T, AMR, DEG>())))
     k_cell_mfma(const T* w, const T* w0, T* out, const T* __restrict__ ff, const T* __restrict__ FV,
                 const T* __restrict__ FG, const T* __restrict__ FL, const T* __restrict__ GX,
                 const T* __restrict__ LX, const T* __restrict__ LFS, const T* __restrict__ L1,
@@ -1419,6 +1426,29 @@ struct AmrFaceShape {
   static constexpr int NKS = (C::N + 3) / 4;
   static constexpr int SZ = D * 2 * NSUB * NKS * 64;
 };
+
+// Signed sub-face lift tables of the octree surface product in fragment
+// order: [a][side][class][k-step][mode tile][lane], A[i][k] = -+ w_r phi_n at
+// point r = 4 s + k of the class (side +a: minus, side -a: plus; quarter
+// weights included), mode n = 16 mt + i.
+template <typename T, int D, int DEG>
+void amr_lift_tables(const Tables& t, std::vector<double>& lt) {
+  using C = Cfg<D, DEG, GLM>;
+  using S = MfmaShape<D, DEG>;
+  constexpr int NSUB = 1 + (1 << (D - 1)), KS1 = (C::FP + 3) / 4;
+  lt.assign((size_t)D * 2 * NSUB * KS1 * S::NMT * 64, 0.0);
+  for (int a = 0; a < D; ++a)
+    for (int sd = 0; sd < 2; ++sd)
+      for (int sub = 0; sub < NSUB; ++sub)
+        for (int s = 0; s < KS1; ++s)
+          for (int mt = 0; mt < S::NMT; ++mt)
+            for (int l = 0; l < 64; ++l) {
+              const int r = 4 * s + l / 16, n = 16 * mt + l % 16;
+              if (r >= C::FP || n >= C::N) continue;
+              const double v = t.LFS[((((size_t)a * 2 + sd) * NSUB + sub) * C::FP + r) * C::N + n];
+              lt[(((((size_t)a * 2 + sd) * NSUB + sub) * KS1 + s) * S::NMT + mt) * 64 + l] = sd ? -v : v;
+            }
+}
 
 template <typename T, int D, int DEG>
 void amr_face_tables(const Tables& t, std::vector<double>& ft) {
@@ -2398,6 +2428,7 @@ struct LauncherImpl : Launcher {
   const T *mpv = nullptr, *mpg = nullptr, *mpl = nullptr;  // and its LDF (Powell) tables
   const T* mft = nullptr;                                   // and of the matrix-core face kernel
   const T* mfta = nullptr;                                  // and of its octree form (sub-face tables)
+  const T* mlfa = nullptr;                                  // octree surface lift of the cell kernels
   const double* mpos = nullptr;                             // and of the matrix-core positivity limiter
   int pos_variant = 1;                                      // 1: matrix-core positivity limiter where built
   int face_variant = DIVB == GLM ? 1 : 0;                   // default: matrix-core face kernel for GLM
@@ -2497,6 +2528,9 @@ struct LauncherImpl : Launcher {
       if ((e = up<T>(ft, mft)) != hipSuccess) return e;
       amr_face_tables<T, D, DEG>(t, fta);
       if ((e = up<T>(fta, mfta)) != hipSuccess) return e;
+      std::vector<double> lfa;
+      amr_lift_tables<T, D, DEG>(t, lfa);
+      if ((e = up<T>(lfa, mlfa)) != hipSuccess) return e;
       std::vector<double> pt;
       pos_tables<D, DEG>(t, pt);
       if ((e = up<double>(pt, mpos)) != hipSuccess) return e;
@@ -2612,7 +2646,7 @@ struct LauncherImpl : Launcher {
       const unsigned grid = (unsigned)(groups < nb ? groups : nb);
       if (g.level)
         k_cell_mfma_p<T, D, DEG, NW, true><<<grid, 64 * NW, 0, s>>>((const T*)w, (const T*)w0, (T*)out,
-                                                                    (const T*)ff, mfv, mfg, mfl, mgx, mlx, tb.LFS, ml1, tb.Minv, g,
+                                                                    (const T*)ff, mfv, mfg, mfl, mgx, mlx, mlfa, ml1, tb.Minv, g,
                                                                     sc, sp.gamma, a0, b0, cdt, mode);
       else
         k_cell_mfma_p<T, D, DEG, NW, false><<<grid, 64 * NW, 0, s>>>((const T*)w, (const T*)w0, (T*)out,
@@ -2630,7 +2664,7 @@ struct LauncherImpl : Launcher {
       const unsigned grid = (unsigned)((tiles + NW - 1) / NW);
       if (g.level)
         k_cell_mfma<T, D, DEG, NW, PF, true><<<grid, 64 * NW, 0, s>>>((const T*)w, (const T*)w0, (T*)out,
-                                                                      (const T*)ff, mfv, mfg, mfl, mgx, mlx, tb.LFS, ml1, tb.Minv, g,
+                                                                      (const T*)ff, mfv, mfg, mfl, mgx, mlx, mlfa, ml1, tb.Minv, g,
                                                                       sc, sp.gamma, a0, b0, cdt, mode);
       else
         k_cell_mfma<T, D, DEG, NW, PF, false><<<grid, 64 * NW, 0, s>>>((const T*)w, (const T*)w0, (T*)out,
