@@ -1464,7 +1464,8 @@ void amr_face_tables(const Tables& t, std::vector<double>& ft) {
 }
 
 template <typename T, int D, int DEG, int NW>
-__global__ void __launch_bounds__(64 * NW) k_face_amr_mfma(const T* __restrict__ w, T* __restrict__ ffa,
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(DEG <= 2 ? 2 : 1)))
+    k_face_amr_mfma(const T* __restrict__ w, T* __restrict__ ffa,
                                                            const T* __restrict__ FT, Grid g,
                                                            const Scal* __restrict__ sc, double gamma) {
   using C = Cfg<D, DEG, GLM>;
