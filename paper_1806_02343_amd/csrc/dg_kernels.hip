@@ -1749,6 +1749,135 @@ __global__ void __launch_bounds__(64 * NW) k_face_mfma(const T* __restrict__ w, 
   else if constexpr (D == 3) riemann(std::integral_constant<int, 2>{});
 }
 
+// Matrix-core face kernel of the Powell scheme (uniform grids): one wave per
+// (tile of 16 faces, axis); the Legendre traces are 16x16x4 products of the
+// trace tables with the two cells' modes, the LDF field's traces products of
+// the per-component LDF trace tables with the LDF weights; each lane then
+// solves the Riemann problems of its four face points and writes the point
+// fluxes and the normal-field jumps (or, with the interpolated q-dagger, both
+// sides' face values) in the layout of k_face.
+template <int D, int DEG>
+struct PowellFaceShape {
+  using C = Cfg<D, DEG, POWELL>;
+  static constexpr int NKS = (C::N + 3) / 4;
+  static constexpr int NKL = (C::NLDF + 3) / 4;
+  static constexpr int SZL = D * 2 * NKS * 64;          // Legendre traces [a][side][s][lane]
+  static constexpr int SZ = SZL + D * 2 * D * NKL * 64;  // then the LDF traces [a][side][c][s][lane]
+  static_assert(C::FP <= 16, "face points per face fit one 16-row tile");
+};
+
+template <typename T, int D, int DEG>
+void powell_face_tables(const Tables& t, std::vector<double>& ft) {
+  using C = Cfg<D, DEG, POWELL>;
+  using S = PowellFaceShape<D, DEG>;
+  ft.assign(S::SZ, 0.0);
+  for (int a = 0; a < D; ++a)
+    for (int side = 0; side < 2; ++side) {
+      for (int s = 0; s < S::NKS; ++s)
+        for (int l = 0; l < 64; ++l) {
+          const int r = l % 16, n = 4 * s + l / 16;
+          if (r < C::FP && n < C::N) ft[((a * 2 + side) * S::NKS + s) * 64 + l] = t.TF[((a * 2 + side) * C::FP + r) * C::N + n];
+        }
+      for (int c = 0; c < D; ++c)
+        for (int s = 0; s < S::NKL; ++s)
+          for (int l = 0; l < 64; ++l) {
+            const int r = l % 16, i = 4 * s + l / 16;
+            if (r < C::FP && i < C::NLDF)
+              ft[S::SZL + (((a * 2 + side) * D + c) * S::NKL + s) * 64 + l] =
+                  t.PTF[(((a * 2 + side) * D + c) * C::FP + r) * C::NLDF + i];
+          }
+    }
+}
+
+template <typename T, int D, int DEG, int NW, bool QINT>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(D == 3 && DEG >= 3 ? 1 : 2)))
+    k_face_mfma_powell(const T* __restrict__ w, T* __restrict__ ff, T* __restrict__ jp, const T* __restrict__ FT,
+                       Grid g, const Scal* __restrict__ sc, double gamma) {
+  using C = Cfg<D, DEG, POWELL>;
+  using S = PowellFaceShape<D, DEG>;
+  using M = Mfma<T>;
+  using v4 = typename M::v4;
+  constexpr int N = C::N, FP = C::FP, NV = 8, NL = C::NLEG, L = C::NLDF;
+  const int64_t pw = (int64_t)xcd_block(blockIdx.x, gridDim.x) * NW + (threadIdx.x >> 6);
+  const int a = (int)(pw % D);
+  const int lane = threadIdx.x & 63;
+  const int64_t f0 = (pw / D) * 16;
+  if (f0 >= g.C) return;  // whole wave; no barrier in this kernel
+  const int kq = lane >> 4, cl = lane & 15;
+  const int64_t F = f0 + cl;
+  const bool live = F < g.C;
+  const int64_t FL = live ? F : f0;  // face F lies between cells F (left) and its +a neighbour
+  const int64_t FR = nbr(FL, a, +1, g);
+  const int64_t ld = g.ld;
+  v4 UL[NV], UR[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    UL[v] = v4{0, 0, 0, 0};
+    UR[v] = v4{0, 0, 0, 0};
+  }
+  auto traces = [&](v4 (&U)[NV], int64_t K, int side) {
+#pragma unroll
+    for (int s = 0; s < S::NKS; ++s) {
+      const int n = 4 * s + kq;
+      const T tk = FT[((a * 2 + side) * S::NKS + s) * 64 + lane];
+#pragma unroll
+      for (int j = 0; j < NL; ++j) {
+        const T b = n < N ? w[(int64_t)(j * N + n) * ld + K] : T(0);
+        U[C::legvar(j)] = M::mma(tk, b, U[C::legvar(j)]);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < S::NKL; ++s) {
+      const int i = 4 * s + kq;
+      const T b = i < L ? w[(int64_t)(NL * N + i) * ld + K] : T(0);
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+        U[5 + c] = M::mma(FT[S::SZL + (((a * 2 + side) * D + c) * S::NKL + s) * 64 + lane], b, U[5 + c]);
+    }
+  };
+  traces(UL, FL, 1);
+  traces(UR, FR, 0);
+  if (!live) return;
+  const T ch = (T)sc->ch;
+  auto riemann = [&](auto axis) {
+    constexpr int A = decltype(axis)::value;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = M::row(kq, j);
+      if (r >= FP) continue;
+      T uL[9], uR[9], Fx[9];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        uL[v] = UL[v][j];
+        uR[v] = UR[v][j];
+      }
+      if constexpr (QINT) {
+        // interpolated q-dagger (eq. powellq-interp): each side's Powell term
+        // with the HLLD interface state, left values to ff, right to jp
+        T vf[3], bf[3], ql[8], qr[8];
+        const T bnF = face_flux_a<T, NV, A>(uL, uR, gamma, ch, Fx, vf, bf);
+        powell_q_interp<T>(uL, vf, bf, ql);
+        powell_q_interp<T>(uR, vf, bf, qr);
+        const T jl = bnF - uL[5 + A], jr = uR[5 + A] - bnF;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          ff[((int64_t)(A * NV + v) * FP + r) * ld + F] = Fx[v] + ql[v] * jl;
+          jp[((int64_t)(A * NV + v) * FP + r) * ld + F] = Fx[v] - qr[v] * jr;
+        }
+      } else {
+        const T bnF = face_flux_a<T, NV, A>(uL, uR, gamma, ch, Fx);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) ff[((int64_t)(A * NV + v) * FP + r) * ld + F] = Fx[v];
+        jp[((int64_t)(A * 2 + 0) * FP + r) * ld + F] = bnF - uL[5 + A];
+        jp[((int64_t)(A * 2 + 1) * FP + r) * ld + F] = uR[5 + A] - bnF;
+      }
+    }
+  };
+  if (a == 0) riemann(std::integral_constant<int, 0>{});
+  else if (a == 1) riemann(std::integral_constant<int, 1>{});
+  else if constexpr (D == 3) riemann(std::integral_constant<int, 2>{});
+}
+
 // Low-register form of the matrix-core face kernel: the operands are loaded
 // one k-step at a time, the right traces wait in LDS, and each lane solves its
 // four face points one after another, so that two waves fit on a SIMD and one
@@ -2430,6 +2559,7 @@ struct LauncherImpl : Launcher {
   const T* mft = nullptr;                                   // and of the matrix-core face kernel
   const T* mfta = nullptr;                                  // and of its octree form (sub-face tables)
   const T* mlfa = nullptr;                                  // octree surface lift of the cell kernels
+  const T* mpft = nullptr;                                  // Powell face trace tables (matrix-core face kernel)
   const double* mpos = nullptr;                             // and of the matrix-core positivity limiter
   int pos_variant = 1;                                      // 1: matrix-core positivity limiter where built
   int face_variant = DIVB == GLM ? 1 : 0;                   // default: matrix-core face kernel for GLM
@@ -2490,6 +2620,9 @@ struct LauncherImpl : Launcher {
           return e;
         persist_powell = bp * ncu;
       }
+      std::vector<double> pft;
+      powell_face_tables<T, D, DEG>(t, pft);
+      if ((e = up<T>(pft, mpft)) != hipSuccess) return e;
     }
     if constexpr (DIVB == GLM) {
       // uniform grids: the matrix-core face kernels store face moments and
@@ -2622,6 +2755,20 @@ struct LauncherImpl : Launcher {
         return;
       }
     }
+    if constexpr (DIVB == POWELL) {
+      if (face_variant == 1 && mpft) {  // matrix-core traces, one wave per (tile, axis) pair
+        constexpr int NW = 4;
+        const int64_t tiles = (g.C + 15) / 16;
+        const unsigned grid = (unsigned)((tiles * D + NW - 1) / NW);
+        if (sp.powell_q)
+          k_face_mfma_powell<T, D, DEG, NW, true><<<grid, 64 * NW, 0, s>>>((const T*)w, (T*)ff, (T*)jp, mpft, g, sc,
+                                                                           sp.gamma);
+        else
+          k_face_mfma_powell<T, D, DEG, NW, false><<<grid, 64 * NW, 0, s>>>((const T*)w, (T*)ff, (T*)jp, mpft, g, sc,
+                                                                            sp.gamma);
+        return;
+      }
+    }
     using FT = FaceTile<T, D, DEG, DIVB>;
     dim3 grid((unsigned)((g.C + FT::TF - 1) / FT::TF), D);
     k_face<T, D, DEG, DIVB><<<grid, FT::NT, 0, s>>>((const T*)w, (T*)ff, (T*)jp, tb, g, sc, sp.gamma,
@@ -2745,7 +2892,7 @@ struct LauncherImpl : Launcher {
   // face variants: 0 LDS-staged; GLM uniform grids, matrix cores: 1 four
   // waves per block, 2 one wave per block, 3 low-register form at two waves
   // per SIMD (octree grids run the matrix-core sub-face kernel for 1-3)
-  int face_variant_count() const override { return DIVB == GLM ? 4 : 1; }
+  int face_variant_count() const override { return DIVB == GLM ? 4 : 2; }
   // GLM uniform grids: the LDS kernels (cell 0-3, face 0) exchange point
   // fluxes, the matrix-core ones (cell 4-9, face 1-3) face moments
   bool layout_compatible(int cv, int fv, const Grid& g) const override {
