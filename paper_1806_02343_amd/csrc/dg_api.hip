@@ -529,10 +529,21 @@ int dg_limit(dg_handle h, void* w, dg_limit_stats* stats) {
 static void step_sequence(dg_handle h, void* w, bool first) {
   const bool lim = h->p.limiter != 0;
   const bool fused = lim && h->L->fused_signal(h->g, h->sp);
+  // Powell (normal-field jumps in jp): the first stage's face kernel runs
+  // before the time step, whose cap then reads the jumps it wrote
+  bool face_ready = false;
   if (first || !fused) {
     launch_reset_step(h->sc, h->stream);
     h->L->maxsig(w, h->g, h->sc, h->sp, h->stream);
-    if (h->p.divb == DG_POWELL) h->L->powell_cap(w, h->jsum, h->g, h->sc, h->sp, h->stream);
+    if (h->p.divb == DG_POWELL) {
+      if (!h->sp.powell_q && !h->g.level) {
+        h->L->face(w, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
+        h->L->powell_cap_jp(w, h->jp, h->jsum, h->g, h->sc, h->stream);
+        face_ready = true;
+      } else {
+        h->L->powell_cap(w, h->jsum, h->g, h->sc, h->sp, h->stream);
+      }
+    }
   } else {
     launch_take_next(h->sc, h->stream);
   }
@@ -545,7 +556,8 @@ static void step_sequence(dg_handle h, void* w, bool first) {
   // one Shu-Osher stage: out = a0 base + b0 (in + c0 dt L(in)), then the
   // limiters (the last stage of the step also folds the next step's signal)
   auto stage = [&](void* in, void* base, void* out, double a0, double b0, double c0, bool last) {
-    h->L->face(in, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
+    if (!(face_ready && in == w)) h->L->face(in, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
+    face_ready = false;
     h->L->cell(in, base, out, h->ff, h->jp, h->g, h->sc, h->sp, a0, b0, c0, 1, h->stream);
     record(out);
     if (last && fused) launch_reset_next(h->sc, h->stream);

@@ -90,6 +90,8 @@ struct Launcher {
   // per-cell signal speeds -> atomic maxima in sc
   virtual void maxsig(const void* w, const Grid& g, Scal* sc, const SchemeParams& sp, hipStream_t s) = 0;
   // Powell dt cap: per-face normal-field jumps then per-cell rate
+  // Powell cap from the normal-field jumps the face kernel wrote for w
+  virtual void powell_cap_jp(const void* w, const void* jp, void* jsum, const Grid& g, Scal* sc, hipStream_t s) = 0;
   virtual void powell_cap(const void* w, void* jsum, const Grid& g, Scal* sc, const SchemeParams& sp,
                           hipStream_t s) = 0;
   // dynamic refinement (Sec. 4.4), Legendre bases: largest smoothness

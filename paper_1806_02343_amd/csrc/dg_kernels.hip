@@ -2178,6 +2178,27 @@ __global__ void __launch_bounds__(256) k_face_jump(const T* __restrict__ w, doub
   js[(int64_t)(a * 2 + 1) * g.C + f] = jr;
 }
 
+// The same face-jump integrals from the jumps the face kernel wrote at the
+// face points (jp[axis][side][point][face]: B^n_F - B^n_L, B^n_R - B^n_F).
+template <typename T, int D, int DEG, int DIVB>
+__global__ void __launch_bounds__(256) k_face_jump_jp(const T* __restrict__ jp, double* __restrict__ js, DevTab<T> tb,
+                                                      Grid g) {
+  using C = Cfg<D, DEG, DIVB>;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)D * g.C) return;
+  const int64_t f = gid % g.C;
+  const int a = (int)(gid / g.C);
+  const int64_t ld = g.ld;
+  double jl = 0.0, jr = 0.0;
+  for (int r = 0; r < C::FP; ++r) {
+    const double wgt = tb.LF[((a * 2 + 1) * C::FP + r) * C::N + 0];  // w_r * P_0
+    jl += wgt * fabs((double)jp[((int64_t)(a * 2 + 0) * C::FP + r) * ld + f]);
+    jr += wgt * fabs((double)jp[((int64_t)(a * 2 + 1) * C::FP + r) * ld + f]);
+  }
+  js[(int64_t)(a * 2 + 0) * g.C + f] = jl;
+  js[(int64_t)(a * 2 + 1) * g.C + f] = jr;
+}
+
 template <typename T, int D, int DEG, int DIVB>
 __global__ void __launch_bounds__(256) k_powell_rate(const T* __restrict__ w, const double* __restrict__ js,
                                                      DevTab<T> tb, Grid g, Scal* sc) {
@@ -2947,6 +2968,13 @@ struct LauncherImpl : Launcher {
     }
     const int nb = (int)((g.C + TL::TC - 1) / TL::TC);
     k_maxsig<T, D, DEG, DIVB><<<nb, 256, 0, s>>>((const T*)w, tb, g, sc, sp.gamma);
+  }
+  void powell_cap_jp(const void* w, const void* jp, void* jsum, const Grid& g, Scal* sc, hipStream_t s) override {
+    if constexpr (DIVB == POWELL) {
+      const int64_t nf = (int64_t)D * g.C;
+      k_face_jump_jp<T, D, DEG, DIVB><<<(int)((nf + 255) / 256), 256, 0, s>>>((const T*)jp, (double*)jsum, tb, g);
+      k_powell_rate<T, D, DEG, DIVB><<<(int)((g.C + 255) / 256), 256, 0, s>>>((const T*)w, (const double*)jsum, tb, g, sc);
+    }
   }
   void powell_cap(const void* w, void* jsum, const Grid& g, Scal* sc, const SchemeParams& sp,
                   hipStream_t s) override {
