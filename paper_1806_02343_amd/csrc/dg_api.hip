@@ -710,9 +710,21 @@ int dg_time_kernel(dg_handle h, const void* w, int32_t which, int32_t reps, doub
   return rc;
 }
 
+// Cache key of a schedule: precision, dimension, degree, scheme, Powell q,
+// cell count and, on octrees, the level mix (leaves per level) and the share
+// of faces between levels, which set the cost of the sub-face gathers.
 static std::string tune_key(dg_handle h) {
   std::ostringstream k;
-  k << "sched/p" << h->p.precision << "/D" << h->p.dim << "/d" << h->p.degree << "/b" << h->p.divb << "/C" << h->g.C;
+  k << "sched/p" << h->p.precision << "/D" << h->p.dim << "/d" << h->p.degree << "/b" << h->p.divb << "/q"
+    << h->p.powell_q << "/C" << h->g.C;
+  if (!h->h_level.empty()) {
+    int64_t cnt[21] = {0};
+    for (int8_t l : h->h_level) cnt[l >= 0 && l <= 20 ? l : 0] += 1;
+    k << "/L";
+    for (int l = 0; l <= 20; ++l)
+      if (cnt[l]) k << l << ":" << cnt[l] << ",";
+    k << "/F" << h->g.NF;
+  }
   return k.str();
 }
 
