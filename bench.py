@@ -237,7 +237,7 @@ def main():
     roof = {"kernel": kname, "bound": "mfma" if mfma else "alu",
             "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
-            "traffic": measured_traffic(args.workload, r64["variant"]) if mfma and octree is None else None,
+            "traffic": measured_traffic(args.workload, r64["variant"]) if mfma else None,
             "ms_per_launch": r64["k_cell"], "flops_per_launch": flops_launch}
     line = {
         "metric": METRIC,

@@ -728,8 +728,8 @@ void mfma_tables(const Tables& t, std::vector<double>& fv, std::vector<double>& 
 // The work of one wave on the 16 cells starting at c0 (tables FV, FG, FL in
 // global memory or LDS).
 // AMR: octree grid; the surface term is then an owner gather of the 1 or
-// 2^(D-1) (sub-)face fluxes of each side with the sub-face tables LFS,
-// accumulated on the vector ALU straight into the accumulator elements.
+// 2^(D-1) (sub-)face point fluxes of each side, multiplied on the matrix
+// cores with the signed sub-face lift tables LFS of each class present.
 //
 // FP32 deviation form (DEV: FP32 state on uniform grids).  A constant flux c
 // added to every volume and face flux of a cell changes nothing in exact
@@ -1024,14 +1024,19 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
   // mass entries are loaded with the other operands: out is not known not
   // to alias Minv, so a load of Minv after a store would wait for that store.
   constexpr bool AHEAD = sizeof(T) == 8;
+  // octree, FP64: the epilogue forms its row offsets afresh rather than
+  // keeping those of the mode loads live through the volume loop
+  int64_t lde = ld;
+  int kqe = kq;
+  if constexpr (AMR && sizeof(T) == 8) asm volatile("" : "+s"(lde), "+v"(kqe));
   T ew[2][S::NMT][4], eb[2][S::NMT][4], em[2][S::NMT][4];
   auto eload = [&](int v, T (&wm)[S::NMT][4], T (&base)[S::NMT][4], T (&mi)[S::NMT][4]) {
 #pragma unroll
     for (int mt = 0; mt < S::NMT; ++mt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int n = 16 * mt + M::row(kq, r);
-        const int64_t at = (int64_t)(v * N + (n < N ? n : 0)) * ld + K;
+        const int n = 16 * mt + M::row(kqe, r);
+        const int64_t at = (int64_t)(v * N + (n < N ? n : 0)) * lde + K;
         wm[mt][r] = (v == 8 || (mode & 1)) ? w[at] : T(0);
         base[mt][r] = (mode & 1) ? w0[at] : T(0);
         mi[mt][r] = n < N ? Minv[v * N + n] : T(0);
@@ -1049,7 +1054,7 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
     for (int mt = 0; mt < S::NMT; ++mt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int n = 16 * mt + M::row(kq, r);
+        const int n = 16 * mt + M::row(kqe, r);
         if (n >= N) continue;
         const int m = v * N + n;
         T racc = R[v][mt][r];
@@ -1080,9 +1085,13 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(ce
 
 // Persistent form: one workgroup per resident slot copies the fragment
 // tables into LDS once, then its waves walk a contiguous range of 16-cell
-// tiles (ranges dealt XCD by XCD, as in xcd_block).
+// tiles (ranges dealt XCD by XCD, as in xcd_block).  FP64 on octrees at
+// degree <= 2: two waves per SIMD, the cell's modes reloaded per row tile
+// (PF off) and the lane's row offsets formed afresh for every tile (hoisted
+// out of the walk they would be held in spilled registers).
 template <typename T, int D, int DEG, int NW, bool AMR>
 __global__ void __launch_bounds__(64 * NW)
+    __attribute__((amdgpu_waves_per_eu((AMR && DEG <= 2 && sizeof(T) == 8) ? 2 : 1)))
     k_cell_mfma_p(const T* w, const T* w0, T* out, const T* __restrict__ ff, const T* __restrict__ FV,
                   const T* __restrict__ FG, const T* __restrict__ FL, const T* __restrict__ GX,
                   const T* __restrict__ LX, const T* __restrict__ LFS, const T* __restrict__ L1,
@@ -1100,9 +1109,15 @@ __global__ void __launch_bounds__(64 * NW)
   const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
   const int64_t t0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * per;
   const int64_t t1 = t0 + per < ntiles ? t0 + per : ntiles;
-  for (int64_t t = t0 + (threadIdx.x >> 6); t < t1; t += NW)
-    cell_tile_mfma<T, D, DEG, true, AMR>(t * 16, threadIdx.x & 63, w, w0, out, ff, sV, sG, sL, sGX, sLX, LFS, L1,
-                                         Minv, g, sc, gamma, a0, b0, cdt, mode);
+  constexpr bool LAUNDER = AMR && DEG <= 2 && sizeof(T) == 8;
+  for (int64_t t = t0 + (threadIdx.x >> 6); t < t1; t += NW) {
+    const T* mi = Minv;
+    Grid gt = g;
+    int ln = threadIdx.x & 63;
+    if constexpr (LAUNDER) asm volatile("" : "+s"(mi), "+s"(gt.ld), "+v"(ln));
+    cell_tile_mfma<T, D, DEG, !LAUNDER, AMR>(t * 16, ln, w, w0, out, ff, sV, sG, sL, sGX, sLX, LFS, L1, mi, gt, sc,
+                                             gamma, a0, b0, cdt, mode);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1215,24 +1230,27 @@ __device__ __forceinline__ void cell_tile_mfma_powell(int64_t c0, int lane, cons
   if (qint)
 #pragma unroll
     for (int v = 0; v < 8; ++v) qv[v] = T(0);
-  // surface first: flux + Powell term of face point k = 4 s + kq as one B operand per variable
-#pragma unroll 1
-  for (int s = 0; s < S::KS; ++s) {
+  // surface first: flux + Powell term of face point k = 4 s + kq as one B operand per variable.
+  // Face values of k-step s, and the normal-field jump that the Powell term
+  // multiplies: side +a: B^n_F - B^n_K at face K; side -a: B^n_K - B^n_F at
+  // face K-a (interpolated q-dagger: the face kernel added each side's
+  // Powell term to its face values, the left side's in ff, the right side's
+  // in jp, and the jump is not read).
+  auto load_face = [&](int s, T* fv) {
     const int k = 4 * s + kq;
     const bool kv = k < 2 * D * FP;
     const int a = kv ? k / (2 * FP) : 0, side = (k / FP) % 2, r = k % FP;
     const int64_t Kf = side ? Kc : nbr(Kc, a, -1, g);
-    // side +a: jump B^n_F - B^n_K at face K; side -a: B^n_K - B^n_F at face K-a
-    // (interpolated q-dagger: the face kernel added each side's Powell term
-    // to its face values, the left side's in ff, the right side's in jp)
-    const T jmp = (kv && !qint) ? jp[((int64_t)(a * 2 + (side ? 0 : 1)) * FP + r) * ld + Kf] : T(0);
+    fv[NV] = (kv && !qint) ? jp[((int64_t)(a * 2 + (side ? 0 : 1)) * FP + r) * ld + Kf] : T(0);
     const T* src = (qint && !side) ? jp : ff;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) fv[v] = kv ? src[((int64_t)(a * NV + v) * FP + r) * ld + Kf] : T(0);
+  };
+  auto surface_step = [&](int s, const T* fv) {
+    const int side = ((4 * s + kq) / FP) % 2;
     T bv[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const T f = kv ? src[((int64_t)(a * NV + v) * FP + r) * ld + Kf] : T(0);
-      bv[v] = side ? f + qv[v] * jmp : f - qv[v] * jmp;
-    }
+    for (int v = 0; v < NV; ++v) bv[v] = side ? fv[v] + qv[v] * fv[NV] : fv[v] - qv[v] * fv[NV];
 #pragma unroll
     for (int mt = 0; mt < S::NMT; ++mt) {
       const T la = FL[(mt * S::KS + s) * 64 + lane];
@@ -1244,6 +1262,20 @@ __device__ __forceinline__ void cell_tile_mfma_powell(int64_t c0, int lane, cons
 #pragma unroll
       for (int mt = 0; mt < P::NMTL; ++mt)
         RB[mt] = M::mma(PLt[((c * P::NMTL + mt) * S::KS + s) * 64 + lane], bv[5 + c], RB[mt]);
+  };
+  // 3-D degree 2: the loads of SB k-steps in flight together (the surface
+  // phase holds few registers: the accumulators and q); elsewhere batching
+  // measured no gain and raised the persistent kernel's spills
+  constexpr int SB = (D == 3 && DEG == 2) ? 7 : 1;
+#pragma unroll 1
+  for (int s0 = 0; s0 < S::KS; s0 += SB) {
+    T fv[SB][NV + 1];
+#pragma unroll
+    for (int b = 0; b < SB; ++b)
+      if (s0 + b < S::KS) load_face(s0 + b, fv[b]);
+#pragma unroll
+    for (int b = 0; b < SB; ++b)
+      if (s0 + b < S::KS) surface_step(s0 + b, fv[b]);
   }
   // the cell's modes as B operands, held for all row tiles
   T bw[NL][S::NKS], bl[P::NKL];
@@ -1310,10 +1342,15 @@ __device__ __forceinline__ void cell_tile_mfma_powell(int64_t c0, int lane, cons
   if (!live) return;
   const double dt = sc->dt * cdt;  // the stage's multiple of the step
   const T two_h = T(2.0 / g.h);
+  // FP64: the epilogue forms its row offsets afresh rather than keeping
+  // those of the mode loads live through the volume loop
+  int64_t lde = ld;
+  int kqe = kq;
+  if constexpr (sizeof(T) == 8) asm volatile("" : "+s"(lde), "+v"(kqe));
   auto finish = [&](int m, T racc) {
     T dw = racc * two_h * Minv[m];
     if (!(mode & 1)) return dw;
-    return (T)a0 * w0[(int64_t)m * ld + K] + (T)b0 * (w[(int64_t)m * ld + K] + (T)dt * dw);
+    return (T)a0 * w0[(int64_t)m * lde + K] + (T)b0 * (w[(int64_t)m * lde + K] + (T)dt * dw);
   };
   // out may alias w or w0: every element's loads precede its store, grouped per block
 #pragma unroll
@@ -1323,15 +1360,15 @@ __device__ __forceinline__ void cell_tile_mfma_powell(int64_t c0, int lane, cons
     for (int mt = 0; mt < S::NMT; ++mt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int n = 16 * mt + M::row(kq, r);
+        const int n = 16 * mt + M::row(kqe, r);
         o[mt][r] = n < N ? finish(j * N + n, R[j][mt][r]) : T(0);
       }
 #pragma unroll
     for (int mt = 0; mt < S::NMT; ++mt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int n = 16 * mt + M::row(kq, r);
-        if (n < N) out[(int64_t)(j * N + n) * ld + K] = o[mt][r];
+        const int n = 16 * mt + M::row(kqe, r);
+        if (n < N) out[(int64_t)(j * N + n) * lde + K] = o[mt][r];
       }
   }
   {
@@ -1340,15 +1377,15 @@ __device__ __forceinline__ void cell_tile_mfma_powell(int64_t c0, int lane, cons
     for (int mt = 0; mt < P::NMTL; ++mt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = 16 * mt + M::row(kq, r);
+        const int i = 16 * mt + M::row(kqe, r);
         o[mt][r] = i < L ? finish(NL * N + i, RB[mt][r]) : T(0);
       }
 #pragma unroll
     for (int mt = 0; mt < P::NMTL; ++mt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = 16 * mt + M::row(kq, r);
-        if (i < L) out[(int64_t)(NL * N + i) * ld + K] = o[mt][r];
+        const int i = 16 * mt + M::row(kqe, r);
+        if (i < L) out[(int64_t)(NL * N + i) * lde + K] = o[mt][r];
       }
   }
 }
@@ -1405,9 +1442,18 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(po
     const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
     const int64_t t0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * per;
     const int64_t t1 = t0 + per < ntiles ? t0 + per : ntiles;
-    for (int64_t t = t0 + (threadIdx.x >> 6); t < t1; t += NW)
-      cell_tile_mfma_powell<T, D, DEG>(t * 16, threadIdx.x & 63, w, w0, out, ff, jp, sV, sG, sL, sPV, sPG, sPL, Pmean,
-                                       Minv, g, sc, gamma, a0, b0, cdt, mode);
+    for (int64_t t = t0 + (threadIdx.x >> 6); t < t1; t += NW) {
+      // FP64: the per-mode constants and the lane's row offsets (mode x
+      // leading dimension) are formed again for every tile: hoisted out of
+      // the walk they would be held in (spilled) registers across all tiles
+      const T* pm = Pmean;
+      const T* mi = Minv;
+      Grid gt = g;
+      int ln = threadIdx.x & 63;
+      if constexpr (sizeof(T) == 8) asm volatile("" : "+s"(pm), "+s"(mi), "+s"(gt.ld), "+v"(ln));
+      cell_tile_mfma_powell<T, D, DEG>(t * 16, ln, w, w0, out, ff, jp, sV, sG, sL, sPV, sPG, sPL, pm, mi, gt, sc, gamma,
+                                       a0, b0, cdt, mode);
+    }
   }
 }
 
