@@ -2018,11 +2018,12 @@ k_face_mfma_lr(const T* __restrict__ w, T* __restrict__ ff, const T* __restrict_
   else if constexpr (D == 3) riemann(std::integral_constant<int, 2>{});
 }
 
-// Max signal speed on the matrix cores (GLM, uniform grids): one wave
-// evaluates 16 cells at every volume point (row tiles of the nodal table)
-// and face point (row tiles of the trace tables) with 16x16x4 products in the
-// state's precision, the modes held in registers; wave and block maxima
-// (NaN-propagating) feed one atomic per block.
+// Max signal speed on the matrix cores (GLM, uniform and octree grids): one
+// wave evaluates 16 cells at every volume point (row tiles of the nodal
+// table) and face point (row tiles of the trace tables) with 16x16x4
+// products in the state's precision, the modes held in registers; wave and
+// block maxima (NaN-propagating) of the speed and of the speed over the
+// cell's size feed one atomic each per block.
 template <typename T, int D, int DEG, int NW>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2))) k_maxsig_mfma(const T* __restrict__ w, const T* __restrict__ FV,
                                                          const T* __restrict__ FT, Grid g, Scal* sc, double gamma) {
@@ -2035,7 +2036,7 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2,
   static_assert(SF::NKS == S::NKS, "same k-steps for the volume and face evaluation tables");
   // evaluation rows: the volume row tiles, then the trace rows of each face
   __shared__ T sT[(S::QT + 2 * D) * S::NKS * 64];
-  __shared__ double red[NW];
+  __shared__ double red[NW], red2[NW];
   for (int i = threadIdx.x; i < S::SZ_V; i += 64 * NW) sT[i] = FV[i];
   for (int i = threadIdx.x; i < 2 * D * S::NKS * 64; i += 64 * NW) sT[S::SZ_V + i] = FT[i];
   __syncthreads();
@@ -2045,12 +2046,13 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2,
   const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
   const int64_t t0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * per;
   const int64_t t1 = t0 + per < ntiles ? t0 + per : ntiles;
-  double smax = 0.0;
+  double smax = 0.0, rmax = 0.0;
   for (int64_t t = t0 + wid; t < t1; t += NW) {
     const int64_t c0 = t * 16;
     const int64_t K = c0 + cl;
     const bool live = K < g.C;
     const int64_t Kc = live ? K : c0;
+    const double ih = 1.0 / cell_h(g, Kc);
     T bw[8][S::NKS];
 #pragma unroll
     for (int v = 0; v < 8; ++v)
@@ -2082,6 +2084,8 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2,
         double sp = signal_sum<T, D>(u, gamma);
         if (!(sp == sp)) sp = __longlong_as_double(0x7ff8000000000000ULL);
         smax = (sp > smax || !(sp == sp)) ? sp : smax;
+        const double rt = sp * ih;
+        rmax = (rt > rmax || !(rt == rt)) ? rt : rmax;
       }
     }
   }
@@ -2089,14 +2093,22 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2,
   for (int o = 32; o > 0; o >>= 1) {
     const double x = __shfl_xor(smax, o);
     smax = (x > smax || !(x == x)) ? x : smax;
+    const double y = __shfl_xor(rmax, o);
+    rmax = (y > rmax || !(y == y)) ? y : rmax;
   }
-  if (lane == 0) red[wid] = smax;
+  if (lane == 0) {
+    red[wid] = smax;
+    red2[wid] = rmax;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double m = red[0];
-    for (int i = 1; i < NW; ++i) m = (red[i] > m || !(red[i] == red[i])) ? red[i] : m;
+    double m = red[0], r = red2[0];
+    for (int i = 1; i < NW; ++i) {
+      m = (red[i] > m || !(red[i] == red[i])) ? red[i] : m;
+      r = (red2[i] > r || !(red2[i] == red2[i])) ? red2[i] : r;
+    }
     atomic_max_pos(&sc->maxsig_bits, m);
-    atomic_max_pos(&sc->maxrate_bits, m * (1.0 / g.h));
+    atomic_max_pos(&sc->maxrate_bits, r);
     if (!(m == m)) atomicAdd(&sc->nonfinite, 1ULL);
   }
 }
@@ -3004,7 +3016,7 @@ struct LauncherImpl : Launcher {
   }
   void maxsig(const void* w, const Grid& g, Scal* sc, const SchemeParams& sp, hipStream_t s) override {
     if constexpr (DIVB == GLM) {
-      if (!g.level && face_variant >= 1 && maxsig_blocks > 0) {
+      if ((g.level || face_variant >= 1) && maxsig_blocks > 0) {
         constexpr int NW = 4;
         const int64_t groups = ((g.C + 15) / 16 + NW - 1) / NW;
         const unsigned grid = (unsigned)(groups < maxsig_blocks ? groups : maxsig_blocks);
