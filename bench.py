@@ -226,9 +226,9 @@ def main():
     ncells = r64["gpu"].ncells
     cv = r64["variant"] & 15
     mfma = cv >= 4
-    # the matrix-core GLM cell kernel on uniform grids lifts face moments; the
-    # octree form and the Powell kernels lift point fluxes
-    flops_launch = cell_flops(D, d, divb, moments=mfma and divb == 0 and octree is None) * ncells
+    # the matrix-core GLM cell kernels (uniform and octree grids) lift face
+    # moments; the Powell kernels lift point fluxes
+    flops_launch = cell_flops(D, d, divb, moments=mfma and divb == 0) * ncells
     achieved = flops_launch / (r64["k_cell"] / 1e3)
     if divb:
         kname = ("k_cell_mfma_powell_p" if cv == 6 else "k_cell_mfma_powell") if mfma else "k_cell"

@@ -971,10 +971,10 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
     // Surface term on the matrix cores: for each side of the cell and each
     // sub-face class (0 the full face, 1 + q quarter q of a side with finer
     // neighbours) one 16x16x4 product chain of the signed lift table of that
-    // class (LFS, fragment order) with the point fluxes of the 16 cells' faces
-    // of that class (cells without such a face contribute zero).  A class no
-    // cell of the tile has is skipped.
-    constexpr int NSUB = 1 + (1 << (D - 1)), NQ = 1 << (D - 1), KS1 = (FP + 3) / 4;
+    // class (LFS, fragment order, over face moments) with the flux moments of
+    // the 16 cells' faces of that class (cells without such a face contribute
+    // zero).  A class no cell of the tile has is skipped.
+    constexpr int NSUB = 1 + (1 << (D - 1)), NQ = 1 << (D - 1), KS1 = (C::FM + 3) / 4, FMA = C::FM;
     const int64_t ldf = g.ldf;
     for (int a = 0; a < D; ++a)
       for (int sd = 0; sd < 2; ++sd) {
@@ -993,10 +993,10 @@ __device__ __forceinline__ void cell_tile_mfma(int64_t c0, int lane, const T* w,
           if (!__any(f >= 0)) continue;
 #pragma unroll
           for (int s = 0; s < KS1; ++s) {
-            const int r = 4 * s + kq;
+            const int m = 4 * s + kq;
             T bv[NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) bv[v] = (f >= 0 && r < FP) ? ff[((int64_t)v * FP + r) * ldf + f] : T(0);
+            for (int v = 0; v < NV; ++v) bv[v] = (f >= 0 && m < FMA) ? ff[((int64_t)v * FMA + m) * ldf + f] : T(0);
 #pragma unroll
             for (int mt = 0; mt < S::NMT; ++mt) {
               const T la = LFS[(((((a * 2 + sd) * NSUB + sub) * KS1 + s) * S::NMT + mt) * 64) + lane];
@@ -1462,7 +1462,9 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(po
 // trace tables (the full face or the quarter of the coarse side, Sec. 4.4
 // prolongation) are shared by the tile's 16 faces; the traces are 16x16x4
 // products with the two cells' modes gathered by face, then each lane solves
-// the Riemann problems of its four face points.
+// the Riemann problems of its four face points, and the face's flux moments
+// (Q^T F on the fine face, as on uniform grids) are stored for the cell
+// kernels' lift over moments.
 template <int D, int DEG>
 struct AmrFaceShape {
   using C = Cfg<D, DEG, GLM>;
@@ -1471,36 +1473,65 @@ struct AmrFaceShape {
   static constexpr int NCL = 1 + 2 * NQ;
   static constexpr int NKS = (C::N + 3) / 4;
   static constexpr int SZ = D * 2 * NSUB * NKS * 64;
+  static constexpr int SZM = SZ + D * 4 * 64;  // and the moment tables Q^T, one per axis
+  static constexpr int KSM = (C::FM + 3) / 4;  // k-steps of the surface product over moments
 };
 
 // Signed sub-face lift tables of the octree surface product in fragment
-// order: [a][side][class][k-step][mode tile][lane], A[i][k] = -+ w_r phi_n at
-// point r = 4 s + k of the class (side +a: minus, side -a: plus; quarter
-// weights included), mode n = 16 mt + i.
+// order over face moments: [a][side][class][k-step][mode tile][lane],
+// A[i][k] = -+ sum_r w_r phi_n(x_r) Q[a][r][m] for moment m = 4 s + k and
+// mode n = 16 mt + i, with r the points of the class's (fine) face (side +a:
+// minus, side -a: plus; the coarse side's rows are those of its quarter,
+// quarter weights included).  The traces of a coarse cell's basis on a
+// quarter are polynomials of the same degree in the fine face's coordinates,
+// so its lift rows lie in the span of Q (checked; false otherwise): the
+// moment form is exact up to rounding.
 template <typename T, int D, int DEG>
-void amr_lift_tables(const Tables& t, std::vector<double>& lt) {
+bool amr_lift_tables(const Tables& t, const std::vector<double>& qb, std::vector<double>& lt) {
   using C = Cfg<D, DEG, GLM>;
   using S = MfmaShape<D, DEG>;
-  constexpr int NSUB = 1 + (1 << (D - 1)), KS1 = (C::FP + 3) / 4;
-  lt.assign((size_t)D * 2 * NSUB * KS1 * S::NMT * 64, 0.0);
+  constexpr int NSUB = 1 + (1 << (D - 1)), KSM = AmrFaceShape<D, DEG>::KSM, FP = C::FP, FM = C::FM, N = C::N;
+  lt.assign((size_t)D * 2 * NSUB * KSM * S::NMT * 64, 0.0);
   for (int a = 0; a < D; ++a)
     for (int sd = 0; sd < 2; ++sd)
-      for (int sub = 0; sub < NSUB; ++sub)
-        for (int s = 0; s < KS1; ++s)
+      for (int sub = 0; sub < NSUB; ++sub) {
+        const double* rows = &t.LFS[(((size_t)a * 2 + sd) * NSUB + sub) * FP * N];  // [r][n]
+        double scale = 0.0;
+        for (int i = 0; i < FP * N; ++i) scale = std::max(scale, std::fabs(rows[i]));
+        std::vector<double> lm((size_t)N * FM, 0.0);  // [n][m]
+        for (int n = 0; n < N; ++n)
+          for (int m = 0; m < FM; ++m)
+            for (int r = 0; r < FP; ++r) lm[(size_t)n * FM + m] += rows[(size_t)r * N + n] * qb[((size_t)a * FP + r) * FM + m];
+        for (int n = 0; n < N; ++n)  // the rows must lie in the span of Q
+          for (int r = 0; r < FP; ++r) {
+            double pr = 0.0;
+            for (int m = 0; m < FM; ++m) pr += lm[(size_t)n * FM + m] * qb[((size_t)a * FP + r) * FM + m];
+            if (std::fabs(pr - rows[(size_t)r * N + n]) > 1e-13 * scale) return false;
+          }
+        for (int s = 0; s < KSM; ++s)
           for (int mt = 0; mt < S::NMT; ++mt)
             for (int l = 0; l < 64; ++l) {
-              const int r = 4 * s + l / 16, n = 16 * mt + l % 16;
-              if (r >= C::FP || n >= C::N) continue;
-              const double v = t.LFS[((((size_t)a * 2 + sd) * NSUB + sub) * C::FP + r) * C::N + n];
-              lt[(((((size_t)a * 2 + sd) * NSUB + sub) * KS1 + s) * S::NMT + mt) * 64 + l] = sd ? -v : v;
+              const int m = 4 * s + l / 16, n = 16 * mt + l % 16;
+              if (m >= FM || n >= N) continue;
+              const double v = lm[(size_t)n * FM + m];
+              lt[(((((size_t)a * 2 + sd) * NSUB + sub) * KSM + s) * S::NMT + mt) * 64 + l] = sd ? -v : v;
             }
+      }
+  return true;
 }
 
 template <typename T, int D, int DEG>
-void amr_face_tables(const Tables& t, std::vector<double>& ft) {
+void amr_face_tables(const Tables& t, const std::vector<double>& qb, std::vector<double>& ft) {
   using C = Cfg<D, DEG, GLM>;
   using S = AmrFaceShape<D, DEG>;
-  ft.assign(S::SZ, 0.0);
+  ft.assign(S::SZM, 0.0);
+  // moment tables as in the uniform face kernel (the fine face's points)
+  for (int a = 0; a < D; ++a)
+    for (int s = 0; s < 4; ++s)
+      for (int l = 0; l < 64; ++l) {
+        const int m = l % 16, r = Mfma<T>::row(l / 16, s);
+        if (m < C::FM && r < C::FP) ft[S::SZ + (a * 4 + s) * 64 + l] = qb[((size_t)a * C::FP + r) * C::FM + m];
+      }
   for (int as = 0; as < D * 2 * S::NSUB; ++as)
     for (int s = 0; s < S::NKS; ++s)
       for (int l = 0; l < 64; ++l) {
@@ -1564,28 +1595,48 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(DE
 #pragma unroll
       for (int v = 0; v < NV; ++v) UR[v] = M::mma(tk[s], bk[s][v], UR[v]);
   }
-  if (!live) return;
+  // every lane stays for the moment product below (its A operand is
+  // loaded by all lanes); a padding lane solves its tile's first face
   const T ch = (T)sc->ch;
+  T FX[NV][4];
   auto riemann = [&](auto axis) {
     constexpr int A = decltype(axis)::value;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int r = M::row(kq, j);
-      if (r >= FP) continue;
       T uL[9], uR[9], Fx[9];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         uL[v] = UL[v][j];
         uR[v] = UR[v][j];
+        Fx[v] = T(0);
       }
-      (void)face_flux_a<T, NV, A>(uL, uR, gamma, ch, Fx);
+      if (r < FP) (void)face_flux_a<T, NV, A>(uL, uR, gamma, ch, Fx);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) ffa[((int64_t)v * FP + r) * g.ldf + f] = Fx[v];
+      for (int v = 0; v < NV; ++v) FX[v][j] = Fx[v];
     }
   };
   if (a == 0) riemann(std::integral_constant<int, 0>{});
   else if (a == 1) riemann(std::integral_constant<int, 1>{});
   else if constexpr (D == 3) riemann(std::integral_constant<int, 2>{});
+  // face moments M = Q^T F (16x16x4 products, the point fluxes as B operands
+  // as they lie), rows m < FM stored: [v][m] rows of ldf faces
+  T mq[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) mq[s] = FT[S::SZ + (a * 4 + s) * 64 + lane];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    v4 acc = v4{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc = M::mma(mq[s], FX[v][s], acc);
+    if (live) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int m = M::row(kq, e);
+        if (m < C::FM) ffa[((int64_t)v * C::FM + m) * g.ldf + f] = acc[e];
+      }
+    }
+  }
 }
 
 // Face kernel on the matrix cores (GLM, uniform grids): one wave owns 16
@@ -2739,10 +2790,10 @@ struct LauncherImpl : Launcher {
       std::vector<double> ft, fta;
       mfma_face_tables<T, D, DEG>(t, qb, ft);
       if ((e = up<T>(ft, mft)) != hipSuccess) return e;
-      amr_face_tables<T, D, DEG>(t, fta);
+      amr_face_tables<T, D, DEG>(t, qb, fta);
       if ((e = up<T>(fta, mfta)) != hipSuccess) return e;
       std::vector<double> lfa;
-      amr_lift_tables<T, D, DEG>(t, lfa);
+      if (!amr_lift_tables<T, D, DEG>(t, qb, lfa)) return hipErrorInvalidValue;
       if ((e = up<T>(lfa, mlfa)) != hipSuccess) return e;
       std::vector<double> pt;
       pos_tables<D, DEG>(t, pt);
@@ -2972,10 +3023,12 @@ struct LauncherImpl : Launcher {
   // waves per block, 2 one wave per block, 3 low-register form at two waves
   // per SIMD (octree grids run the matrix-core sub-face kernel for 1-3)
   int face_variant_count() const override { return DIVB == GLM ? 4 : 2; }
-  // GLM uniform grids: the LDS kernels (cell 0-3, face 0) exchange point
-  // fluxes, the matrix-core ones (cell 4-9, face 1-3) face moments
+  // GLM (uniform and octree grids): the LDS kernels (cell 0-3, face 0)
+  // exchange point fluxes, the matrix-core ones (cell 4-9, face 1-3) face
+  // moments
   bool layout_compatible(int cv, int fv, const Grid& g) const override {
-    if (DIVB != GLM || g.level) return true;
+    (void)g;
+    if (DIVB != GLM) return true;
     return (fv >= 1) == (cv >= 4);
   }
   void set_face_variant(int v) override { face_variant = v < 0 ? (DIVB == GLM ? 1 : 0) : v; }
