@@ -2164,6 +2164,140 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2,
   }
 }
 
+// Max signal speed on the matrix cores, Powell scheme (uniform grids): one
+// wave per 16 cells; the Legendre variables at every volume and face point
+// are products of the nodal and trace tables with the cell's modes, the
+// field's components products of the LDF tables (PV at volume points, the
+// LDF trace tables at face points) with its LDF weights; maxima as in
+// k_maxsig_mfma.  Persistent: where the tables fit, each workgroup stages
+// them in LDS once and its waves walk a contiguous, XCD-dealt range of
+// tiles; otherwise they are read through the L1.
+template <typename T, int D, int DEG>
+struct PowellSigLds {
+  static constexpr int SZ_V = MfmaShape<D, DEG>::SZ_V;
+  static constexpr int SZ_PV = PowellShape<D, DEG>::SZ_PV;
+  static constexpr int SZ_F = PowellFaceShape<D, DEG>::SZ;
+  static constexpr bool fits = (size_t)(SZ_V + SZ_PV + SZ_F) * sizeof(T) <= 128 * 1024;
+};
+
+template <typename T, int D, int DEG, int NW>
+__device__ __forceinline__ void maxsig_powell_walk(const T* __restrict__ w, const T* FV, const T* PVt, const T* PFT,
+                                                   const Grid& g, double gamma, double& smax, double& rmax) {
+  using C = Cfg<D, DEG, POWELL>;
+  using S = MfmaShape<D, DEG>;
+  using P = PowellShape<D, DEG>;
+  using F = PowellFaceShape<D, DEG>;
+  using M = Mfma<T>;
+  using v4 = typename M::v4;
+  constexpr int N = C::N, NL = C::NLEG, L = C::NLDF;
+  static_assert(S::NKS == F::NKS && P::NKL == F::NKL, "same k-steps for the volume and face tables");
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int kq = lane >> 4, cl = lane & 15;
+  const int64_t ntiles = (g.C + 15) / 16;
+  const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+  const int64_t t0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * per;
+  const int64_t t1 = t0 + per < ntiles ? t0 + per : ntiles;
+  for (int64_t tt = t0 + wid; tt < t1; tt += NW) {
+    const int64_t c0 = tt * 16;
+    const int64_t K = c0 + cl;
+    const bool live = K < g.C;
+    const int64_t Kc = live ? K : c0;
+    const double ih = 1.0 / cell_h(g, Kc);
+    T bw[NL][S::NKS], bl[P::NKL];
+#pragma unroll
+    for (int j = 0; j < NL; ++j)
+#pragma unroll
+      for (int s = 0; s < S::NKS; ++s) {
+        const int n = 4 * s + kq;
+        bw[j][s] = n < N ? w[(int64_t)(j * N + n) * g.ld + Kc] : T(0);
+      }
+#pragma unroll
+    for (int s = 0; s < P::NKL; ++s) {
+      const int i = 4 * s + kq;
+      bl[s] = i < L ? w[(int64_t)(NL * N + i) * g.ld + Kc] : T(0);
+    }
+#pragma unroll 1
+    for (int rt = 0; rt < S::QT + 2 * D; ++rt) {
+      const bool vol = rt < S::QT;
+      const int as = rt - S::QT;  // face (a, side) = as
+      v4 U[8];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) U[v] = v4{0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < S::NKS; ++s) {
+        const T a = vol ? FV[(rt * S::NKS + s) * 64 + lane] : PFT[(as * F::NKS + s) * 64 + lane];
+#pragma unroll
+        for (int j = 0; j < NL; ++j) U[C::legvar(j)] = M::mma(a, bw[j][s], U[C::legvar(j)]);
+      }
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+#pragma unroll
+        for (int s = 0; s < P::NKL; ++s) {
+          const T a = vol ? PVt[((c * S::QT + rt) * P::NKL + s) * 64 + lane]
+                          : PFT[F::SZL + ((as * D + c) * F::NKL + s) * 64 + lane];
+          U[5 + c] = M::mma(a, bl[s], U[5 + c]);
+        }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int i = M::row(kq, j);
+        const bool valid = live && (vol ? (16 * rt + i < C::Q) : (i < C::FP));
+        if (!valid) continue;
+        T u[9];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) u[v] = U[v][j];
+        u[8] = T(0);
+        double sp = signal_sum<T, D>(u, gamma);
+        if (!(sp == sp)) sp = __longlong_as_double(0x7ff8000000000000ULL);
+        smax = (sp > smax || !(sp == sp)) ? sp : smax;
+        const double rr = sp * ih;
+        rmax = (rr > rmax || !(rr == rr)) ? rr : rmax;
+      }
+    }
+  }
+}
+
+template <typename T, int D, int DEG, int NW>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2)))
+    k_maxsig_mfma_powell(const T* __restrict__ w, const T* __restrict__ FV, const T* __restrict__ PVt,
+                         const T* __restrict__ PFT, Grid g, Scal* sc, double gamma) {
+  using SL = PowellSigLds<T, D, DEG>;
+  __shared__ double red[NW], red2[NW];
+  double smax = 0.0, rmax = 0.0;
+  if constexpr (SL::fits) {
+    __shared__ T sT[SL::SZ_V + SL::SZ_PV + SL::SZ_F];
+    for (int i = threadIdx.x; i < SL::SZ_V; i += 64 * NW) sT[i] = FV[i];
+    for (int i = threadIdx.x; i < SL::SZ_PV; i += 64 * NW) sT[SL::SZ_V + i] = PVt[i];
+    for (int i = threadIdx.x; i < SL::SZ_F; i += 64 * NW) sT[SL::SZ_V + SL::SZ_PV + i] = PFT[i];
+    __syncthreads();
+    maxsig_powell_walk<T, D, DEG, NW>(w, sT, sT + SL::SZ_V, sT + SL::SZ_V + SL::SZ_PV, g, gamma, smax, rmax);
+  } else {
+    maxsig_powell_walk<T, D, DEG, NW>(w, FV, PVt, PFT, g, gamma, smax, rmax);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double x = __shfl_xor(smax, o);
+    smax = (x > smax || !(x == x)) ? x : smax;
+    const double y = __shfl_xor(rmax, o);
+    rmax = (y > rmax || !(y == y)) ? y : rmax;
+  }
+  if (lane == 0) {
+    red[wid] = smax;
+    red2[wid] = rmax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = red[0], r = red2[0];
+    for (int i = 1; i < NW; ++i) {
+      m = (red[i] > m || !(red[i] == red[i])) ? red[i] : m;
+      r = (red2[i] > r || !(red2[i] == red2[i])) ? red2[i] : r;
+    }
+    atomic_max_pos(&sc->maxsig_bits, m);
+    atomic_max_pos(&sc->maxrate_bits, r);
+    if (!(m == m)) atomicAdd(&sc->nonfinite, 1ULL);
+  }
+}
+
 // tile-shape variants of the cell kernel offered to the autotuner
 template <typename T, int D, int DEG, int DIVB>
 struct CellVariants {
@@ -2753,6 +2887,15 @@ struct LauncherImpl : Launcher {
       std::vector<double> pft;
       powell_face_tables<T, D, DEG>(t, pft);
       if ((e = up<T>(pft, mpft)) != hipSuccess) return e;
+      {  // resident workgroups of the persistent max-signal kernel
+        int dev = 0, ncu = 0, bm = 0;
+        if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+        if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bm, k_maxsig_mfma_powell<T, D, DEG, 8>, 512, 0)) !=
+            hipSuccess)
+          return e;
+        maxsig_blocks = bm * ncu;
+      }
     }
     if constexpr (DIVB == GLM) {
       // uniform grids: the matrix-core face kernels store face moments and
@@ -3068,6 +3211,15 @@ struct LauncherImpl : Launcher {
     }
   }
   void maxsig(const void* w, const Grid& g, Scal* sc, const SchemeParams& sp, hipStream_t s) override {
+    if constexpr (DIVB == POWELL) {
+      if (!g.level && face_variant >= 1 && maxsig_blocks > 0) {
+        constexpr int NW = 8;
+        const int64_t groups = ((g.C + 15) / 16 + NW - 1) / NW;
+        const unsigned grid = (unsigned)(groups < maxsig_blocks ? groups : maxsig_blocks);
+        k_maxsig_mfma_powell<T, D, DEG, NW><<<grid, 64 * NW, 0, s>>>((const T*)w, mfv, mpv, mpft, g, sc, sp.gamma);
+        return;
+      }
+    }
     if constexpr (DIVB == GLM) {
       if ((g.level || face_variant >= 1) && maxsig_blocks > 0) {
         constexpr int NW = 4;
