@@ -266,14 +266,16 @@ def test_schedule_pairs_face_flux_layouts():
     assert ((chosen >> 4) >= 1) == ((chosen & 15) >= 4), chosen
 
 
+@pytest.mark.parametrize("fv", [0, 1])
 @pytest.mark.parametrize("D,d,n", [(3, 2, 6), (2, 2, 12)])
-def test_powell_dt_cap_binds_matches_oracle(D, d, n):
+def test_powell_dt_cap_binds_matches_oracle(D, d, n, fv):
     """Powell time-step cap (eq. powell_dt with |div B|_K from the face jumps of
     eq. divb-cell) on a state with O(0.1) normal-field jumps at every face and
     a small eta, so that the cap and not eq. cfl sets the step: dg_dt and two
-    SSP-RK3 steps against the oracle."""
+    SSP-RK3 steps against the oracle, with the LDS-staged face kernel and
+    signal speeds (face variant 0) and with the matrix-core ones (1)."""
     from paper_1806_02343_amd import DG
-    _announce("powell cap", D, d, n)
+    _announce("powell cap", D, d, n, fv)
     eta = 1e-6
     orc = dg.DG(dg.Mesh.uniform(D, n), d, divb=dg.POWELL, powell_eta=eta)
     rng = np.random.default_rng(77)
@@ -283,6 +285,8 @@ def test_powell_dt_cap_binds_matches_oracle(D, d, n):
     wo[:, nl:] += 0.05 * rng.normal(size=(orc.mesh.ncells, orc.nldf))
     gpu = DG(D, d, n, divb=dg.POWELL, powell_eta=eta)
     wg = torch.as_tensor(orc.to_abi(wo, gpu.ld), device="cuda")
+    if fv:
+        gpu.autotune(wg, variant=8 + 16 * fv)
     dt_o, _, _ = orc.timestep(wo)
     dt_cfl = dg.DG(dg.Mesh.uniform(D, n), d, divb=dg.POWELL).timestep(wo)[0]
     assert dt_o < 0.2 * dt_cfl          # the cap binds by a wide margin
@@ -295,6 +299,32 @@ def test_powell_dt_cap_binds_matches_oracle(D, d, n):
     t_g = gpu.step(wg, 2)
     assert abs(t_g - t_o) <= 1e-12 * t_o
     err = rel_l1(orc, to_cells(wg, orc.mesh.ncells), wo)
+    assert np.all(err < 1e-12), err
+
+
+@pytest.mark.parametrize("case", [(3, 2, 6, dg.POWELL), (3, 1, 7, dg.POWELL), (3, 3, 5, dg.POWELL),
+                                  (2, 2, 12, dg.POWELL), (2, 3, 9, dg.POWELL)], ids=ids)
+@pytest.mark.parametrize("cv", [6, 8])
+def test_powell_matrix_core_schedule_steps_fp64(case, cv):
+    """The Powell scheme with the matrix-core face kernel (face variant 1),
+    whose time step evaluates the signal speeds on the matrix cores and takes
+    the cap from the jumps the first stage's face launch wrote, and the
+    persistent (6) or plain (8) matrix-core cell kernel: dg_dt and three
+    SSP-RK3 steps against the oracle at 1e-12."""
+    D, d, n, divb = case
+    _announce("powell mfma steps", case, cv)
+    gpu, wg, orc, wo = make_pair(D, d, n, divb)
+    gpu.autotune(wg, variant=cv + 16)
+    dt_g, _, _ = gpu.dt(wg)
+    dt_o, _, _ = orc.timestep(wo)
+    assert abs(dt_g - dt_o) <= 1e-12 * dt_o
+    t_o = 0.0
+    for _ in range(3):
+        wo, dt, ch, k = orc.step(wo)
+        t_o += dt
+    t_g = gpu.step(wg, 3)
+    assert abs(t_g - t_o) <= 1e-12 * t_o
+    err = rel_l1(orc, to_cells(wg, orc.mesh.ncells), wo, ch=max(ch, 1.0))
     assert np.all(err < 1e-12), err
 
 
