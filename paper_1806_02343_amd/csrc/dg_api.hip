@@ -415,9 +415,10 @@ int dg_nodal(dg_handle h, const void* w, int64_t cell0, int64_t ncell, double* o
 
 static int dt_sequence(dg_handle h, const void* w) {
   launch_reset_step(h->sc, h->stream);
-  h->L->maxsig(w, h->g, h->sc, h->sp, h->stream);
+  const DtFinalize fin{h->p.dim, h->p.degree, h->p.divb, h->hmin};
+  const bool done = h->L->maxsig(w, h->g, h->sc, h->sp, h->stream, &fin);
   if (h->p.divb == DG_POWELL) h->L->powell_cap(w, h->jsum, h->g, h->sc, h->sp, h->stream);
-  launch_finalize_dt(h->sc, h->sp, h->p.dim, h->p.degree, h->p.divb, h->hmin, h->stream);
+  if (!done) launch_finalize_dt(h->sc, h->sp, h->p.dim, h->p.degree, h->p.divb, h->hmin, h->stream);
   return check_launch(h, "time step");
 }
 
@@ -532,9 +533,14 @@ static void step_sequence(dg_handle h, void* w, bool first) {
   // Powell (normal-field jumps in jp): the first stage's face kernel runs
   // before the time step, whose cap then reads the jumps it wrote
   bool face_ready = false;
+  // where the reduction finalises the step itself it also leaves its maxima
+  // clear, so only the first step of a call resets them
+  const bool self_final = h->p.divb == DG_GLM && h->L->maxsig_finalizes(h->g);
+  bool finalized = false;
   if (first || !fused) {
-    launch_reset_step(h->sc, h->stream);
-    h->L->maxsig(w, h->g, h->sc, h->sp, h->stream);
+    if (first || !self_final) launch_reset_step(h->sc, h->stream);
+    const DtFinalize fin{h->p.dim, h->p.degree, h->p.divb, h->hmin};
+    finalized = h->L->maxsig(w, h->g, h->sc, h->sp, h->stream, &fin);
     if (h->p.divb == DG_POWELL) {
       if (!h->sp.powell_q && !h->g.level) {
         h->L->face(w, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
@@ -547,7 +553,7 @@ static void step_sequence(dg_handle h, void* w, bool first) {
   } else {
     launch_take_next(h->sc, h->stream);
   }
-  launch_finalize_dt(h->sc, h->sp, h->p.dim, h->p.degree, h->p.divb, h->hmin, h->stream);
+  if (!finalized) launch_finalize_dt(h->sc, h->sp, h->p.dim, h->p.degree, h->p.divb, h->hmin, h->stream);
   auto record = [&](void* u) {
     if (h->rec_X)
       (void)h->L->mlp_record(u, h->rec_X, h->rec_y, h->rec_counter, h->rec_cap, h->rec_qpos, h->rec_q, h->rec_seed,

@@ -26,6 +26,15 @@ struct Scal {
   // the next step's max signal and rate, folded into the last stage's
   // positivity limiter (bit patterns of non-negative doubles)
   unsigned long long next_maxsig_bits, next_maxrate_bits;
+  // workgroups of a time-step reduction that finalises the step itself
+  // (the last one computes dt, c_h and kappa); 0 between launches
+  unsigned int blocks_done;
+};
+
+// What the time-step finalisation needs besides the scheme parameters.
+struct DtFinalize {
+  int D, d, divb;
+  double hmin;
 };
 
 struct Grid {
@@ -87,8 +96,14 @@ struct Launcher {
   virtual int face_variant_count() const = 0;
   virtual void set_face_variant(int v) = 0;
   virtual int get_face_variant() const = 0;
-  // per-cell signal speeds -> atomic maxima in sc
-  virtual void maxsig(const void* w, const Grid& g, Scal* sc, const SchemeParams& sp, hipStream_t s) = 0;
+  // per-cell signal speeds -> atomic maxima in sc.  With fin, a launch that
+  // can also finalises the step (dt, c_h, kappa from the maxima, which it
+  // then clears) and returns true; the caller launches the finalisation
+  // otherwise.
+  virtual bool maxsig(const void* w, const Grid& g, Scal* sc, const SchemeParams& sp, hipStream_t s,
+                      const DtFinalize* fin = nullptr) = 0;
+  // maxsig(..., fin) finalises on g (so the maxima are clear after it)
+  virtual bool maxsig_finalizes(const Grid& g) const = 0;
   // Powell dt cap: per-face normal-field jumps then per-cell rate
   // Powell cap from the normal-field jumps the face kernel wrote for w
   virtual void powell_cap_jp(const void* w, const void* jp, void* jsum, const Grid& g, Scal* sc, hipStream_t s) = 0;

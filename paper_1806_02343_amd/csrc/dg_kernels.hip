@@ -2306,6 +2306,34 @@ struct CellVariants {
   static constexpr int nt(int i) { return i == 0 ? 256 : i == 1 ? 256 : i == 2 ? 512 : 512; }
 };
 
+// Time step, c_h and kappa from the reductions (eq. cfl, the GLM rules,
+// the Powell cap): s = max signal speed, rate = max speed over cell size,
+// pr = Powell rate.
+static __device__ __forceinline__ void finalize_dt_dev(Scal* sc, const SchemeParams& sp, int D, int d, int divb,
+                                                       double hmin, double s, double rate, double pr) {
+  double dt = sp.cfl / (2 * d + 1) / rate;
+  double ch = 0.0, kappa = 0.0;
+  if (!(s == s) || !(rate > 0.0)) sc->nonfinite += 1ULL;
+  if (divb == GLM) {
+    if (sp.glm_ch_fixed > 0.0) {
+      ch = sp.glm_ch_fixed;
+      const double cap = sp.cfl_glm * hmin / ((2 * d + 1) * D * ch);
+      dt = fmin(dt, cap);
+      if (ch < 2.0 * s / D) sc->n_ch_violation += 1ULL;
+    } else {
+      ch = (sp.cfl_glm / sp.cfl) * s / D;
+    }
+    kappa = fmin(ch / sp.glm_cr, 1.0 / (3.0 * dt));
+  } else {
+    if (pr > 0.0) dt = fmin(dt, sp.powell_eta / pr);
+  }
+  sc->dt = dt;
+  sc->ch = ch;
+  sc->kappa = kappa;
+  sc->t += dt;
+  sc->last_maxsig = s / D;
+}
+
 // ---------------------------------------------------------------------------
 // max signal speed over volume and face points (eq. cfl; reading: max over
 // the cell's quadrature points)
@@ -2331,7 +2359,7 @@ __device__ __forceinline__ void eval_point(const T* sw, int TC, int c, const T* 
 
 template <typename T, int D, int DEG, int DIVB>
 __global__ void __launch_bounds__(256) k_maxsig(const T* __restrict__ w, DevTab<T> tb, Grid g, Scal* sc,
-                                                double gamma) {
+                                                double gamma, SchemeParams sp, DtFinalize fin, int finalize) {
   using C = Cfg<D, DEG, DIVB>;
   constexpr int TC = Tile<T, D, DEG, DIVB>::TC;
   constexpr int NPT = C::Q + 2 * D * C::FP;
@@ -2382,6 +2410,22 @@ __global__ void __launch_bounds__(256) k_maxsig(const T* __restrict__ w, DevTab<
     atomic_max_pos(&sc->maxsig_bits, red[0]);
     atomic_max_pos(&sc->maxrate_bits, red2[0]);
     if (!(red[0] == red[0])) atomicAdd(&sc->nonfinite, 1ULL);
+    if (finalize) {
+      // the last workgroup to finish reads the maxima, finalises the step
+      // and clears them for the next reduction (two launches fewer per step
+      // where launches dominate: small grids)
+      __threadfence();
+      if (atomicAdd(&sc->blocks_done, 1u) == gridDim.x - 1) {
+        __threadfence();
+        const double s = __longlong_as_double((long long)atomicAdd(&sc->maxsig_bits, 0ULL));
+        const double rate = __longlong_as_double((long long)atomicAdd(&sc->maxrate_bits, 0ULL));
+        finalize_dt_dev(sc, sp, fin.D, fin.d, fin.divb, fin.hmin, s, rate, 0.0);
+        atomicExch(&sc->maxsig_bits, 0ULL);
+        atomicExch(&sc->maxrate_bits, 0ULL);
+        atomicExch(&sc->powell_rate_bits, 0ULL);
+        atomicExch(&sc->blocks_done, 0u);
+      }
+    }
   }
 }
 
@@ -2689,30 +2733,8 @@ __global__ void k_reset_step(Scal* sc) {
 }
 
 __global__ void k_finalize_dt(Scal* sc, SchemeParams sp, int D, int d, int divb, double hmin) {
-  const double s = __longlong_as_double(sc->maxsig_bits);
-  const double rate = __longlong_as_double(sc->maxrate_bits);
-  double dt = sp.cfl / (2 * d + 1) / rate;
-  double ch = 0.0, kappa = 0.0;
-  if (!(s == s) || !(rate > 0.0)) sc->nonfinite += 1ULL;
-  if (divb == GLM) {
-    if (sp.glm_ch_fixed > 0.0) {
-      ch = sp.glm_ch_fixed;
-      const double cap = sp.cfl_glm * hmin / ((2 * d + 1) * D * ch);
-      dt = fmin(dt, cap);
-      if (ch < 2.0 * s / D) sc->n_ch_violation += 1ULL;
-    } else {
-      ch = (sp.cfl_glm / sp.cfl) * s / D;
-    }
-    kappa = fmin(ch / sp.glm_cr, 1.0 / (3.0 * dt));
-  } else {
-    const double pr = __longlong_as_double(sc->powell_rate_bits);
-    if (pr > 0.0) dt = fmin(dt, sp.powell_eta / pr);
-  }
-  sc->dt = dt;
-  sc->ch = ch;
-  sc->kappa = kappa;
-  sc->t += dt;
-  sc->last_maxsig = s / D;
+  finalize_dt_dev(sc, sp, D, d, divb, hmin, __longlong_as_double(sc->maxsig_bits),
+                  __longlong_as_double(sc->maxrate_bits), __longlong_as_double(sc->powell_rate_bits));
 }
 
 __global__ void k_set_scalars(Scal* sc, double ch, double kappa, double dt) {
@@ -3210,14 +3232,19 @@ struct LauncherImpl : Launcher {
       default: launch_cell_v<3>(w, w0, out, ff, jp, g, sc, sp, a0, b0, cdt, mode, s); break;
     }
   }
-  void maxsig(const void* w, const Grid& g, Scal* sc, const SchemeParams& sp, hipStream_t s) override {
+  bool maxsig_finalizes(const Grid& g) const override {
+    if constexpr (DIVB == GLM) return !((g.level || face_variant >= 1) && maxsig_blocks > 0);
+    return false;
+  }
+  bool maxsig(const void* w, const Grid& g, Scal* sc, const SchemeParams& sp, hipStream_t s,
+              const DtFinalize* fin) override {
     if constexpr (DIVB == POWELL) {
       if (!g.level && face_variant >= 1 && maxsig_blocks > 0) {
         constexpr int NW = 8;
         const int64_t groups = ((g.C + 15) / 16 + NW - 1) / NW;
         const unsigned grid = (unsigned)(groups < maxsig_blocks ? groups : maxsig_blocks);
         k_maxsig_mfma_powell<T, D, DEG, NW><<<grid, 64 * NW, 0, s>>>((const T*)w, mfv, mpv, mpft, g, sc, sp.gamma);
-        return;
+        return false;
       }
     }
     if constexpr (DIVB == GLM) {
@@ -3226,11 +3253,14 @@ struct LauncherImpl : Launcher {
         const int64_t groups = ((g.C + 15) / 16 + NW - 1) / NW;
         const unsigned grid = (unsigned)(groups < maxsig_blocks ? groups : maxsig_blocks);
         k_maxsig_mfma<T, D, DEG, NW><<<grid, 64 * NW, 0, s>>>((const T*)w, mfv, mft, g, sc, sp.gamma);
-        return;
+        return false;
       }
     }
     const int nb = (int)((g.C + TL::TC - 1) / TL::TC);
-    k_maxsig<T, D, DEG, DIVB><<<nb, 256, 0, s>>>((const T*)w, tb, g, sc, sp.gamma);
+    const bool f = fin != nullptr && DIVB == GLM;
+    k_maxsig<T, D, DEG, DIVB><<<nb, 256, 0, s>>>((const T*)w, tb, g, sc, sp.gamma, sp, f ? *fin : DtFinalize{0, 0, 0, 0.0},
+                                                 f ? 1 : 0);
+    return f;
   }
   void powell_cap_jp(const void* w, const void* jp, void* jsum, const Grid& g, Scal* sc, hipStream_t s) override {
     if constexpr (DIVB == POWELL) {
