@@ -226,9 +226,10 @@ def main():
     ncells = r64["gpu"].ncells
     cv = r64["variant"] & 15
     mfma = cv >= 4
-    # the matrix-core GLM cell kernels (uniform and octree grids) lift face
-    # moments; the Powell kernels lift point fluxes
-    flops_launch = cell_flops(D, d, divb, moments=mfma and divb == 0) * ncells
+    # the matrix-core cell kernels lift face moments (GLM on uniform and
+    # octree grids, 3-D Powell with the cell-mean q-dagger); 2-D Powell lifts
+    # point values
+    flops_launch = cell_flops(D, d, divb, moments=mfma and (divb == 0 or D == 3)) * ncells
     achieved = flops_launch / (r64["k_cell"] / 1e3)
     if divb:
         kname = ("k_cell_mfma_powell_p" if cv == 6 else "k_cell_mfma_powell") if mfma else "k_cell"

@@ -562,7 +562,9 @@ static void step_sequence(dg_handle h, void* w, bool first) {
   // one Shu-Osher stage: out = a0 base + b0 (in + c0 dt L(in)), then the
   // limiters (the last stage of the step also folds the next step's signal)
   auto stage = [&](void* in, void* base, void* out, double a0, double b0, double c0, bool last) {
-    if (!(face_ready && in == w)) h->L->face(in, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
+    // the stages' face launches feed no Powell cap (the step's cap, if any,
+    // comes from the launch ahead of the time step)
+    if (!(face_ready && in == w)) h->L->face(in, h->ff, h->jp, h->g, h->sc, h->sp, h->stream, false);
     face_ready = false;
     h->L->cell(in, base, out, h->ff, h->jp, h->g, h->sc, h->sp, a0, b0, c0, 1, h->stream);
     record(out);
@@ -596,7 +598,7 @@ static void step_sequence(dg_handle h, void* w, bool first) {
       stage(h->S1, w, h->S2, a20, a21, b21 / a21, false);
       stage(h->S2, w, h->S1, a30, a32, b32 / a32, false);
       // u4 unlimited, then Q, then the limiters on u4
-      h->L->face(h->S1, h->ff, h->jp, h->g, h->sc, h->sp, h->stream);
+      h->L->face(h->S1, h->ff, h->jp, h->g, h->sc, h->sp, h->stream, false);
       h->L->cell(h->S1, w, h->S3, h->ff, h->jp, h->g, h->sc, h->sp, a40, a43, b43 / a43, 1, h->stream);
       {
         const double k = b53 / b43;

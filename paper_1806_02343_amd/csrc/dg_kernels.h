@@ -79,9 +79,12 @@ struct Launcher {
   virtual void free_tables() = 0;
   virtual size_t face_buffer_elems(const Grid& g) const = 0;
   virtual size_t jump_buffer_elems(const Grid& g, int powell_q) const = 0;
-  // face fluxes of state w into ff (and Powell jumps into jp)
+  // face fluxes of state w into ff (and Powell jumps into jp).  cap false:
+  // the caller does not take the Powell cap from this launch's jumps, so a
+  // face kernel that hands the cell kernels jump moments in ff may skip the
+  // jump points
   virtual void face(const void* w, void* ff, void* jp, const Grid& g, const Scal* sc, const SchemeParams& sp,
-                    hipStream_t s) = 0;
+                    hipStream_t s, bool cap = true) = 0;
   // mode 0: out = M^-1 R;  mode 1: out = a0 w0 + b0 (w + cdt dt M^-1 R)
   virtual void cell(const void* w, const void* w0, void* out, const void* ff, const void* jp, const Grid& g,
                     const Scal* sc, const SchemeParams& sp, double a0, double b0, double cdt, int mode,

@@ -1140,10 +1140,48 @@ struct PowellShape {
   static constexpr int NMTL = (C::NLDF + 15) / 16;   // 16-row tiles of the LDF result
   static constexpr int QT = (C::Q + 15) / 16;
   static constexpr int KS = (2 * D * C::FP + 3) / 4;
+  // 3-D with the cell-mean q-dagger: the faces carry flux and jump moments
+  static constexpr int KSM = (2 * D * C::FM + 3) / 4;
   static constexpr int SZ_PV = D * QT * NKL * 64;
   static constexpr int SZ_PG = D * D * NMTL * QT * 4 * 64;
   static constexpr int SZ_PL = D * NMTL * KS * 64;
+  static constexpr int SZ_PLM = D * NMTL * KSM * 64;
 };
+
+// LDF lift tables over face moments (3-D, cell-mean q-dagger): entries
+// sum_r PLF[a][side][c][r][i] Q[a][r][m] at K index (a * 2 + side) * FM + m,
+// negated on the -a side as the point tables.  The LDF components restricted
+// to a face are polynomials of degree <= DEG in the face coordinates, so the
+// lift rows lie in the span of Q (checked; false otherwise).
+template <typename T, int D, int DEG>
+bool powell_moment_lift(const Tables& t, const std::vector<double>& qb, std::vector<double>& plm) {
+  using C = Cfg<D, DEG, POWELL>;
+  using S = PowellShape<D, DEG>;
+  constexpr int FP = C::FP, FM = C::FM, L = C::NLDF;
+  plm.assign(S::SZ_PLM, 0.0);
+  for (int a = 0; a < D; ++a)
+    for (int side = 0; side < 2; ++side)
+      for (int c = 0; c < D; ++c) {
+        const double* rows = &t.PLF[(((size_t)a * 2 + side) * D + c) * FP * L];  // [r][i]
+        double scale = 0.0;
+        for (int i = 0; i < FP * L; ++i) scale = std::max(scale, std::fabs(rows[i]));
+        for (int i = 0; i < L; ++i) {
+          double lm[16] = {0.0};
+          for (int m = 0; m < FM; ++m)
+            for (int r = 0; r < FP; ++r) lm[m] += rows[(size_t)r * L + i] * qb[((size_t)a * FP + r) * FM + m];
+          for (int r = 0; r < FP; ++r) {
+            double pr = 0.0;
+            for (int m = 0; m < FM; ++m) pr += lm[m] * qb[((size_t)a * FP + r) * FM + m];
+            if (std::fabs(pr - rows[(size_t)r * L + i]) > 1e-13 * scale) return false;
+          }
+          for (int m = 0; m < FM; ++m) {
+            const int k = (a * 2 + side) * FM + m, s = k / 4, lq = k % 4, mt = i / 16;
+            plm[((c * S::NMTL + mt) * S::KSM + s) * 64 + lq * 16 + i % 16] = side ? -lm[m] : lm[m];
+          }
+        }
+      }
+  return true;
+}
 
 template <typename T, int D, int DEG>
 void powell_tables(const Tables& t, std::vector<double>& pv, std::vector<double>& pg, std::vector<double>& pl) {
@@ -1182,7 +1220,11 @@ void powell_tables(const Tables& t, std::vector<double>& pv, std::vector<double>
         }
 }
 
-template <typename T, int D, int DEG>
+// PM (3-D, cell-mean q-dagger): the faces carry moments (face kernel
+// variant 1): flux moments at rows a NV FP + v FM + m, the two sides' jump
+// moments at a NV FP + 8 FM + side FM + m, and FL / PLt are the lift tables
+// over moments.
+template <typename T, int D, int DEG, bool PM = false>
 __device__ __forceinline__ void cell_tile_mfma_powell(int64_t c0, int lane, const T* w, const T* w0, T* out,
                                                       const T* __restrict__ ff, const T* __restrict__ jp,
                                                       const T* FV, const T* FG, const T* FL, const T* PVt,
@@ -1236,24 +1278,33 @@ __device__ __forceinline__ void cell_tile_mfma_powell(int64_t c0, int lane, cons
   // face K-a (interpolated q-dagger: the face kernel added each side's
   // Powell term to its face values, the left side's in ff, the right side's
   // in jp, and the jump is not read).
+  constexpr int FK = PM ? C::FM : FP;                  // face values per face and variable
+  constexpr int KSX = PM ? P::KSM : S::KS;            // k-steps of the surface product
   auto load_face = [&](int s, T* fv) {
     const int k = 4 * s + kq;
-    const bool kv = k < 2 * D * FP;
-    const int a = kv ? k / (2 * FP) : 0, side = (k / FP) % 2, r = k % FP;
+    const bool kv = k < 2 * D * FK;
+    const int a = kv ? k / (2 * FK) : 0, side = (k / FK) % 2, r = k % FK;
     const int64_t Kf = side ? Kc : nbr(Kc, a, -1, g);
-    fv[NV] = (kv && !qint) ? jp[((int64_t)(a * 2 + (side ? 0 : 1)) * FP + r) * ld + Kf] : T(0);
-    const T* src = (qint && !side) ? jp : ff;
+    if constexpr (PM) {
+      const int64_t base = (int64_t)a * NV * FP;
+      fv[NV] = kv ? ff[(base + 8 * FK + (side ? 0 : 1) * FK + r) * ld + Kf] : T(0);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) fv[v] = kv ? src[((int64_t)(a * NV + v) * FP + r) * ld + Kf] : T(0);
+      for (int v = 0; v < NV; ++v) fv[v] = kv ? ff[(base + v * FK + r) * ld + Kf] : T(0);
+    } else {
+      fv[NV] = (kv && !qint) ? jp[((int64_t)(a * 2 + (side ? 0 : 1)) * FP + r) * ld + Kf] : T(0);
+      const T* src = (qint && !side) ? jp : ff;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) fv[v] = kv ? src[((int64_t)(a * NV + v) * FP + r) * ld + Kf] : T(0);
+    }
   };
   auto surface_step = [&](int s, const T* fv) {
-    const int side = ((4 * s + kq) / FP) % 2;
+    const int side = ((4 * s + kq) / FK) % 2;
     T bv[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) bv[v] = side ? fv[v] + qv[v] * fv[NV] : fv[v] - qv[v] * fv[NV];
 #pragma unroll
     for (int mt = 0; mt < S::NMT; ++mt) {
-      const T la = FL[(mt * S::KS + s) * 64 + lane];
+      const T la = FL[(mt * KSX + s) * 64 + lane];
 #pragma unroll
       for (int j = 0; j < NL; ++j) R[j][mt] = M::mma(la, bv[C::legvar(j)], R[j][mt]);
     }
@@ -1261,21 +1312,21 @@ __device__ __forceinline__ void cell_tile_mfma_powell(int64_t c0, int lane, cons
     for (int c = 0; c < D; ++c)
 #pragma unroll
       for (int mt = 0; mt < P::NMTL; ++mt)
-        RB[mt] = M::mma(PLt[((c * P::NMTL + mt) * S::KS + s) * 64 + lane], bv[5 + c], RB[mt]);
+        RB[mt] = M::mma(PLt[((c * P::NMTL + mt) * KSX + s) * 64 + lane], bv[5 + c], RB[mt]);
   };
   // 3-D degree 2: the loads of SB k-steps in flight together (the surface
   // phase holds few registers: the accumulators and q); elsewhere batching
   // measured no gain and raised the persistent kernel's spills
   constexpr int SB = (D == 3 && DEG == 2) ? 7 : 1;
 #pragma unroll 1
-  for (int s0 = 0; s0 < S::KS; s0 += SB) {
+  for (int s0 = 0; s0 < KSX; s0 += SB) {
     T fv[SB][NV + 1];
 #pragma unroll
     for (int b = 0; b < SB; ++b)
-      if (s0 + b < S::KS) load_face(s0 + b, fv[b]);
+      if (s0 + b < KSX) load_face(s0 + b, fv[b]);
 #pragma unroll
     for (int b = 0; b < SB; ++b)
-      if (s0 + b < S::KS) surface_step(s0 + b, fv[b]);
+      if (s0 + b < KSX) surface_step(s0 + b, fv[b]);
   }
   // the cell's modes as B operands, held for all row tiles
   T bw[NL][S::NKS], bl[P::NKL];
@@ -1396,7 +1447,7 @@ constexpr int powell_cell_waves_per_eu() {
   return (D == 3 && DEG >= 3) ? 1 : 2;
 }
 
-template <typename T, int D, int DEG, int NW>
+template <typename T, int D, int DEG, int NW, bool PM>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(powell_cell_waves_per_eu<T, D, DEG>())))
     k_cell_mfma_powell(const T* w, const T* w0, T* out, const T* __restrict__ ff, const T* __restrict__ jp,
                        const T* __restrict__ FV, const T* __restrict__ FG, const T* __restrict__ FL,
@@ -1405,38 +1456,41 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(po
                        double gamma, double a0, double b0, double cdt, int mode) {
   const int64_t c0 = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * NW + (threadIdx.x >> 6)) * 16;
   if (c0 >= g.C) return;  // whole wave; no barrier in this kernel
-  cell_tile_mfma_powell<T, D, DEG>(c0, threadIdx.x & 63, w, w0, out, ff, jp, FV, FG, FL, PVt, PGt, PLt, Pmean, Minv, g,
+  cell_tile_mfma_powell<T, D, DEG, PM>(c0, threadIdx.x & 63, w, w0, out, ff, jp, FV, FG, FL, PVt, PGt, PLt, Pmean, Minv, g,
                                    sc, gamma, a0, b0, cdt, mode);
 }
 
 // Persistent form: one workgroup per CU stages every fragment table in LDS
 // (157 KB at 3-D degree 2 FP64) and its waves walk a contiguous, XCD-dealt
 // range of 16-cell tiles.  Built where the tables fit the 160 KB of LDS.
-template <typename T, int D, int DEG>
+template <typename T, int D, int DEG, bool PM = false>
 struct PowellLds {
   using S = MfmaShape<D, DEG>;
   using P = PowellShape<D, DEG>;
-  static constexpr size_t bytes = (size_t)(S::SZ_V + S::SZ_G + S::SZ_L + P::SZ_PV + P::SZ_PG + P::SZ_PL) * sizeof(T);
+  static constexpr int SZ_L = PM ? S::SZ_LM : S::SZ_L;    // surface lift tables: moments or points
+  static constexpr int SZ_PL = PM ? P::SZ_PLM : P::SZ_PL;
+  static constexpr size_t bytes = (size_t)(S::SZ_V + S::SZ_G + SZ_L + P::SZ_PV + P::SZ_PG + SZ_PL) * sizeof(T);
   static constexpr bool fits = bytes <= 160 * 1024;
 };
 
-template <typename T, int D, int DEG, int NW>
+template <typename T, int D, int DEG, int NW, bool PM>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(powell_cell_waves_per_eu<T, D, DEG>())))
     k_cell_mfma_powell_p(const T* w, const T* w0, T* out, const T* __restrict__ ff, const T* __restrict__ jp,
                          const T* __restrict__ FV, const T* __restrict__ FG, const T* __restrict__ FL,
                          const T* __restrict__ PVt, const T* __restrict__ PGt, const T* __restrict__ PLt,
                          const T* __restrict__ Pmean, const T* __restrict__ Minv, Grid g, const Scal* __restrict__ sc,
                          double gamma, double a0, double b0, double cdt, int mode) {
-  if constexpr (PowellLds<T, D, DEG>::fits) {
+  using PL = PowellLds<T, D, DEG, PM>;
+  if constexpr (PL::fits) {
     using S = MfmaShape<D, DEG>;
     using P = PowellShape<D, DEG>;
-    __shared__ T sV[S::SZ_V], sG[S::SZ_G], sL[S::SZ_L], sPV[P::SZ_PV], sPG[P::SZ_PG], sPL[P::SZ_PL];
+    __shared__ T sV[S::SZ_V], sG[S::SZ_G], sL[PL::SZ_L], sPV[P::SZ_PV], sPG[P::SZ_PG], sPL[PL::SZ_PL];
     for (int i = threadIdx.x; i < S::SZ_V; i += 64 * NW) sV[i] = FV[i];
     for (int i = threadIdx.x; i < S::SZ_G; i += 64 * NW) sG[i] = FG[i];
-    for (int i = threadIdx.x; i < S::SZ_L; i += 64 * NW) sL[i] = FL[i];
+    for (int i = threadIdx.x; i < PL::SZ_L; i += 64 * NW) sL[i] = FL[i];
     for (int i = threadIdx.x; i < P::SZ_PV; i += 64 * NW) sPV[i] = PVt[i];
     for (int i = threadIdx.x; i < P::SZ_PG; i += 64 * NW) sPG[i] = PGt[i];
-    for (int i = threadIdx.x; i < P::SZ_PL; i += 64 * NW) sPL[i] = PLt[i];
+    for (int i = threadIdx.x; i < PL::SZ_PL; i += 64 * NW) sPL[i] = PLt[i];
     __syncthreads();
     const int64_t ntiles = (g.C + 15) / 16;
     const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
@@ -1451,7 +1505,7 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(po
       Grid gt = g;
       int ln = threadIdx.x & 63;
       if constexpr (sizeof(T) == 8) asm volatile("" : "+s"(pm), "+s"(mi), "+s"(gt.ld), "+v"(ln));
-      cell_tile_mfma_powell<T, D, DEG>(t * 16, ln, w, w0, out, ff, jp, sV, sG, sL, sPV, sPG, sPL, pm, mi, gt, sc, gamma,
+      cell_tile_mfma_powell<T, D, DEG, PM>(t * 16, ln, w, w0, out, ff, jp, sV, sG, sL, sPV, sPG, sPL, pm, mi, gt, sc, gamma,
                                        a0, b0, cdt, mode);
     }
   }
@@ -1860,14 +1914,22 @@ struct PowellFaceShape {
   static constexpr int NKL = (C::NLDF + 3) / 4;
   static constexpr int SZL = D * 2 * NKS * 64;          // Legendre traces [a][side][s][lane]
   static constexpr int SZ = SZL + D * 2 * D * NKL * 64;  // then the LDF traces [a][side][c][s][lane]
+  static constexpr int SZM = SZ + (D == 3 ? D * 4 * 64 : 0);  // then (3-D) the moment tables Q^T per axis
   static_assert(C::FP <= 16, "face points per face fit one 16-row tile");
 };
 
 template <typename T, int D, int DEG>
-void powell_face_tables(const Tables& t, std::vector<double>& ft) {
+void powell_face_tables(const Tables& t, const std::vector<double>& qb, std::vector<double>& ft) {
   using C = Cfg<D, DEG, POWELL>;
   using S = PowellFaceShape<D, DEG>;
-  ft.assign(S::SZ, 0.0);
+  ft.assign(S::SZM, 0.0);
+  if constexpr (D == 3)  // moment tables as in the GLM face kernel
+    for (int a = 0; a < D; ++a)
+      for (int s = 0; s < 4; ++s)
+        for (int l = 0; l < 64; ++l) {
+          const int m = l % 16, r = Mfma<T>::row(l / 16, s);
+          if (m < C::FM && r < C::FP) ft[S::SZ + (a * 4 + s) * 64 + l] = qb[((size_t)a * C::FP + r) * C::FM + m];
+        }
   for (int a = 0; a < D; ++a)
     for (int side = 0; side < 2; ++side) {
       for (int s = 0; s < S::NKS; ++s)
@@ -1889,7 +1951,7 @@ void powell_face_tables(const Tables& t, std::vector<double>& ft) {
 template <typename T, int D, int DEG, int NW, bool QINT>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(D == 3 && DEG >= 3 ? 1 : 2)))
     k_face_mfma_powell(const T* __restrict__ w, T* __restrict__ ff, T* __restrict__ jp, const T* __restrict__ FT,
-                       Grid g, const Scal* __restrict__ sc, double gamma) {
+                       Grid g, const Scal* __restrict__ sc, double gamma, int cap) {
   using C = Cfg<D, DEG, POWELL>;
   using S = PowellFaceShape<D, DEG>;
   using M = Mfma<T>;
@@ -1934,14 +1996,29 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(D 
   };
   traces(UL, FL, 1);
   traces(UR, FR, 0);
-  if (!live) return;
+  // 3-D with the cell-mean q-dagger: the point fluxes and the two sides'
+  // jumps wait in LDS (lane-private slots) for the moment product; every
+  // lane stays (the product's A operand is loaded by all lanes)
+  constexpr bool MOM = D == 3 && !QINT;
+  constexpr int NVM = MOM ? NV + 2 : 1;
+  __shared__ T sU[MOM ? NW : 1][NVM * 4 * 64];
+  T* const su = sU[MOM ? (threadIdx.x >> 6) : 0];
+  if (!MOM && !live) return;
   const T ch = (T)sc->ch;
   auto riemann = [&](auto axis) {
     constexpr int A = decltype(axis)::value;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int r = M::row(kq, j);
-      if (r >= FP) continue;
+      if constexpr (MOM) {
+        if (r >= FP) {
+#pragma unroll
+          for (int v = 0; v < NV + 2; ++v) su[(v * 4 + j) * 64 + lane] = T(0);
+          continue;
+        }
+      } else {
+        if (r >= FP) continue;
+      }
       T uL[9], uR[9], Fx[9];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -1963,16 +2040,49 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(D 
         }
       } else {
         const T bnF = face_flux_a<T, NV, A>(uL, uR, gamma, ch, Fx);
+        const T jl = bnF - uL[5 + A], jr = uR[5 + A] - bnF;
+        if (live && (cap || !MOM)) {  // the jump points feed the time step's Powell cap
+          jp[((int64_t)(A * 2 + 0) * FP + r) * ld + F] = jl;
+          jp[((int64_t)(A * 2 + 1) * FP + r) * ld + F] = jr;
+        }
+        if constexpr (MOM) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) ff[((int64_t)(A * NV + v) * FP + r) * ld + F] = Fx[v];
-        jp[((int64_t)(A * 2 + 0) * FP + r) * ld + F] = bnF - uL[5 + A];
-        jp[((int64_t)(A * 2 + 1) * FP + r) * ld + F] = uR[5 + A] - bnF;
+          for (int v = 0; v < NV; ++v) su[(v * 4 + j) * 64 + lane] = Fx[v];
+          su[(NV * 4 + j) * 64 + lane] = jl;
+          su[((NV + 1) * 4 + j) * 64 + lane] = jr;
+        } else {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) ff[((int64_t)(A * NV + v) * FP + r) * ld + F] = Fx[v];
+        }
       }
     }
   };
   if (a == 0) riemann(std::integral_constant<int, 0>{});
   else if (a == 1) riemann(std::integral_constant<int, 1>{});
   else if constexpr (D == 3) riemann(std::integral_constant<int, 2>{});
+  if constexpr (MOM) {
+    // moments Q^T of the fluxes (rows a NV FP + v FM + m) and of the jumps
+    // (rows a NV FP + 8 FM + side FM + m): 16x16x4 products with the point
+    // values as B operands as they lie in the accumulator rows
+    constexpr int FM = C::FM;
+    T mq[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) mq[s] = FT[S::SZ + (a * 4 + s) * 64 + lane];
+    const int64_t base = (int64_t)a * NV * FP;
+#pragma unroll 1
+    for (int v = 0; v < NV + 2; ++v) {
+      v4 acc = v4{0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc = M::mma(mq[s], su[(v * 4 + s) * 64 + lane], acc);
+      if (live) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int m = M::row(kq, e);
+          if (m < FM) ff[(base + v * FM + m) * ld + F] = acc[e];
+        }
+      }
+    }
+  }
 }
 
 // Low-register form of the matrix-core face kernel: the operands are loaded
@@ -2845,10 +2955,11 @@ struct LauncherImpl : Launcher {
   const T* mft = nullptr;                                   // and of the matrix-core face kernel
   const T* mfta = nullptr;                                  // and of its octree form (sub-face tables)
   const T* mlfa = nullptr;                                  // octree surface lift of the cell kernels
-  const T* mpft = nullptr;                                  // Powell face trace tables (matrix-core face kernel)
+  const T* mpft = nullptr;
+  const T *mflm = nullptr, *mplm = nullptr;  // Powell lift tables over face moments (3-D)                                  // Powell face trace tables (matrix-core face kernel)
   const double* mpos = nullptr;                             // and of the matrix-core positivity limiter
   int pos_variant = 1;                                      // 1: matrix-core positivity limiter where built
-  int face_variant = DIVB == GLM ? 1 : 0;                   // default: matrix-core face kernel for GLM
+  int face_variant = 1;                                     // default: the matrix-core face kernel
 
   template <typename U>
   hipError_t up(const std::vector<double>& src, const U*& dst) {
@@ -2888,7 +2999,7 @@ struct LauncherImpl : Launcher {
     if ((e = up<double>(t.RES, d1)) != hipSuccess) return e;
     res64 = (double*)d1;
     if constexpr (DIVB == POWELL) {
-      std::vector<double> fv, fg, fl, pv, pg, pl, gx, lx;
+      std::vector<double> fv, fg, fl, pv, pg, pl, gx, lx, qb;
       mfma_tables<T, D, DEG>(t, fv, fg, fl, gx, lx);
       powell_tables<T, D, DEG>(t, pv, pg, pl);
       if ((e = up<T>(fv, mfv)) != hipSuccess) return e;
@@ -2897,17 +3008,34 @@ struct LauncherImpl : Launcher {
       if ((e = up<T>(pv, mpv)) != hipSuccess) return e;
       if ((e = up<T>(pg, mpg)) != hipSuccess) return e;
       if ((e = up<T>(pl, mpl)) != hipSuccess) return e;
-      if constexpr (PowellLds<T, D, DEG>::fits) {
+      if constexpr (D == 3) {
+        // the cell-mean q-dagger's face moments (matrix-core face and cell kernels)
+        std::vector<double> flm, lxm, plm;
+        if (!face_moment_basis<D, DEG>(t, qb)) return hipErrorInvalidValue;
+        mfma_moment_lift<T, D, DEG>(t, qb, flm, lxm);
+        if (!powell_moment_lift<T, D, DEG>(t, qb, plm)) return hipErrorInvalidValue;
+        if ((e = up<T>(flm, mflm)) != hipSuccess) return e;
+        if ((e = up<T>(plm, mplm)) != hipSuccess) return e;
+      }
+      {
         int dev = 0, ncu = 0, bp = 0;
         if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
         if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bp, k_cell_mfma_powell_p<T, D, DEG, 8>, 512, 0)) !=
-            hipSuccess)
-          return e;
-        persist_powell = bp * ncu;
+        if constexpr (PowellLds<T, D, DEG, false>::fits) {
+          if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bp, k_cell_mfma_powell_p<T, D, DEG, 8, false>, 512,
+                                                                 0)) != hipSuccess)
+            return e;
+          persist_powell = bp * ncu;
+        }
+        if constexpr (D == 3 && PowellLds<T, D, DEG, true>::fits) {
+          if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bp, k_cell_mfma_powell_p<T, D, DEG, 8, true>, 512,
+                                                                 0)) != hipSuccess)
+            return e;
+          persist_powell_m = bp * ncu;
+        }
       }
       std::vector<double> pft;
-      powell_face_tables<T, D, DEG>(t, pft);
+      powell_face_tables<T, D, DEG>(t, qb, pft);
       if ((e = up<T>(pft, mpft)) != hipSuccess) return e;
       {  // resident workgroups of the persistent max-signal kernel
         int dev = 0, ncu = 0, bm = 0;
@@ -3014,7 +3142,7 @@ struct LauncherImpl : Launcher {
   int nmodes() const override { return C::NMODES; }
 
   void face(const void* w, void* ff, void* jp, const Grid& g, const Scal* sc, const SchemeParams& sp,
-            hipStream_t s) override {
+            hipStream_t s, bool cap) override {
     if (g.level) {
       if constexpr (DIVB == GLM) {
         if (face_variant >= 1 && mfta && g.nftile > 0) {
@@ -3057,10 +3185,10 @@ struct LauncherImpl : Launcher {
         const unsigned grid = (unsigned)((tiles * D + NW - 1) / NW);
         if (sp.powell_q)
           k_face_mfma_powell<T, D, DEG, NW, true><<<grid, 64 * NW, 0, s>>>((const T*)w, (T*)ff, (T*)jp, mpft, g, sc,
-                                                                           sp.gamma);
+                                                                           sp.gamma, 1);
         else
           k_face_mfma_powell<T, D, DEG, NW, false><<<grid, 64 * NW, 0, s>>>((const T*)w, (T*)ff, (T*)jp, mpft, g, sc,
-                                                                            sp.gamma);
+                                                                            sp.gamma, cap ? 1 : 0);
         return;
       }
     }
@@ -3077,6 +3205,7 @@ struct LauncherImpl : Launcher {
   static constexpr int NVAR = 10;
   int persist_blocks[2] = {0, 0};      // resident workgroups of the persistent kernels (4 and 2 waves)
   int persist_powell = 0;              // resident workgroups of the persistent Powell cell kernel (8 waves)
+  int persist_powell_m = 0;            // the same, face-moment form (3-D, cell-mean q-dagger)
   int persist_blocks_amr[2] = {0, 0};  // the same on octree grids
   int pos_blocks = 0, maxsig_blocks = 0;
   template <int NW>
@@ -3122,27 +3251,45 @@ struct LauncherImpl : Launcher {
                           hipStream_t s) {
     if constexpr (DIVB == POWELL) {
       if (g.level) return false;
+      // 3-D with the cell-mean q-dagger: the matrix-core face kernel stored
+      // face moments; the interpolated q-dagger and 2-D keep the face points
+      if constexpr (D == 3) {
+        if (!sp.powell_q) return launch_cell_powell_t<true>(nw, w, w0, out, ff, jp, g, sc, sp, a0, b0, cdt, mode, s);
+      }
+      return launch_cell_powell_t<false>(nw, w, w0, out, ff, jp, g, sc, sp, a0, b0, cdt, mode, s);
+    }
+    return false;
+  }
+  template <bool PM>
+  bool launch_cell_powell_t(int nw, const void* w, const void* w0, void* out, const void* ff, const void* jp,
+                            const Grid& g, const Scal* sc, const SchemeParams& sp, double a0, double b0, double cdt,
+                            int mode, hipStream_t s) {
+    if constexpr (DIVB == POWELL) {
+      const T* fl = PM ? mflm : mfl;
+      const T* pl = PM ? mplm : mpl;
+      const int pb = PM ? persist_powell_m : persist_powell;
       if (nw == 8) {  // persistent, tables in LDS
-        if constexpr (PowellLds<T, D, DEG>::fits) {
-          if (persist_powell <= 0) return false;
+        if constexpr (PowellLds<T, D, DEG, PM>::fits) {
+          if (pb <= 0) return false;
           const int64_t groups = ((g.C + 15) / 16 + 7) / 8;
-          const unsigned grid = (unsigned)(groups < persist_powell ? groups : persist_powell);
-          k_cell_mfma_powell_p<T, D, DEG, 8><<<grid, 512, 0, s>>>((const T*)w, (const T*)w0, (T*)out, (const T*)ff,
-                                                                  (const T*)jp, mfv, mfg, mfl, mpv, mpg, mpl, tb.Pmean,
-                                                                  tb.Minv, g, sc, sp.gamma, a0, b0, cdt, mode);
+          const unsigned grid = (unsigned)(groups < pb ? groups : pb);
+          k_cell_mfma_powell_p<T, D, DEG, 8, PM><<<grid, 512, 0, s>>>((const T*)w, (const T*)w0, (T*)out,
+                                                                      (const T*)ff, (const T*)jp, mfv, mfg, fl, mpv,
+                                                                      mpg, pl, tb.Pmean, tb.Minv, g, sc, sp.gamma, a0,
+                                                                      b0, cdt, mode);
           return true;
         }
         return false;
       }
       const unsigned grid = (unsigned)(((g.C + 15) / 16 + nw - 1) / nw);
       if (nw == 4)
-        k_cell_mfma_powell<T, D, DEG, 4><<<grid, 256, 0, s>>>((const T*)w, (const T*)w0, (T*)out, (const T*)ff,
-                                                              (const T*)jp, mfv, mfg, mfl, mpv, mpg, mpl, tb.Pmean,
-                                                              tb.Minv, g, sc, sp.gamma, a0, b0, cdt, mode);
+        k_cell_mfma_powell<T, D, DEG, 4, PM><<<grid, 256, 0, s>>>((const T*)w, (const T*)w0, (T*)out, (const T*)ff,
+                                                                  (const T*)jp, mfv, mfg, fl, mpv, mpg, pl, tb.Pmean,
+                                                                  tb.Minv, g, sc, sp.gamma, a0, b0, cdt, mode);
       else
-        k_cell_mfma_powell<T, D, DEG, 2><<<grid, 128, 0, s>>>((const T*)w, (const T*)w0, (T*)out, (const T*)ff,
-                                                              (const T*)jp, mfv, mfg, mfl, mpv, mpg, mpl, tb.Pmean,
-                                                              tb.Minv, g, sc, sp.gamma, a0, b0, cdt, mode);
+        k_cell_mfma_powell<T, D, DEG, 2, PM><<<grid, 128, 0, s>>>((const T*)w, (const T*)w0, (T*)out, (const T*)ff,
+                                                                  (const T*)jp, mfv, mfg, fl, mpv, mpg, pl, tb.Pmean,
+                                                                  tb.Minv, g, sc, sp.gamma, a0, b0, cdt, mode);
       return true;
     }
     return false;
@@ -3176,8 +3323,8 @@ struct LauncherImpl : Launcher {
       case 3: return CellTile<T, D, DEG, DIVB, CellVariants<T, D, DEG, DIVB>::tc(3), CellVariants<T, D, DEG, DIVB>::nt(3)>::valid;
       case 4:
       case 5:
+      case 7: return DIVB == GLM;  // the Powell scheme's matrix-core cell forms are 6, 8 and 9
       case 6:
-      case 7:
       case 8:
       case 9: return true;
       default: return false;
@@ -3188,15 +3335,16 @@ struct LauncherImpl : Launcher {
   // waves per block, 2 one wave per block, 3 low-register form at two waves
   // per SIMD (octree grids run the matrix-core sub-face kernel for 1-3)
   int face_variant_count() const override { return DIVB == GLM ? 4 : 2; }
-  // GLM (uniform and octree grids): the LDS kernels (cell 0-3, face 0)
-  // exchange point fluxes, the matrix-core ones (cell 4-9, face 1-3) face
-  // moments
+  // GLM (uniform and octree grids) and 3-D Powell: the LDS kernels (cell
+  // 0-3, face 0) exchange point fluxes, the matrix-core ones (cell 4-9, face
+  // 1-3) face moments (3-D Powell with the interpolated q-dagger: points in
+  // both, paired the same way)
   bool layout_compatible(int cv, int fv, const Grid& g) const override {
     (void)g;
-    if (DIVB != GLM) return true;
+    if (DIVB == POWELL && D == 2) return true;  // 2-D Powell: points throughout
     return (fv >= 1) == (cv >= 4);
   }
-  void set_face_variant(int v) override { face_variant = v < 0 ? (DIVB == GLM ? 1 : 0) : v; }
+  void set_face_variant(int v) override { face_variant = v < 0 ? 1 : v; }
   int get_face_variant() const override { return face_variant; }
   void set_cell_variant(int v) override { cell_variant = v; }
   int get_cell_variant() const override { return cell_variant; }
@@ -3218,6 +3366,9 @@ struct LauncherImpl : Launcher {
     if (v == 9 && launch_cell_mfma_p<2>(w, w0, out, ff, g, sc, sp, a0, b0, cdt, mode, s)) return;
     if ((v == 8 || v == 9) && launch_cell_powell(v == 8 ? 4 : 2, w, w0, out, ff, jp, g, sc, sp, a0, b0, cdt, mode, s)) return;
     if (v == 6 && launch_cell_powell(8, w, w0, out, ff, jp, g, sc, sp, a0, b0, cdt, mode, s)) return;
+    // Powell: a persistent form that cannot be resident runs the plain one
+    // (same face layout)
+    if (v == 6 && launch_cell_powell(4, w, w0, out, ff, jp, g, sc, sp, a0, b0, cdt, mode, s)) return;
     // GLM: a persistent form that cannot be resident runs the batched one
     // (same face-flux layout)
     if (v >= 8 && launch_cell_mfma<4, true>(w, w0, out, ff, g, sc, sp, a0, b0, cdt, mode, s)) return;
