@@ -17,7 +17,8 @@
 
 namespace dgmhd {
 
-typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef short s16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
@@ -30,9 +31,9 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 
 // C[i][n] = sum_k A(i,k) B(k,n) (+ beta C), A(i,k) = A[i*ari + k*ark],
 // B(k,n) = B[k*brk + n*brn] (BF16), C FP32 row-major.  One wavefront per
-// 16x16 output tile with v_mfma_f32_16x16x16bf16_1k: lane l supplies
-// A[l%16][4(l/16)+j], B[4(l/16)+j][l%16] (j = 0..3) and receives
-// C[4(l/16)+j][l%16].  M, N, K multiples of 16.
+// 16x16 output tile with gfx950's v_mfma_f32_16x16x32_bf16: lane l supplies
+// A[l%16][8(l/16)+e], B[8(l/16)+e][l%16] (e = 0..7; zero past K) and
+// receives C[4(l/16)+j][l%16] (j = 0..3).  M, N, K multiples of 16.
 __global__ void __launch_bounds__(256) k_gemm_bf16(const uint16_t* __restrict__ A, int64_t ari, int64_t ark,
                                                    const uint16_t* __restrict__ B, int64_t brk, int64_t brn,
                                                    float* __restrict__ C, int64_t ldc, int M, int N, int K,
@@ -42,16 +43,18 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(const uint16_t* __restrict__ 
   const int ntn = N / 16;
   const int tm = wave / ntn, tn = wave % ntn;
   if (tm >= M / 16) return;
-  const int i = tm * 16 + lane % 16, n = tn * 16 + lane % 16, kq = 4 * (lane / 16);
+  const int i = tm * 16 + lane % 16, n = tn * 16 + lane % 16, kq = 4 * (lane / 16), k8 = 8 * (lane / 16);
   f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    bf16x4_t a, b;
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    s16x8_t a, b;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      a[j] = (short)A[(int64_t)i * ari + (int64_t)(k0 + kq + j) * ark];
-      b[j] = (short)B[(int64_t)(k0 + kq + j) * brk + (int64_t)n * brn];
+    for (int e = 0; e < 8; ++e) {
+      const int k = k0 + k8 + e;
+      a[e] = k < K ? (short)A[(int64_t)i * ari + (int64_t)k * ark] : (short)0;
+      b[e] = k < K ? (short)B[(int64_t)k * brk + (int64_t)n * brn] : (short)0;
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b),
+                                                  acc, 0, 0, 0);
   }
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
