@@ -288,28 +288,31 @@ int dg_time_kernel(dg_handle h, const void* w, int32_t which, int32_t reps, doub
 
 /* Autotuner of the kernel schedule.  A schedule is cell variant + 16 x face
  * variant.  Cell variants: 0-3 LDS-tiled kernels (cells per block x threads
- * per block: 16x256, 32x256, 32x512, 64x512), 4-7 matrix-core kernel (4 or 2
- * waves of 16 cells per block, 6-7 with batched operand loads, 8-9 batched and
- * persistent with the tables in LDS; for the Powell scheme 8-9 are the
- * matrix-core kernel with the LDF basis, 4 or 2 waves per block; on octree
- * grids the GLM kernels gather sub-face fluxes; where a variant is not
- * built, variant 0 runs).  Face variants: 0 LDS-staged; 1-3 matrix-core (GLM;
- * also select the matrix-core max-signal-speed reduction of the time step):
- * 1 four waves per block, 2 one wave per block, 3 one wave per block with the
- * right traces in LDS and one face point solved at a time (two waves per
- * SIMD); on octree grids 1-3 run the matrix-core sub-face kernel.  On
- * uniform GLM grids the matrix-core face kernels hand the cell kernel face
- * moments (the projections of the face fluxes on the polynomials of degree
- * <= d in the face coordinates, the only part of a face flux the weak form
- * uses) and the LDS kernels face-point values, so a schedule pairs cell 0-3
- * with face 0 or cell 4-9 with face 1-3.  *variant >= 0 forces that schedule
- * (DG_EINVAL if it is not built for this configuration or pairs the two
- * layouts); *variant < 0 times every built cell variant and every face
+ * per block: 16x256, 32x256, 32x512, 64x512); GLM: 4-7 matrix-core kernel (4
+ * or 2 waves of 16 cells per block, 6-7 with batched operand loads), 8-9
+ * batched and persistent with the tables in LDS; Powell: 6 the persistent
+ * matrix-core kernel with the LDF basis (tables in LDS; the plain one where
+ * they do not fit), 8-9 the plain one with 4 or 2 waves per block (4, 5 and
+ * 7 are not built).  Face variants: 0 LDS-staged; 1-3 matrix-core (GLM; 1 for
+ * Powell; they also select the matrix-core max-signal-speed reduction of the
+ * time step): 1 four waves per block, 2 one wave per block, 3 one wave per
+ * block with the right traces in LDS and one face point solved at a time
+ * (two waves per SIMD); on octree grids 1-3 run the matrix-core sub-face
+ * kernel.  The matrix-core face kernels hand the cell kernels face moments
+ * (the projections of the face values on the polynomials of degree <= d in
+ * the face coordinates, the only part of a face flux the weak form uses) on
+ * GLM grids (uniform and octree) and for the 3-D Powell scheme with the
+ * cell-mean q-dagger; the LDS kernels hand over face-point values; so a
+ * schedule pairs cell 0-3 with face 0 or a matrix-core cell variant with a
+ * matrix-core face variant (2-D Powell: any pair).  *variant >= 0 forces that
+ * schedule (DG_EINVAL if it is not built for this configuration or pairs the
+ * two layouts); *variant < 0 times every built cell variant and every face
  * variant on the state w (read only; the handle's workspaces are written)
- * and keeps the fastest valid pair.  Before any call the schedule is
- * 6 + 16 (GLM) or 8 (Powell).  cache_path (may be NULL): a JSON
- * file of earlier choices keyed by precision, dimension, degree, divergence
- * scheme and cell count; an entry found there is used without timing and new
+ * and keeps the fastest valid pair.  Before any call the schedule is 6 + 16
+ * (GLM) or 8 + 16 (Powell).  cache_path (may be NULL): a JSON file of earlier
+ * choices keyed by precision, dimension, degree, divergence scheme, the
+ * Powell q-dagger form, cell count and, on octrees, the leaves per level and
+ * the face count; an entry found there is used without timing and new
  * choices are appended.  On return *variant holds the schedule in use.
  * Synchronous. */
 int dg_autotune(dg_handle h, const void* w, const char* cache_path, int32_t* variant /*[host] in/out*/);
