@@ -58,3 +58,95 @@ def block_rel_max(a, b, orc, floor=1e-3):
         sl = slice(len(orc.leg_vars) * n, None)
         res.append(np.abs(a[:, sl] - b[:, sl]).max() / max(np.abs(b[:, sl]).max(), floor * gmax))
     return np.array(res)
+
+
+class LeafIndex:
+    """Lookup of octree leaves (level, integer coordinates on the level grid
+    of n0 2^level cells per periodic axis) by sorted integer keys, for leaf
+    sets too large for a Python dictionary of tuples."""
+
+    def __init__(self, level, ijk, n0, D=3):
+        self.n0, self.D = n0, D
+        self.level = np.asarray(level, dtype=np.int64)
+        self.ijk = np.asarray(ijk, dtype=np.int64)[:, :D]
+        self.lmax = int(self.level.max()) if len(self.level) else 0
+        keys = self._keys(self.level, self.ijk)
+        self.order = np.argsort(keys, kind="stable")
+        self.sorted = keys[self.order]
+
+    def _keys(self, level, ijk):
+        m = self.n0 << self.lmax
+        k = level.astype(np.int64)
+        for a in range(self.D):
+            k = k * m + ijk[..., a]
+        return k
+
+    def find(self, level, c):
+        """Index of leaf (level, c) (c wrapped periodically), or -1."""
+        if level < 0 or level > self.lmax:
+            return -1
+        m = self.n0 << level
+        c = np.array([x % m for x in c], dtype=np.int64)
+        key = self._keys(np.int64(level), c[None, :])[0]
+        p = np.searchsorted(self.sorted, key)
+        return int(self.order[p]) if p < len(self.sorted) and self.sorted[p] == key else -1
+
+    def local_mesh(self, i):
+        """The leaf i, its face neighbours and every face touching leaf i, as
+        an oracle Mesh (leaf i is cell 0) in the oracle octree's face
+        conventions (a face listed from its left cell's +e_a side; a coarse
+        side on quarter q, bit t of q set for the upper half of the t-th
+        tangential axis), plus the global indices of the mesh's cells.  The
+        oracle's right-hand side of cell 0 on this mesh is that of leaf i on
+        the whole octree."""
+        D = self.D
+        l = int(self.level[i])
+        c = [int(x) for x in self.ijk[i]]
+        cells = [i]
+
+        def cid(j):
+            assert j >= 0, "mesh is not complete or not 2:1 balanced"
+            if j not in cells:
+                cells.append(j)
+            return cells.index(j)
+
+        faces = []
+        for a in range(D):
+            tang = [b for b in range(D) if b != a]
+            qc = sum(((c[b] & 1) << k) for k, b in enumerate(tang))
+            F = []
+            # +a side
+            nc = list(c)
+            nc[a] += 1
+            j = self.find(l, nc)
+            if j >= 0:
+                F.append((0, cid(j), -1, -1))
+            elif l > 0 and self.find(l - 1, [x // 2 for x in nc]) >= 0:
+                F.append((0, cid(self.find(l - 1, [x // 2 for x in nc])), -1, qc))
+            else:
+                for q in range(1 << (D - 1)):
+                    ch = [2 * x for x in nc]
+                    for k, b in enumerate(tang):
+                        ch[b] += (q >> k) & 1
+                    F.append((0, cid(self.find(l + 1, ch)), q, -1))
+            # -a side
+            nc = list(c)
+            nc[a] -= 1
+            j = self.find(l, nc)
+            if j >= 0:
+                F.append((cid(j), 0, -1, -1))
+            elif l > 0 and self.find(l - 1, [x // 2 for x in nc]) >= 0:
+                F.append((cid(self.find(l - 1, [x // 2 for x in nc])), 0, qc, -1))
+            else:
+                for q in range(1 << (D - 1)):
+                    ch = [2 * x for x in nc]
+                    ch[a] += 1
+                    for k, b in enumerate(tang):
+                        ch[b] += (q >> k) & 1
+                    F.append((cid(self.find(l + 1, ch)), 0, -1, q))
+            F = np.array(F, dtype=np.int64)
+            faces.append(dict(axis=a, L=F[:, 0], R=F[:, 1], subL=F[:, 2], subR=F[:, 3]))
+        lv = self.level[cells]
+        h = 1.0 / (self.n0 * (2.0 ** lv))
+        centers = (self.ijk[cells] + 0.5) * h[:, None]
+        return dg.Mesh(D, h, centers, faces), np.array(cells)

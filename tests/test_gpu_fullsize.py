@@ -206,6 +206,58 @@ def test_fullsize_conservation_octree_peaks():
     assert np.all(np.abs(after - before) <= 1e-12 * scale), (before, after)
 
 
+def test_fullsize_rhs_samples_octree_peaks():
+    """The octree workload (1,520,093 leaves, degree 2, GLM with fixed c_h),
+    right-hand side of sampled leaves against the oracle run on each leaf's
+    local mesh (the leaf, its face neighbours and the faces touching it):
+    leaves on both sides of hanging faces of each level, the origin's corner
+    leaf (periodic wrap) and the leaf of the largest energy change.  The
+    bar is 1e-13 of the cancelling terms' size (see below)."""
+    from parity_util import LeafIndex
+    _announce("fullsize octree rhs")
+    pk = wl.Peaks(3000)
+    lv, ijk = wl.peaks_leaves(pk)
+    gpu, w, stream = _gpu(3, 2, 64, field=pk, octree=(lv, ijk), ch=3.25)
+    C = len(lv)
+    with torch.cuda.stream(stream):
+        out = gpu.empty_state()
+        gpu.rhs(w, out, 3.25, 1.5)
+    torch.cuda.synchronize()
+    idx = LeafIndex(lv, ijk, 64)
+    rng = np.random.default_rng(11)
+    picks = [int(torch.argmax(out[4 * 10, :C].abs()).item()),
+             int(np.flatnonzero((ijk[:, :3] == 0).all(axis=1))[0])]
+    # a leaf of each level next to a finer (+1) or a coarser (-1) one
+    for l, side in ((0, 1), (1, 1), (1, -1), (2, -1)):
+        for i in rng.permutation(np.flatnonzero(lv == l))[:20000]:
+            m, cells = idx.local_mesh(int(i))
+            nl = idx.level[cells]
+            if (side > 0 and nl.max() > l) or (side < 0 and nl.min() < l):
+                picks.append(int(i))
+                break
+    assert len(picks) >= 6, picks
+    go, oo, vo = [], [], []
+    for i in picks:
+        m, cells = idx.local_mesh(i)
+        sub = w[:, torch.as_tensor(cells, device=w.device)].double().cpu().numpy().T.copy()
+        oo.append(dg.DG(m, 2, glm_ch_fixed=3.25).rhs(sub, 3.25, 1.5)[0])
+        # the volume term alone (no faces): the size of what the surface
+        # term cancels
+        vo.append(dg.DG(dg.Mesh(3, m.h, m.centers, []), 2, glm_ch_fixed=3.25).rhs(sub, 3.25, 1.5)[0])
+        go.append(out[:, i].double().cpu().numpy())
+    go, oo, vo = np.array(go), np.array(oo), np.array(vo)
+    # On this smooth field the right-hand side is the small difference of the
+    # volume and surface terms (10^2-10^4 times smaller at h down to 1/256;
+    # zero up to rounding for B and psi, the field being uniform), so the
+    # rounding of either side scales with those terms: each variable block
+    # is judged against its volume term's largest value.
+    for b in range(9):
+        sl = slice(10 * b, 10 * (b + 1))
+        err, terms = np.abs(go[:, sl] - oo[:, sl]).max(), np.abs(vo[:, sl]).max()
+        print("block", b, "err", err, "max|rhs|", np.abs(oo[:, sl]).max(), "max|volume|", terms, flush=True)
+        assert err <= 1e-13 * terms, (b, err, terms)
+
+
 @pytest.mark.parametrize("limiter,steps", [(7, 20), (4, 50)])
 def test_fullsize_fp32_within_tolerance_blast128(limiter, steps):
     """FP32 against FP64 on the full 128^3 degree-3 blast by the nodal

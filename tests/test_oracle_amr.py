@@ -119,3 +119,39 @@ def test_advected_peaks_entropy_wave_converges_with_degree():
         ex = pk(x.reshape(-1, 3), t=tt)["rho"].reshape(m.ncells, -1)
         errs.append((np.abs(U[0] - ex) * wq * (m.h ** 3)[:, None] / 8).sum())
     assert errs[1] < 0.7 * errs[0], errs
+
+
+def test_local_mesh_gives_the_whole_octree_rhs():
+    """The full-size octree parity samples leaves and runs the oracle on each
+    leaf's local mesh (the leaf, its face neighbours and the faces touching
+    it).  On the peaks recipe's octree over an 8^3 base grid that local
+    right-hand side equals the whole mesh's for leaves on every kind of face
+    (same level, coarse and fine sides of hanging faces, periodic wrap)."""
+    from parity_util import LeafIndex
+    pk = wl.Peaks(3000, npk=3, width=0.08)
+    lv, ijk = wl.peaks_leaves(pk, n0=8, r1=0.25, r2=0.15)
+    t = Octree.from_arrays(3, 8, lv, ijk)
+    orc = dg.DG(t.mesh(), 1, glm_ch_fixed=3.5)
+    wo = orc.project(dg.conserved_field(pk, G, 9))
+    R = orc.rhs(wo, 3.5, 1.5)
+    idx = LeafIndex(lv, ijk, 8)
+    rng = np.random.default_rng(5)
+    picks = set(rng.choice(len(lv), 12, replace=False).tolist())
+    for l in (0, 1, 2):  # leaves next to a level change, of each level
+        cand = np.flatnonzero(lv == l)
+        for i in rng.permutation(cand):
+            m, cells = idx.local_mesh(int(i))
+            if len(np.unique(idx.level[cells])) > 1:
+                picks.add(int(i))
+                break
+    picks.add(int(np.flatnonzero((ijk[:, :3] == 0).all(axis=1))[0]))  # the origin's corner leaf
+    kinds = set()
+    for i in sorted(picks):
+        m, cells = idx.local_mesh(i)
+        for f in m.faces:
+            kinds |= {("coarse left" if s >= 0 else "full") for s in f["subL"]}
+            kinds |= {("coarse right" if s >= 0 else "full") for s in f["subR"]}
+        loc = dg.DG(m, 1, glm_ch_fixed=3.5).rhs(wo[cells], 3.5, 1.5)[0]
+        scale = np.abs(R[i]).max()
+        assert np.abs(loc - R[i]).max() <= 1e-13 * scale, (i, np.abs(loc - R[i]).max(), scale)
+    assert kinds == {"full", "coarse left", "coarse right"}
