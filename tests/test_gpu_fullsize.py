@@ -186,6 +186,38 @@ def test_fullsize_rhs_samples_powell64():
                  np.concatenate([o[:, :50], np.pad(o[:, 50:], ((0, 0), (0, 4)))], 1), 2e-11, nblocks=8)
 
 
+def test_fullsize_step_samples_powell64():
+    """One SSP-RK3 step of the full 64^3 degree-2 Powell/LDF workload (graph
+    replay on the benchmark's stream, the step's dt from the whole grid:
+    CFL and the Powell cap), sampled cells against the oracle stepped on their
+    7^3 dependency box (one face layer per stage).  The states meet 1e-12:
+    the right-hand side's cancellation (see the test above) enters them
+    multiplied by dt ~ 1e-3."""
+    _announce("fullsize powell step")
+    n = 64
+    gpu, w, stream = _gpu(3, 2, n, divb=dg.POWELL, field=wl.config_field(1))
+    w0 = w.clone()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        dt_g, _, _ = gpu.dt(w)
+        t = gpu.step(w, 1, t=0.0)
+    torch.cuda.synchronize()
+    assert abs(t - dt_g) <= 1e-14 * dt_g
+    go, oo = [], []
+    for c in [(0, 0, 0), (63, 17, 40), (20, 63, 5), (33, 2, 61)]:
+        sub, ns = _sub_box(w0, n, c, 3)
+        orc = dg.DG(dg.Mesh.uniform(3, ns, ns / n), 2, divb=dg.POWELL, cfl=0.3)
+        u1 = sub + dt_g * orc.rhs(sub)
+        u2 = 0.75 * sub + 0.25 * (u1 + dt_g * orc.rhs(u1))
+        u3 = sub / 3.0 + 2.0 / 3.0 * (u2 + dt_g * orc.rhs(u2))
+        go.append(w[:, c[0] + n * (c[1] + n * c[2])].double().cpu().numpy())
+        oo.append(u3[_center_index(ns)])
+    g = np.asarray(go)
+    o = np.asarray(oo)
+    _check_close(np.concatenate([g[:, :50], np.pad(g[:, 50:], ((0, 0), (0, 4)))], 1),
+                 np.concatenate([o[:, :50], np.pad(o[:, 50:], ((0, 0), (0, 4)))], 1), 1e-12, nblocks=8)
+
+
 def test_fullsize_conservation_octree_peaks():
     """The octree workload (base 64^3, two levels around 16 peaks, 1,520,093
     leaves, degree 2, GLM with fixed c_h): three steps conserve mass, momentum
