@@ -150,3 +150,35 @@ class LeafIndex:
         h = 1.0 / (self.n0 * (2.0 ** lv))
         centers = (self.ijk[cells] + 0.5) * h[:, None]
         return dg.Mesh(D, h, centers, faces), np.array(cells)
+
+    def region_mesh(self, i, layers):
+        """Oracle mesh of the leaves within `layers` face layers of leaf i, with
+        every face touching the inner layers (leaf i is cell 0), and the global
+        leaf indices of its cells.  The scheme's value at leaf i after `layers`
+        stages is exact on it: a stage needs one face layer."""
+        shells = [[i]]
+        seen = {i}
+        for _ in range(layers):
+            nxt = []
+            for x in shells[-1]:
+                _, cells = self.local_mesh(x)
+                for y in cells.tolist():
+                    if y not in seen:
+                        seen.add(y)
+                        nxt.append(y)
+            shells.append(nxt)
+        order = [x for sh in shells for x in sh]
+        pos = {x: k for k, x in enumerate(order)}
+        faces = [set() for _ in range(self.D)]
+        for x in [x for sh in shells[:-1] for x in sh]:
+            m, cells = self.local_mesh(x)
+            for f in m.faces:
+                for L, R, sL, sR in zip(f["L"], f["R"], f["subL"], f["subR"]):
+                    faces[f["axis"]].add((pos[int(cells[L])], pos[int(cells[R])], int(sL), int(sR)))
+        fl = []
+        for a in range(self.D):
+            F = np.array(sorted(faces[a]), dtype=np.int64)
+            fl.append(dict(axis=a, L=F[:, 0], R=F[:, 1], subL=F[:, 2], subR=F[:, 3]))
+        lv = self.level[order]
+        h = 1.0 / (self.n0 * (2.0 ** lv))
+        return dg.Mesh(self.D, h, (self.ijk[order] + 0.5) * h[:, None], fl), np.array(order)

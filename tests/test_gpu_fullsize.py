@@ -290,6 +290,49 @@ def test_fullsize_rhs_samples_octree_peaks():
         assert err <= 1e-13 * terms, (b, err, terms)
 
 
+def test_fullsize_step_samples_octree_peaks():
+    """One SSP-RK3 step of the full octree workload (1,520,093 leaves, graph
+    replay on the benchmark's stream, the whole grid's dt and kappa), sampled
+    leaves next to hanging faces against the oracle stepped on their three
+    face layers.  The states meet 1e-12 block-relative: the right-hand
+    side's cancellation (see the right-hand-side test) enters them
+    multiplied by dt."""
+    from parity_util import LeafIndex
+    _announce("fullsize octree step")
+    pk = wl.Peaks(3000)
+    lv, ijk = wl.peaks_leaves(pk)
+    gpu, w, stream = _gpu(3, 2, 64, field=pk, octree=(lv, ijk), ch=3.25)
+    w0 = w.clone()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        dt_g, ch, kappa = gpu.dt(w)
+        t = gpu.step(w, 1, t=0.0)
+    torch.cuda.synchronize()
+    assert abs(t - dt_g) <= 1e-14 * dt_g
+    idx = LeafIndex(lv, ijk, 64)
+    rng = np.random.default_rng(12)
+    picks = [int(np.flatnonzero((ijk[:, :3] == 0).all(axis=1))[0])]
+    for l, side in ((0, 1), (1, 1), (2, -1)):
+        for i in rng.permutation(np.flatnonzero(lv == l))[:20000]:
+            m, cells = idx.local_mesh(int(i))
+            nl = idx.level[cells]
+            if (side > 0 and nl.max() > l) or (side < 0 and nl.min() < l):
+                picks.append(int(i))
+                break
+    assert len(picks) == 4, picks
+    go, oo = [], []
+    for i in picks:
+        m, cells = idx.region_mesh(i, 3)
+        sub = w0[:, torch.as_tensor(cells, device=w0.device)].double().cpu().numpy().T.copy()
+        orc = dg.DG(m, 2, glm_ch_fixed=3.25)
+        u1 = sub + dt_g * orc.rhs(sub, ch, kappa)
+        u2 = 0.75 * sub + 0.25 * (u1 + dt_g * orc.rhs(u1, ch, kappa))
+        u3 = sub / 3.0 + 2.0 / 3.0 * (u2 + dt_g * orc.rhs(u2, ch, kappa))
+        go.append(w[:, i].double().cpu().numpy())
+        oo.append(u3[0])
+    _check_close(go, oo, 1e-12)
+
+
 @pytest.mark.parametrize("limiter,steps", [(7, 20), (4, 50)])
 def test_fullsize_fp32_within_tolerance_blast128(limiter, steps):
     """FP32 against FP64 on the full 128^3 degree-3 blast by the nodal

@@ -155,3 +155,32 @@ def test_local_mesh_gives_the_whole_octree_rhs():
         scale = np.abs(R[i]).max()
         assert np.abs(loc - R[i]).max() <= 1e-13 * scale, (i, np.abs(loc - R[i]).max(), scale)
     assert kinds == {"full", "coarse left", "coarse right"}
+
+
+def test_region_mesh_gives_the_whole_octree_step():
+    """The full-size octree step parity runs the oracle on the leaves within
+    three face layers of a sampled leaf (every face touching the inner two
+    layers).  On the peaks recipe's small octree one SSP-RK3 step on that
+    region equals the whole mesh's step at the leaf; two layers do not."""
+    from parity_util import LeafIndex
+    pk = wl.Peaks(3000, npk=3, width=0.08)
+    lv, ijk = wl.peaks_leaves(pk, n0=8, r1=0.25, r2=0.15)
+    orc = dg.DG(Octree.from_arrays(3, 8, lv, ijk).mesh(), 1, glm_ch_fixed=3.5)
+    wo = orc.project(dg.conserved_field(pk, G, 9))
+
+    def step(o, w, dt=1e-3, ch=3.5, kappa=1.5):
+        u1 = w + dt * o.rhs(w, ch, kappa)
+        u2 = 0.75 * w + 0.25 * (u1 + dt * o.rhs(u1, ch, kappa))
+        return w / 3.0 + 2.0 / 3.0 * (u2 + dt * o.rhs(u2, ch, kappa))
+
+    full = step(orc, wo)
+    idx = LeafIndex(lv, ijk, 8)
+    rng = np.random.default_rng(3)
+    short = 0.0
+    for i in rng.choice(len(lv), 8, replace=False):
+        scale = np.abs(full[i]).max()
+        m, cells = idx.region_mesh(int(i), 3)
+        assert np.abs(step(dg.DG(m, 1, glm_ch_fixed=3.5), wo[cells])[0] - full[i]).max() <= 1e-14 * scale
+        m, cells = idx.region_mesh(int(i), 2)
+        short = max(short, np.abs(step(dg.DG(m, 1, glm_ch_fixed=3.5), wo[cells])[0] - full[i]).max() / scale)
+    assert short > 1e-6
